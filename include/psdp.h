@@ -1,0 +1,201 @@
+/*
+ * psdp.h -- warm-started approximate projection onto the PSD cone, MI355X.
+ *
+ * The library computes Pi(X) = argmin_{Y psd} ||X - Y||_F for a dense
+ * symmetric n x n matrix X (paper §1, definition of the projection and
+ * eq. `projection`) with a warm-started block eigensolver of the LOBPCG
+ * family (paper §5.1, Alg. 3) applied to whichever spectral side is smaller
+ * (§5.1, "When is projecting with LOBPCG most efficient"; §6 side rule), and
+ * returns the gap-free a-posteriori error bound of §5.2 (Thm `bound`):
+ *
+ *     ||Vt Lt Vt^T - Pi(A)||_F^2 <= 2 ||R||_F^2 + ||Pi(Vt_perp^T A Vt_perp)||_F^2
+ *
+ * where (Vt, Lt) are the positive Ritz pairs with Lt = Vt^T A Vt and
+ * R = A Vt - Vt Lt.  The last term is reported as an estimate (tail_est,
+ * certified = 0); §5.2 and §6 treat it the same way.
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major (Fortran order) with a leading dimension;
+ *   - pointers named X, V, lambda, Pi are DEVICE pointers (HIP, on the
+ *     handle's device) unless stated otherwise; options/info are HOST;
+ *   - X is read-only and only its LOWER triangle is read (LAPACK uplo='L');
+ *   - work is enqueued on the handle's stream; psdp_project and
+ *     psdp_full_eig_project synchronise that stream before returning because
+ *     they fill the host info struct;
+ *   - no entry point aborts: each returns a psdp_status; arguments are
+ *     validated on the host before any launch;
+ *   - the caller owns X, V, lambda and Pi; the handle owns its workspace;
+ *   - a handle is not thread safe: use one handle per host thread.
+ */
+#ifndef PSDP_H
+#define PSDP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct psdp_handle_s *psdp_handle;
+
+typedef enum {
+    PSDP_OK = 0,                 /* converged to tol; Pi, V, lambda valid        */
+    PSDP_NOT_CONVERGED = 1,      /* max_iter reached; Pi valid with its (larger)  */
+                                 /* bound in info->err_bound                      */
+    PSDP_FELL_BACK_FULL_EIG = 2, /* exact full eigendecomposition was used       */
+    PSDP_ERR_INVALID_ARG = -1,   /* bad size, pointer, stride or option          */
+    PSDP_ERR_HIP = -2,           /* a HIP/ROCm call failed (e.g. no device)      */
+    PSDP_ERR_OUT_OF_MEMORY = -3, /* workspace allocation failed                  */
+    PSDP_ERR_NUMERICAL = -4,     /* non-finite input or breakdown not recovered  */
+    PSDP_ERR_CAPACITY = -5       /* block would exceed m_cap and no fallback     */
+} psdp_status;
+
+typedef enum {
+    PSDP_SIDE_AUTO = 0, /* paper §6: positive side if the estimated count of    */
+                        /* positive eigenvalues is < side_threshold*n, negative */
+                        /* side if the negative count is, else full eig; with   */
+                        /* no estimate (pos_hint < 0) the full eig is used      */
+    PSDP_SIDE_POS = 1,  /* approximate the positive pairs of X (eq. projection, */
+                        /* middle)                                              */
+    PSDP_SIDE_NEG = 2,  /* approximate the positive pairs of -X and use the     */
+                        /* Moreau identity Pi(X) = X + Pi(-X) (eq. projection,  */
+                        /* right)                                               */
+    PSDP_SIDE_FULL = 3  /* exact full eigendecomposition                        */
+} psdp_side;
+
+typedef enum {
+    PSDP_PREC_FP64 = 0, /* block products in FP64 (MFMA f64)                    */
+    PSDP_PREC_FP32 = 1, /* block products in FP32 (MFMA f32), FP64 elsewhere     */
+    PSDP_PREC_BF16 = 2  /* block products BF16 x BF16 -> FP32 (MFMA), FP64      */
+                        /* elsewhere                                            */
+} psdp_prec;
+
+typedef struct {
+    int side;               /* psdp_side                                          */
+    int prec;               /* psdp_prec of the block products                    */
+    double tol;             /* absolute 2-norm tolerance on each positive Ritz    */
+                            /* residual (paper §5.2/§6 stopping rule); <= 0 picks */
+                            /* 1e-8 * ||X||_F / sqrt(2 m)                          */
+    int max_iter;           /* LOBPCG iteration cap (all phases together)         */
+    int refine_fp64;        /* low-precision runs: finish with the FP64 residual- */
+                            /* correction sweep (default 1)                       */
+    int ladder;             /* on a stalled low-precision residual move BF16 ->   */
+                            /* FP32 -> FP64 products (default 1); 0 = raw path    */
+    int certify;            /* reserved, must be 0                                */
+    unsigned long long seed;/* counter-based RNG seed (cold start, expansion)     */
+    double side_threshold;  /* AUTO side rule threshold, default 1/3 (paper §6)   */
+    int expand_cols;        /* columns added per expansion, 0 = ceil(n/50)        */
+                            /* (paper §5.1 expansion rule)                        */
+    int pos_hint;           /* estimated count of positive eigenvalues for AUTO,  */
+                            /* e.g. the previous call's info.n_pos; -1 = none     */
+    int fallback_full;      /* 1: when LOBPCG is not converged at max_iter or the */
+                            /* block outgrows m_cap, use the full eig instead     */
+    int block_guard;        /* cold start block = hint + max(block_guard,         */
+                            /* ceil(0.2 hint)); default 4                         */
+} psdp_options;
+
+typedef struct {
+    double err_bound;   /* sqrt(2 ||R||_F^2 + tail_est^2), absolute Frobenius     */
+    double res_fro;     /* ||R||_F of the final positive Ritz pairs (FP64)        */
+    double tail_est;    /* estimate of ||Pi(Vt_perp^T A Vt_perp)||_F (uncertified) */
+    double pi_fro;      /* ||Pi||_F of the returned projection (host estimate     */
+                        /* sqrt(sum lt^2) for the positive side)                  */
+    double theta_guard; /* largest non-positive Ritz value kept in the block      */
+    double tol_used;    /* tolerance actually applied                            */
+    int n_pos;          /* positive Ritz pairs of the approximated side (m~)     */
+    int m_out;          /* columns returned in V                                  */
+    int iters;          /* LOBPCG iterations (all phases)                         */
+    int side_used;      /* PSDP_SIDE_POS, _NEG or _FULL                           */
+    int certified;      /* 1 if the tail term is proven zero (not implemented: 0) */
+    int status;         /* same as the return value                               */
+    int expansions;     /* block expansions performed                             */
+    int prec_final;     /* product precision in the last LOBPCG phase             */
+    int n_pos_full;     /* eigenvalue count of X above 0 (full eig path) or -1    */
+} psdp_info;
+
+/* Fill *opt with the defaults documented above. */
+void psdp_default_options(psdp_options *opt);
+
+/* Create a handle on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Returns PSDP_ERR_HIP when the
+ * device is absent.  Allocates nothing until the first call needs it. */
+psdp_status psdp_create(psdp_handle *h, int device, void *hip_stream);
+
+/* Release the handle and all of its device memory. */
+psdp_status psdp_destroy(psdp_handle h);
+
+/* Change the stream later calls enqueue on. */
+psdp_status psdp_set_stream(psdp_handle h, void *hip_stream);
+
+/* Device workspace bytes a psdp_project call of order n with block capacity
+ * m_cap and product precision prec needs (host-only computation). */
+psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t *bytes);
+
+/* Project one matrix (paper §5.1 Alg. 3 + §5.2 Thm `bound`).
+ *   n        order of X (n >= 1)
+ *   X, ldx   symmetric input, lower triangle read, ldx >= n (device)
+ *   V, ldv   n x m_cap block (device).  On entry its first *m_inout columns
+ *            are the warm start (the previous call's Ritz block; 0 = cold
+ *            start from seeded N(0,1) columns).  On exit it holds the m_out
+ *            Ritz vectors of the approximated side (of -X on the negative
+ *            side), orthonormal.
+ *   m_cap    column capacity of V and lambda (>= 1)
+ *   m_inout  in: warm-start columns (0..m_cap); out: m_out
+ *   lambda   m_cap doubles (device): Ritz values of the approximated side's
+ *            matrix (X on the positive side, -X on the negative side) for the
+ *            returned columns of V, in descending order
+ *   Pi, ldpi n x n output Pi(X), both triangles written (device); Pi may not
+ *            alias X
+ * Returns PSDP_OK, PSDP_NOT_CONVERGED (Pi still valid, bound larger),
+ * PSDP_FELL_BACK_FULL_EIG, or an error.  info (host) is filled on return.
+ * On the full-eig side, V/lambda return the eigenpairs with positive
+ * eigenvalues (up to m_cap) and m_out their count. */
+psdp_status psdp_project(psdp_handle h, int n, const double *X, int ldx,
+                         double *V, int ldv, int m_cap, int *m_inout,
+                         double *lambda, double *Pi, int ldpi,
+                         const psdp_options *opt, psdp_info *info);
+
+/* Project `count` independent cones of uneven size in one persistent
+ * launch (paper §6.1: block-diagonal SDPs split into many smaller PSD
+ * variables).  Every array argument is a HOST array of length count whose
+ * elements are device pointers / sizes; cone i has order n[i] in [1, 256],
+ * leading dimension n[i] for X[i], V[i] and Pi[i], and m_cap[i] <= 96.
+ * m_inout[i] (host) is the warm-start width on entry and m_out on exit.
+ * Cones are solved with FP32 block products and FP64 Rayleigh-Ritz
+ * (opt->prec FP64 selects FP64 products).  info is a host array[count].
+ * A cone whose block outgrows m_cap[i] or that does not converge is
+ * reported in its info (status), the call returns the worst status. */
+psdp_status psdp_project_batched(psdp_handle h, int count, const int *n,
+                                 const double *const *X, double *const *V,
+                                 const int *m_cap, int *m_inout,
+                                 double *const *lambda, double *const *Pi,
+                                 const psdp_options *opt, psdp_info *info);
+
+/* Exact projection through a full FP64 eigendecomposition (rocSOLVER
+ * syevd), clip and rebuild: the exact fallback and the baseline path
+ * (paper §1: full eigendecomposition with syevr in COSMO).
+ *   lambda_all  n doubles (device, may be NULL): all eigenvalues ascending
+ *   Pi, ldpi    n x n output (device). */
+psdp_status psdp_full_eig_project(psdp_handle h, int n, const double *X, int ldx,
+                                  double *lambda_all, double *Pi, int ldpi);
+
+/* Static string for a status code. */
+const char *psdp_status_str(psdp_status s);
+
+/* Per-kernel timing on the handle's stream (hipEvents around every launch of
+ * the named kernel family while enabled).  Families: "product", "gram",
+ * "tsmm", "small", "rebuild", "ingest", "batched".  *launches is the count,
+ * *total_ms the summed event time, *bytes and *flops the algorithmic HBM
+ * bytes and flops of those launches.  Reset by psdp_profile_enable. */
+psdp_status psdp_profile_enable(psdp_handle h, int on);
+psdp_status psdp_profile_get(psdp_handle h, const char *family, long *launches,
+                             double *total_ms, double *bytes, double *flops);
+
+/* Library version string. */
+const char *psdp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSDP_H */

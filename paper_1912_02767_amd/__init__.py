@@ -1,0 +1,300 @@
+"""Warm-started approximate PSD-cone projection on AMD MI355X (gfx950).
+
+Python binding over the C-ABI of ``include/psdp.h`` (``libpsdp.so``).  This
+module only marshals arguments: every step of the projection runs in the HIP
+kernels of the library.  PyTorch provides device memory and the stream.
+
+    proj = Projector()
+    res = proj.project(X)                  # X: (n, n) float64 CUDA tensor
+    res.Pi, res.V, res.lam, res.info
+
+A ``Session`` keeps the Ritz block of one matrix sequence on the device so
+that the next projection is warm-started from it (paper §5.1: LOBPCG allows
+warm starting; §6: the side is chosen from the previous iterate's inertia).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+from . import _abi
+from ._abi import (PREC_BF16, PREC_FP32, PREC_FP64, PSDP_ERR_CAPACITY,
+                   PSDP_ERR_HIP, PSDP_ERR_INVALID_ARG, PSDP_ERR_NUMERICAL,
+                   PSDP_ERR_OUT_OF_MEMORY, PSDP_FELL_BACK_FULL_EIG,
+                   PSDP_NOT_CONVERGED, PSDP_OK, SIDE_AUTO, SIDE_FULL, SIDE_NEG,
+                   SIDE_POS, LibraryMissing, load, status_str)
+
+__all__ = ["Projector", "Session", "Result", "PsdpError", "load", "status_str",
+           "fortran", "PREC", "SIDE", "LibraryMissing"]
+
+PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
+SIDE = {"auto": SIDE_AUTO, "pos": SIDE_POS, "neg": SIDE_NEG, "full": SIDE_FULL}
+
+
+class PsdpError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {status_str(code)} ({code})")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def fortran(t):
+    """A column-major (Fortran-ordered) view of a 2-D tensor, copying only
+    when the tensor is not already column-major."""
+    if t.dim() != 2:
+        raise ValueError("expected a matrix")
+    if t.stride(0) == 1 and t.stride(1) >= max(1, t.shape[0]):
+        return t
+    return t.t().contiguous().t()
+
+
+def _empty_f(rows, cols, device, dtype=None):
+    torch = _torch()
+    dtype = dtype or torch.float64
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+@dataclass
+class Result:
+    Pi: object          # (n, n) float64, column-major
+    V: object           # (n, m_out) Ritz vectors of the approximated side
+    lam: object         # (m_out,) Ritz values of the approximated side's matrix
+    info: dict
+    status: int
+
+
+def _opts(lib, side="pos", prec="fp64", tol=0.0, max_iter=300, refine=True,
+          ladder=True, seed=None, side_threshold=1.0 / 3.0, expand_cols=0,
+          pos_hint=-1, fallback_full=False, block_guard=4):
+    o = _abi.Options()
+    lib.psdp_default_options(ctypes.byref(o))
+    o.side = SIDE[side] if isinstance(side, str) else int(side)
+    o.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.refine_fp64 = 1 if refine else 0
+    o.ladder = 1 if ladder else 0
+    if seed is not None:
+        o.seed = int(seed) & ((1 << 64) - 1)
+    o.side_threshold = float(side_threshold)
+    o.expand_cols = int(expand_cols)
+    o.pos_hint = int(pos_hint)
+    o.fallback_full = 1 if fallback_full else 0
+    o.block_guard = int(block_guard)
+    return o
+
+
+class Projector:
+    """A library handle bound to one device; calls enqueue on torch's
+    current stream of that device."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise PsdpError(PSDP_ERR_HIP, "Projector: no GPU visible")
+        self.device = int(device)
+        self._h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = self.lib.psdp_create(ctypes.byref(self._h), self.device, ctypes.c_void_p(stream))
+        if rc != PSDP_OK:
+            raise PsdpError(rc, "psdp_create")
+
+    # ------------------------------------------------------------ plumbing
+    def _sync_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        self.lib.psdp_set_stream(self._h, ctypes.c_void_p(s))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self.lib.psdp_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_matrix(self, X):
+        torch = _torch()
+        if X.dtype != torch.float64 or X.device.type != "cuda":
+            raise TypeError("X must be a float64 CUDA tensor")
+        if X.dim() != 2 or X.shape[0] != X.shape[1] or X.shape[0] < 1:
+            raise ValueError("X must be a non-empty square matrix")
+        return fortran(X)
+
+    # ------------------------------------------------------------ calls
+    def project(self, X, V=None, m_cap: Optional[int] = None, side="pos", prec="fp64",
+                tol: float = 0.0, max_iter: int = 300, refine: bool = True, ladder: bool = True,
+                seed=None, pos_hint: int = -1, expand_cols: int = 0, fallback_full: bool = False,
+                side_threshold: float = 1.0 / 3.0, block_guard: int = 4, V_buf=None,
+                Pi_out=None, lam_buf=None, raise_on_error: bool = True) -> Result:
+        """Pi(X) with LOBPCG on one spectral side (psdp_project).
+
+        V: optional warm start (n x k).  V_buf: optional column-major
+        (n x m_cap) device buffer reused in place (no copy of the block)."""
+        torch = _torch()
+        Xf = self._check_matrix(X)
+        n = Xf.shape[0]
+        self._sync_stream()
+        if V_buf is None:
+            k = 0 if V is None else V.shape[1]
+            cap = int(m_cap or max(k, 64))
+            cap = max(cap, k, 1)
+            V_buf = _empty_f(n, cap, Xf.device)
+            if k:
+                V_buf[:, :k].copy_(V)
+        else:
+            k = 0 if V is None else int(V)
+            cap = V_buf.shape[1]
+            if V_buf.stride(0) != 1:
+                raise ValueError("V_buf must be column-major")
+        if lam_buf is None or lam_buf.numel() < cap:
+            lam_buf = torch.empty(cap, dtype=torch.float64, device=Xf.device)
+        Pi = Pi_out if Pi_out is not None else _empty_f(n, n, Xf.device)
+        m_io = ctypes.c_int(k)
+        opt = _opts(self.lib, side, prec, tol, max_iter, refine, ladder, seed, side_threshold,
+                    expand_cols, pos_hint, fallback_full, block_guard)
+        info = _abi.Info()
+        rc = self.lib.psdp_project(self._h, n, ctypes.c_void_p(Xf.data_ptr()), Xf.stride(1),
+                                   ctypes.c_void_p(V_buf.data_ptr()), V_buf.stride(1), cap,
+                                   ctypes.byref(m_io), ctypes.c_void_p(lam_buf.data_ptr()),
+                                   ctypes.c_void_p(Pi.data_ptr()), Pi.stride(1),
+                                   ctypes.byref(opt), ctypes.byref(info))
+        if rc < 0 and raise_on_error:
+            raise PsdpError(rc, "psdp_project")
+        mo = m_io.value
+        return Result(Pi, V_buf[:, :mo], lam_buf[:mo], info.as_dict(), rc)
+
+    def full_eig(self, X, Pi_out=None, lam_out=None):
+        """Exact Pi(X) via the FP64 full eigendecomposition (psdp_full_eig_project)."""
+        torch = _torch()
+        Xf = self._check_matrix(X)
+        n = Xf.shape[0]
+        self._sync_stream()
+        Pi = Pi_out if Pi_out is not None else _empty_f(n, n, Xf.device)
+        lam = lam_out if lam_out is not None else torch.empty(n, dtype=torch.float64, device=Xf.device)
+        rc = self.lib.psdp_full_eig_project(self._h, n, ctypes.c_void_p(Xf.data_ptr()), Xf.stride(1),
+                                            ctypes.c_void_p(lam.data_ptr()),
+                                            ctypes.c_void_p(Pi.data_ptr()), Pi.stride(1))
+        if rc < 0:
+            raise PsdpError(rc, "psdp_full_eig_project")
+        return Pi, lam
+
+    def project_batched(self, Xs: Sequence, m_caps=None, Vs=None, prec="fp32", tol: float = 0.0,
+                        max_iter: int = 300, seed=None, pos_hints=None, V_bufs=None,
+                        Pi_outs=None) -> List[Result]:
+        """Many uneven cones in one persistent launch (psdp_project_batched)."""
+        torch = _torch()
+        if not hasattr(self.lib, "psdp_project_batched"):
+            raise PsdpError(PSDP_ERR_INVALID_ARG, "psdp_project_batched not in this build")
+        count = len(Xs)
+        Xf = [self._check_matrix(x) for x in Xs]
+        ns = [x.shape[0] for x in Xf]
+        for x in Xf:
+            if x.stride(1) != x.shape[0]:
+                raise ValueError("batched cones need leading dimension n")
+        self._sync_stream()
+        caps = list(m_caps) if m_caps is not None else [min(96, max(8, n // 3)) for n in ns]
+        if V_bufs is None:
+            V_bufs = [_empty_f(n, c, x.device) for n, c, x in zip(ns, caps, Xf)]
+        m_in = [0] * count
+        if Vs is not None:
+            for i, v in enumerate(Vs):
+                if v is not None and v.shape[1] > 0:
+                    V_bufs[i][:, :v.shape[1]].copy_(v)
+                    m_in[i] = v.shape[1]
+        lams = [torch.empty(c, dtype=torch.float64, device=x.device) for c, x in zip(caps, Xf)]
+        Pis = Pi_outs if Pi_outs is not None else [_empty_f(n, n, x.device) for n, x in zip(ns, Xf)]
+        IA = ctypes.c_int * count
+        PA = ctypes.c_void_p * count
+        n_arr = IA(*ns)
+        cap_arr = IA(*caps)
+        mio = IA(*m_in)
+        X_arr = PA(*[x.data_ptr() for x in Xf])
+        V_arr = PA(*[v.data_ptr() for v in V_bufs])
+        L_arr = PA(*[l.data_ptr() for l in lams])
+        P_arr = PA(*[p.data_ptr() for p in Pis])
+        opt = _opts(self.lib, "pos", prec, tol, max_iter, True, True, seed)
+        infos = (_abi.Info * count)()
+        rc = self.lib.psdp_project_batched(self._h, count, n_arr, X_arr, V_arr, cap_arr, mio,
+                                           L_arr, P_arr, ctypes.byref(opt), infos)
+        if rc < 0:
+            raise PsdpError(rc, "psdp_project_batched")
+        out = []
+        for i in range(count):
+            mo = mio[i]
+            out.append(Result(Pis[i], V_bufs[i][:, :mo], lams[i][:mo], infos[i].as_dict(),
+                              infos[i].status))
+        return out
+
+    # ------------------------------------------------------------ profiling
+    def profile_enable(self, on: bool = True):
+        self.lib.psdp_profile_enable(self._h, 1 if on else 0)
+
+    def profile_get(self, family: str):
+        n = ctypes.c_long()
+        ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self.lib.psdp_profile_get(self._h, family.encode(), ctypes.byref(n), ctypes.byref(ms),
+                                  ctypes.byref(by), ctypes.byref(fl))
+        return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+
+
+class Session:
+    """Warm-start memory of one matrix sequence (one PSD variable of an ADMM
+    solve): the Ritz block stays on the device between calls and the side is
+    chosen from the previous call's inertia (paper §6)."""
+
+    def __init__(self, projector: Projector, n: int, m_cap: int = 64, prec="fp64",
+                 tol: float = 0.0, side="auto", pos_hint: int = -1, **kw):
+        torch = _torch()
+        self.p = projector
+        self.n = n
+        self.m_cap = m_cap
+        self.prec = prec
+        self.tol = tol
+        self.side_mode = side
+        self.kw = kw
+        self.V_buf = _empty_f(n, m_cap, torch.device("cuda", projector.device))
+        self.lam_buf = torch.empty(m_cap, dtype=torch.float64, device=self.V_buf.device)
+        self.m = 0
+        self.last_side = None
+        self.pos_hint = pos_hint
+        self.calls = 0
+
+    def project(self, X, Pi_out=None) -> Result:
+        side = self.side_mode
+        hint = self.pos_hint
+        if side == "auto":
+            # resolve here so that a side switch drops the (other side's) block
+            if hint < 0:
+                side = "full"
+            elif hint < self.n / 3.0:
+                side = "pos"
+            elif self.n - hint < self.n / 3.0:
+                side = "neg"
+            else:
+                side = "full"
+        warm = self.m if (self.last_side == side and side != "full") else 0
+        res = self.p.project(X, V=warm, side=side, prec=self.prec, tol=self.tol,
+                             pos_hint=hint, V_buf=self.V_buf, lam_buf=self.lam_buf,
+                             Pi_out=Pi_out, **self.kw)
+        info = res.info
+        if info["side_used"] == SIDE_FULL:
+            self.pos_hint = info["n_pos_full"]
+            self.m = 0
+            self.last_side = "full"
+        else:
+            self.m = info["m_out"]
+            self.last_side = "pos" if info["side_used"] == SIDE_POS else "neg"
+            np_side = info["n_pos"]
+            self.pos_hint = np_side if self.last_side == "pos" else self.n - np_side
+        self.calls += 1
+        return res

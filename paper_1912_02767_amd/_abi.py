@@ -1,0 +1,129 @@
+"""ctypes declarations of the C-ABI in include/psdp.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsdp.so")
+
+PSDP_OK = 0
+PSDP_NOT_CONVERGED = 1
+PSDP_FELL_BACK_FULL_EIG = 2
+PSDP_ERR_INVALID_ARG = -1
+PSDP_ERR_HIP = -2
+PSDP_ERR_OUT_OF_MEMORY = -3
+PSDP_ERR_NUMERICAL = -4
+PSDP_ERR_CAPACITY = -5
+
+SIDE_AUTO, SIDE_POS, SIDE_NEG, SIDE_FULL = 0, 1, 2, 3
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
+
+# every symbol include/psdp.h declares
+EXPORTED = [
+    "psdp_default_options", "psdp_create", "psdp_destroy", "psdp_set_stream",
+    "psdp_workspace_bytes", "psdp_project", "psdp_project_batched",
+    "psdp_full_eig_project", "psdp_status_str", "psdp_profile_enable",
+    "psdp_profile_get", "psdp_version",
+]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("side", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("refine_fp64", ctypes.c_int),
+        ("ladder", ctypes.c_int),
+        ("certify", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong),
+        ("side_threshold", ctypes.c_double),
+        ("expand_cols", ctypes.c_int),
+        ("pos_hint", ctypes.c_int),
+        ("fallback_full", ctypes.c_int),
+        ("block_guard", ctypes.c_int),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("err_bound", ctypes.c_double),
+        ("res_fro", ctypes.c_double),
+        ("tail_est", ctypes.c_double),
+        ("pi_fro", ctypes.c_double),
+        ("theta_guard", ctypes.c_double),
+        ("tol_used", ctypes.c_double),
+        ("n_pos", ctypes.c_int),
+        ("m_out", ctypes.c_int),
+        ("iters", ctypes.c_int),
+        ("side_used", ctypes.c_int),
+        ("certified", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("expansions", ctypes.c_int),
+        ("prec_final", ctypes.c_int),
+        ("n_pos_full", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def load():
+    """Load libpsdp.so (built in-tree by paper_1912_02767_amd/build.py).
+
+    Raises LibraryMissing when it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LibraryMissing(
+            f"{LIB_PATH} not found: build it with `python -m paper_1912_02767_amd.build` "
+            "(hipcc --offload-arch=gfx950); the projection has no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    lib.psdp_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.psdp_default_options.restype = None
+    lib.psdp_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.psdp_create.restype = ctypes.c_int
+    lib.psdp_destroy.argtypes = [vp]
+    lib.psdp_destroy.restype = ctypes.c_int
+    lib.psdp_set_stream.argtypes = [vp, vp]
+    lib.psdp_set_stream.restype = ctypes.c_int
+    lib.psdp_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_size_t)]
+    lib.psdp_workspace_bytes.restype = ctypes.c_int
+    lib.psdp_project.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
+                                 ctypes.c_int, ip, vp, vp, ctypes.c_int,
+                                 ctypes.POINTER(Options), ctypes.POINTER(Info)]
+    lib.psdp_project.restype = ctypes.c_int
+    if hasattr(lib, "psdp_project_batched"):
+        lib.psdp_project_batched.argtypes = [vp, ctypes.c_int, ip, ctypes.POINTER(vp),
+                                             ctypes.POINTER(vp), ip, ip, ctypes.POINTER(vp),
+                                             ctypes.POINTER(vp), ctypes.POINTER(Options),
+                                             ctypes.POINTER(Info)]
+        lib.psdp_project_batched.restype = ctypes.c_int
+    lib.psdp_full_eig_project.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp,
+                                          ctypes.c_int]
+    lib.psdp_full_eig_project.restype = ctypes.c_int
+    lib.psdp_status_str.argtypes = [ctypes.c_int]
+    lib.psdp_status_str.restype = ctypes.c_char_p
+    lib.psdp_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.psdp_profile_enable.restype = ctypes.c_int
+    lib.psdp_profile_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp, dp, dp]
+    lib.psdp_profile_get.restype = ctypes.c_int
+    lib.psdp_version.argtypes = []
+    lib.psdp_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def status_str(code: int) -> str:
+    return load().psdp_status_str(int(code)).decode()

@@ -1,0 +1,935 @@
+// Host driver of the single-cone projection and the C-ABI entry points.
+//
+// One psdp_project call (paper §5.1, Alg. 3 with the §6 side rule and the
+// §5.2 bound):
+//   ingest      A = s * sym(X) (s = +1 positive side, -1 negative side), in
+//               FP64 and in the product precision
+//   start       warm-start block V (or seeded N(0,1) columns), Rayleigh-Ritz
+//               on its span with an FP64 product (Alg. 3, initial RR)
+//   iterate     trial basis [X, R, P] -> two Cholesky-QR passes -> A S ->
+//               S^T A S -> Jacobi -> X, AX, P, R   (Alg. 3 loop)
+//   expand      when more positive Ritz values than columns: append seeded
+//               random columns (paper §5.1 expansion rule)
+//   ladder      low-precision products until the residual stalls, then
+//               higher precision; an FP64 refresh + sweep at the end
+//   bound       err^2 = 2 ||R||_F^2 + tail^2 (Thm `bound`), tail estimated
+//   rebuild     Pi = V diag(l) V^T (+ X on the negative side, Moreau)
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/psdp.h"
+#include "common.h"
+
+namespace psdp {
+// launchers defined in the kernel files
+hipError_t launch_gram_partial(const ColMap& bptr, const ColMap* yptr, const int* nb_dev,
+                               int nb_host, const int* ny_dev, int ny_host, int n, double* part,
+                               int ldp, size_t part_stride, int* nblk_out, const int* stop,
+                               hipStream_t st);
+hipError_t launch_reduce_partials(const double* part, int nblk, size_t part_stride, int ldp,
+                                  const int* rows_dev, int rows_host, const int* cols_dev,
+                                  int cols_host, double* out, int ldo, const int* stop,
+                                  hipStream_t st);
+hipError_t launch_tsmm(const ColMap& src, const int* kk_dev, int kk_host, const int* q_dev,
+                       int q_host, const double* M, int ldm, int n, double* Y, int ldy,
+                       const int* stop, hipStream_t st);
+hipError_t launch_update(const double* S, const double* AS, int lds, const double* C, int ldc,
+                         const State* stt, int want_p, int n, int mk_host, double* Xo,
+                         double* AXo, double* Po, double* Ro, int ldo, hipStream_t st);
+hipError_t launch_rebuild(const double* V, int ldv, const double* lt, int mt, int n,
+                          const double* base, int ldb, double base_sign, double* Pi, int ldpi,
+                          hipStream_t st);
+}  // namespace psdp
+
+using namespace psdp;
+
+namespace {
+
+constexpr int kMaxSweeps = 40;
+
+struct ProfEntry {
+  long launches = 0;
+  double ms = 0.0, bytes = 0.0, flops = 0.0;
+};
+
+struct PendingEvent {
+  std::string family;
+  hipEvent_t a, b;
+  double bytes, flops;
+};
+
+struct Workspace {
+  int L = 0, MC = 0, NC = 0, prec = -1, nblk = 0;
+  size_t bytes = 0;
+  char* base = nullptr;
+  double *A64 = nullptr;
+  void* Alp = nullptr;
+  double *X = nullptr, *R = nullptr, *P = nullptr, *AX = nullptr, *Z = nullptr;
+  double *S1 = nullptr, *S2 = nullptr, *AS = nullptr;
+  double *Gpart = nullptr, *G = nullptr, *T = nullptr, *C = nullptr;
+  double* log = nullptr;
+  size_t log_cap = 0;
+  const double** colptr = nullptr;
+  double* fro_part = nullptr;
+  int fro_nblk = 0;
+  double* scal = nullptr;  // [0] fro2
+  int* nonfinite = nullptr;
+  State* st = nullptr;
+};
+
+}  // namespace
+
+struct psdp_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Workspace ws;
+  State* h_state = nullptr;  // pinned mirror
+  rocblas_handle rb = nullptr;
+  double* eig_d = nullptr;  // full-eig scratch
+  double* eig_e = nullptr;
+  rocblas_int* eig_info = nullptr;
+  double* eig_A = nullptr;
+  int eig_cap = 0;
+  double* h_pin = nullptr;  // pinned scratch for small readbacks
+  size_t h_pin_cap = 0;
+  unsigned long long calls = 0;
+  bool prof = false;
+  std::map<std::string, ProfEntry> prof_tab;
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return PSDP_ERR_HIP;         \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+hipEvent_t get_event(psdp_handle h) {
+  if (!h->event_pool.empty()) {
+    hipEvent_t e = h->event_pool.back();
+    h->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  psdp_handle h;
+  const char* fam;
+  hipEvent_t a = nullptr, b = nullptr;
+  double bytes, flops;
+  ProfScope(psdp_handle h_, const char* f, double by = 0, double fl = 0)
+      : h(h_), fam(f), bytes(by), flops(fl) {
+    if (h->prof) {
+      a = get_event(h);
+      b = get_event(h);
+      if (a) (void)hipEventRecord(a, h->stream);
+    }
+  }
+  ~ProfScope() {
+    if (h->prof && a && b) {
+      (void)hipEventRecord(b, h->stream);
+      h->pending.push_back({fam, a, b, bytes, flops});
+    }
+  }
+};
+
+void prof_collect(psdp_handle h) {
+  if (h->pending.empty()) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.a, p.b);
+    auto& e = h->prof_tab[p.family];
+    e.launches += 1;
+    e.ms += ms;
+    e.bytes += p.bytes;
+    e.flops += p.flops;
+    h->event_pool.push_back(p.a);
+    h->event_pool.push_back(p.b);
+  }
+  h->pending.clear();
+}
+
+size_t product_elem_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+
+psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
+  Workspace& w = h->ws;
+  int L = round_up(std::max(n, 1), 64);
+  int MC = std::min(std::max(mc, 1), kMaxM);
+  int NC = 3 * MC;
+  (void)prec;  // the low-precision copy is sized for FP32, which also holds BF16
+  if (w.base && L <= w.L && MC <= w.MC) return PSDP_OK;
+  // grow
+  L = std::max(L, w.L);
+  MC = std::max(MC, w.MC);
+  NC = 3 * MC;
+  int wprec = 1;
+  int nblk = (L + kGramRows - 1) / kGramRows;
+  int T32 = (L + 31) / 32;
+  int fro_nblk = T32 * (T32 + 1) / 2;
+  size_t log_cap = (size_t)kMaxSweeps * (NC + 1) * (NC + 2);
+  size_t sz = 0;
+  auto take = [&](size_t b) {
+    size_t off = sz;
+    sz = align_up(sz + b, 256);
+    return off;
+  };
+  size_t oA64 = take(sizeof(double) * (size_t)L * L);
+  size_t oAlp = take((size_t)L * L * 4);
+  size_t oX = take(sizeof(double) * (size_t)L * MC);
+  size_t oR = take(sizeof(double) * (size_t)L * MC);
+  size_t oP = take(sizeof(double) * (size_t)L * MC);
+  size_t oAX = take(sizeof(double) * (size_t)L * MC);
+  size_t oZ = take(sizeof(double) * (size_t)L * MC);
+  size_t oS1 = take(sizeof(double) * (size_t)L * NC);
+  size_t oS2 = take(sizeof(double) * (size_t)L * NC);
+  size_t oAS = take(sizeof(double) * (size_t)L * NC);
+  size_t oGp = take(sizeof(double) * (size_t)nblk * NC * NC);
+  size_t oG = take(sizeof(double) * (size_t)NC * NC);
+  size_t oT = take(sizeof(double) * (size_t)NC * NC);
+  size_t oC = take(sizeof(double) * (size_t)NC * NC);
+  size_t oLog = take(sizeof(double) * log_cap);
+  size_t oPtr = take(sizeof(double*) * (size_t)NC);
+  size_t oFro = take(sizeof(double) * (size_t)fro_nblk);
+  size_t oScal = take(sizeof(double) * 16);
+  size_t oNf = take(sizeof(int) * 16);
+  size_t oSt = take(sizeof(State));
+  if (w.base) {
+    (void)hipStreamSynchronize(h->stream);
+    hipFree(w.base);
+    w.base = nullptr;
+  }
+  char* base = nullptr;
+  if (hipMalloc(&base, sz) != hipSuccess) {
+    w = Workspace();
+    return PSDP_ERR_OUT_OF_MEMORY;
+  }
+  w.base = base;
+  w.bytes = sz;
+  w.L = L; w.MC = MC; w.NC = NC; w.prec = wprec; w.nblk = nblk;
+  w.A64 = (double*)(base + oA64);
+  w.Alp = (void*)(base + oAlp);
+  w.X = (double*)(base + oX);
+  w.R = (double*)(base + oR);
+  w.P = (double*)(base + oP);
+  w.AX = (double*)(base + oAX);
+  w.Z = (double*)(base + oZ);
+  w.S1 = (double*)(base + oS1);
+  w.S2 = (double*)(base + oS2);
+  w.AS = (double*)(base + oAS);
+  w.Gpart = (double*)(base + oGp);
+  w.G = (double*)(base + oG);
+  w.T = (double*)(base + oT);
+  w.C = (double*)(base + oC);
+  w.log = (double*)(base + oLog);
+  w.log_cap = log_cap;
+  w.colptr = (const double**)(base + oPtr);
+  w.fro_part = (double*)(base + oFro);
+  w.fro_nblk = fro_nblk;
+  w.scal = (double*)(base + oScal);
+  w.nonfinite = (int*)(base + oNf);
+  w.st = (State*)(base + oSt);
+  // zero everything once so padded rows are zero
+  HIP_TRY(hipMemsetAsync(base, 0, sz, h->stream));
+  return PSDP_OK;
+}
+
+psdp_status ensure_pinned(psdp_handle h, size_t bytes) {
+  if (h->h_pin_cap >= bytes) return PSDP_OK;
+  if (h->h_pin) hipHostFree(h->h_pin);
+  h->h_pin = nullptr;
+  h->h_pin_cap = 0;
+  if (hipHostMalloc((void**)&h->h_pin, bytes, hipHostMallocDefault) != hipSuccess)
+    return PSDP_ERR_OUT_OF_MEMORY;
+  h->h_pin_cap = bytes;
+  return PSDP_OK;
+}
+
+// ---------------------------------------------------------------- solver --
+struct Solver {
+  psdp_handle h;
+  Workspace& w;
+  hipStream_t s;
+  int n;
+  int m;       // current block
+  int mcap;    // capacity (<= kMaxM and the caller's m_cap)
+  int has_p = 0;
+  int iters = 0;
+  int prec;    // product precision of the current phase
+  State* hs;   // pinned host mirror
+  Solver(psdp_handle h_, int n_, int mcap_)
+      : h(h_), w(h_->ws), s(h_->stream), n(n_), m(0), mcap(mcap_), prec(0), hs(h_->h_state) {}
+
+  const void* amat(int p) const { return p == 0 ? (const void*)w.A64 : w.Alp; }
+
+  psdp_status read_state() {
+    HIP_TRY(hipMemcpyAsync(hs, w.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PSDP_OK;
+  }
+
+  // one Rayleigh-Ritz iteration on the trial basis given by `mode`
+  psdp_status iterate(int mode, int pprec, int mtarget, int nz) {
+    const int L = w.L, NC = w.NC;
+    const int* stop = &w.st->stop;
+    // ---- Gram of the candidate columns (gives residual norms too)
+    ColMap cand;
+    int Ng;
+    if (mode == kModeXOnly) {
+      cand = colmap_seg(w.X, m, L);
+      Ng = m;
+    } else if (mode == kModeXZ) {
+      cand = colmap_seg(w.X, m, L, w.Z, nz);
+      Ng = m + nz;
+    } else {
+      cand = colmap_seg(w.X, m, L, w.R, m, has_p ? w.P : nullptr, has_p ? m : 0);
+      Ng = has_p ? 3 * m : 2 * m;
+    }
+    int nblk = 0;
+    {
+      ProfScope ps(h, "gram");
+      HIP_TRY(launch_gram_partial(cand, nullptr, nullptr, Ng, nullptr, Ng, n, w.Gpart, NC,
+                                  (size_t)NC * NC, &nblk, nullptr, s));
+      HIP_TRY(launch_reduce_partials(w.Gpart, nblk, (size_t)NC * NC, NC, nullptr, Ng, nullptr, Ng,
+                                     w.G, NC, nullptr, s));
+    }
+    // ---- decisions + first Cholesky-QR pass
+    DecideArgs da{};
+    da.G = w.G; da.ldg = NC; da.Ng = Ng; da.mode = mode; da.m = m; da.nz = nz;
+    da.has_p = has_p; da.phase_lowprec = pprec != 0; da.tau = 1e-10;
+    da.bases[0] = w.X; da.bases[1] = w.R; da.bases[2] = w.P; da.bases[3] = w.Z; da.bases[4] = w.S1;
+    da.ld = L; da.T = w.T; da.ldt = NC; da.colptr = w.colptr; da.st = w.st;
+    int Nmax = Ng;  // upper bound on the trial width
+    {
+      ProfScope ps(h, "chol");
+      HIP_TRY(launch_decide_chol(da, Nmax, s));
+    }
+    // orth pass 1: S1 = S T1
+    {
+      ProfScope ps(h, "tsmm");
+      HIP_TRY(launch_tsmm(colmap_ptrs(w.colptr), &w.st->N, Nmax, &w.st->Np, Nmax, w.T, NC, n,
+                          w.S1, L, stop, s));
+    }
+    // orth pass 2
+    {
+      ProfScope ps(h, "gram");
+      HIP_TRY(launch_gram_partial(colmap_seg(w.S1, NC, L), nullptr, &w.st->Np, Nmax, nullptr, 0,
+                                  n, w.Gpart, NC, (size_t)NC * NC, &nblk, stop, s));
+      HIP_TRY(launch_reduce_partials(w.Gpart, nblk, (size_t)NC * NC, NC, &w.st->Np, Nmax,
+                                     &w.st->Np, Nmax, w.G, NC, stop, s));
+    }
+    DecideArgs db = da;
+    db.mode = -1;  // second pass: the candidate count is st->Np on the device
+    db.Ng = Nmax;
+    {
+      ProfScope ps(h, "chol");
+      HIP_TRY(launch_decide_chol(db, Nmax, s));
+    }
+    {
+      ProfScope ps(h, "tsmm");
+      HIP_TRY(launch_tsmm(colmap_seg(w.S1, NC, L), &w.st->Np1, Nmax, &w.st->Np, Nmax, w.T, NC, n,
+                          w.S2, L, stop, s));
+    }
+    // ---- block product AS = A S2 at the phase precision
+    {
+      ProfScope ps(h, "product");
+      ProductArgs pa{};
+      pa.A = amat(pprec); pa.lda = L; pa.n = n; pa.prec = pprec;
+      pa.S = w.S2; pa.lds = L; pa.Y = w.AS; pa.ldy = L;
+      pa.cols_dev = &w.st->Np; pa.cols_max = Nmax; pa.stop = stop;
+      HIP_TRY(launch_product(pa, s));
+    }
+    // ---- projected matrix K = S2^T A S2
+    {
+      ProfScope ps(h, "gram");
+      ColMap s2 = colmap_seg(w.S2, NC, L), as = colmap_seg(w.AS, NC, L);
+      HIP_TRY(launch_gram_partial(s2, &as, &w.st->Np, Nmax, &w.st->Np, Nmax, n, w.Gpart, NC,
+                                  (size_t)NC * NC, &nblk, stop, s));
+      HIP_TRY(launch_reduce_partials(w.Gpart, nblk, (size_t)NC * NC, NC, &w.st->Np, Nmax,
+                                     &w.st->Np, Nmax, w.G, NC, stop, s));
+    }
+    // ---- Rayleigh-Ritz
+    RRArgs ra{};
+    ra.K = w.G; ra.ldk = NC; ra.mtarget = mtarget; ra.C = w.C; ra.ldc = NC;
+    ra.log = w.log; ra.log_cap = w.log_cap; ra.max_sweeps = kMaxSweeps;
+    ra.count_iter = (mode == kModeFull || mode == kModeXR) ? 1 : 0;
+    ra.st = w.st;
+    {
+      ProfScope ps(h, "rr");
+      HIP_TRY(launch_rr(ra, Nmax, std::min(mtarget, Nmax), s));
+    }
+    // ---- update X, AX, P, R
+    int want_p = (mode == kModeFull || mode == kModeXR) ? 1 : 0;
+    {
+      ProfScope ps(h, "tsmm");
+      HIP_TRY(launch_update(w.S2, w.AS, L, w.C, NC, w.st, want_p, n, std::min(mtarget, Nmax),
+                            w.X, w.AX, w.P, w.R, L, s));
+    }
+    psdp_status rs = read_state();
+    if (rs != PSDP_OK) return rs;
+    if (h->prof && hs->stop == kRunning) {
+      auto& e = h->prof_tab["rr_stats"];  // launches: RR calls, bytes: sum Np, flops: sum rounds
+      e.launches += 1;
+      e.bytes += hs->Np;
+      e.flops += hs->jacobi_rounds;
+    }
+    if (h->prof) {
+      // attribute the algorithmic bytes/flops of this iteration's product
+      // now that its width is known
+      for (auto it = h->pending.rbegin(); it != h->pending.rend(); ++it)
+        if (it->family == "product") {
+          double k = (hs->stop == kRunning || mode == kModeXOnly || mode == kModeXZ) ? hs->Np : 0;
+          it->flops = 2.0 * n * (double)n * k;
+          it->bytes = (double)product_elem_bytes(pprec) * n * (double)n + 16.0 * n * k;
+          break;
+        }
+    }
+    if (hs->stop == kRunning || mode == kModeXOnly || mode == kModeXZ) {
+      if (hs->stop == kBreakdown) return PSDP_ERR_NUMERICAL;
+      m = hs->mk;
+      has_p = want_p;
+    }
+    return PSDP_OK;
+  }
+  // residual statistics of the current block without changing it
+  psdp_status evaluate() {
+    const int L = w.L, NC = w.NC;
+    ColMap cand = colmap_seg(w.X, m, L, w.R, m, has_p ? w.P : nullptr, has_p ? m : 0);
+    int Ng = has_p ? 3 * m : 2 * m;
+    int nblk = 0;
+    {
+      ProfScope ps(h, "gram");
+      HIP_TRY(launch_gram_partial(cand, nullptr, nullptr, Ng, nullptr, Ng, n, w.Gpart, NC,
+                                  (size_t)NC * NC, &nblk, nullptr, s));
+      HIP_TRY(launch_reduce_partials(w.Gpart, nblk, (size_t)NC * NC, NC, nullptr, Ng, nullptr, Ng,
+                                     w.G, NC, nullptr, s));
+    }
+    DecideArgs da{};
+    da.G = w.G; da.ldg = NC; da.Ng = Ng; da.mode = kModeEval; da.m = m; da.nz = 0;
+    da.has_p = has_p; da.tau = 1e-10;
+    da.bases[0] = w.X; da.bases[1] = w.R; da.bases[2] = w.P; da.bases[3] = w.Z; da.bases[4] = w.S1;
+    da.ld = L; da.T = w.T; da.ldt = NC; da.colptr = w.colptr; da.st = w.st;
+    {
+      ProfScope ps(h, "chol");
+      HIP_TRY(launch_decide_chol(da, Ng, s));
+    }
+    return read_state();
+  }
+};
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* psdp_version(void) { return "psdp 0.1 (gfx950)"; }
+
+const char* psdp_status_str(psdp_status s) {
+  switch (s) {
+    case PSDP_OK: return "PSDP_OK";
+    case PSDP_NOT_CONVERGED: return "PSDP_NOT_CONVERGED";
+    case PSDP_FELL_BACK_FULL_EIG: return "PSDP_FELL_BACK_FULL_EIG";
+    case PSDP_ERR_INVALID_ARG: return "PSDP_ERR_INVALID_ARG";
+    case PSDP_ERR_HIP: return "PSDP_ERR_HIP";
+    case PSDP_ERR_OUT_OF_MEMORY: return "PSDP_ERR_OUT_OF_MEMORY";
+    case PSDP_ERR_NUMERICAL: return "PSDP_ERR_NUMERICAL";
+    case PSDP_ERR_CAPACITY: return "PSDP_ERR_CAPACITY";
+  }
+  return "PSDP_UNKNOWN_STATUS";
+}
+
+void psdp_default_options(psdp_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->side = PSDP_SIDE_AUTO;
+  o->prec = PSDP_PREC_FP64;
+  o->tol = 0.0;
+  o->max_iter = 300;
+  o->refine_fp64 = 1;
+  o->ladder = 1;
+  o->certify = 0;
+  o->seed = 0x1912276700000000ull;
+  o->side_threshold = 1.0 / 3.0;
+  o->expand_cols = 0;
+  o->pos_hint = -1;
+  o->fallback_full = 0;
+  o->block_guard = 4;
+}
+
+psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t* bytes) {
+  if (!bytes || n < 1 || m_cap < 1 || prec < 0 || prec > 2) return PSDP_ERR_INVALID_ARG;
+  size_t L = (size_t)round_up(n, 64);
+  size_t MC = (size_t)std::min(m_cap, kMaxM), NC = 3 * MC;
+  size_t nblk = (L + kGramRows - 1) / kGramRows;
+  size_t T32 = (L + 31) / 32;
+  size_t b = 8 * L * L + 4 * L * L + 5 * 8 * L * MC + 3 * 8 * L * NC + 8 * nblk * NC * NC +
+             3 * 8 * NC * NC + 8 * (size_t)kMaxSweeps * (NC + 1) * (NC + 2) + 8 * NC +
+             8 * T32 * (T32 + 1) / 2 + sizeof(State) + 4096;
+  *bytes = b;
+  return PSDP_OK;
+}
+
+psdp_status psdp_create(psdp_handle* out, int device, void* stream) {
+  if (!out) return PSDP_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PSDP_ERR_HIP;
+  if (device < 0 || device >= count) return PSDP_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return PSDP_ERR_HIP;
+  psdp_handle h = new (std::nothrow) psdp_handle_s();
+  if (!h) return PSDP_ERR_OUT_OF_MEMORY;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  if (small_kernels_init() != hipSuccess) { delete h; return PSDP_ERR_HIP; }
+  if (hipHostMalloc((void**)&h->h_state, sizeof(State), hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return PSDP_ERR_OUT_OF_MEMORY;
+  }
+  *out = h;
+  return PSDP_OK;
+}
+
+psdp_status psdp_destroy(psdp_handle h) {
+  if (!h) return PSDP_ERR_INVALID_ARG;
+  hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  prof_collect(h);
+  for (auto e : h->event_pool) hipEventDestroy(e);
+  if (h->ws.base) hipFree(h->ws.base);
+  if (h->eig_A) hipFree(h->eig_A);
+  if (h->h_state) hipHostFree(h->h_state);
+  if (h->h_pin) hipHostFree(h->h_pin);
+  if (h->rb) rocblas_destroy_handle(h->rb);
+  delete h;
+  return PSDP_OK;
+}
+
+psdp_status psdp_set_stream(psdp_handle h, void* stream) {
+  if (!h) return PSDP_ERR_INVALID_ARG;
+  h->stream = (hipStream_t)stream;
+  if (h->rb) rocblas_set_stream(h->rb, h->stream);
+  return PSDP_OK;
+}
+
+psdp_status psdp_profile_enable(psdp_handle h, int on) {
+  if (!h) return PSDP_ERR_INVALID_ARG;
+  prof_collect(h);
+  h->prof_tab.clear();
+  h->prof = on != 0;
+  return PSDP_OK;
+}
+
+psdp_status psdp_profile_get(psdp_handle h, const char* family, long* launches, double* total_ms,
+                             double* bytes, double* flops) {
+  if (!h || !family) return PSDP_ERR_INVALID_ARG;
+  prof_collect(h);
+  auto it = h->prof_tab.find(family);
+  ProfEntry e;
+  if (it != h->prof_tab.end()) e = it->second;
+  if (launches) *launches = e.launches;
+  if (total_ms) *total_ms = e.ms;
+  if (bytes) *bytes = e.bytes;
+  if (flops) *flops = e.flops;
+  return PSDP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ full eig ----
+static psdp_status full_eig_core(psdp_handle h, int n, const double* X, int ldx, double* lambda_all,
+                                 double* Pi, int ldpi, double* V, int ldv, int m_cap, int* m_out,
+                                 double* lambda_pos, int* npos_out) {
+  hipStream_t s = h->stream;
+  if (!h->rb) {
+    if (rocblas_create_handle(&h->rb) != rocblas_status_success) return PSDP_ERR_HIP;
+  }
+  rocblas_set_stream(h->rb, s);
+  int lda = round_up(n, 64);
+  const int T32 = (lda + 31) / 32;
+  const size_t fro_n = (size_t)T32 * (T32 + 1) / 2;
+  if (h->eig_cap < n) {
+    if (h->eig_A) hipFree(h->eig_A);
+    h->eig_A = nullptr;
+    size_t b = sizeof(double) * ((size_t)lda * n + 2 * (size_t)n + 8 + fro_n + 8) + 64;
+    if (hipMalloc(&h->eig_A, b) != hipSuccess) { h->eig_cap = 0; return PSDP_ERR_OUT_OF_MEMORY; }
+    h->eig_cap = n;
+  }
+  double* A = h->eig_A;
+  double* d = A + (size_t)lda * n;
+  double* e = d + n;
+  rocblas_int* info = (rocblas_int*)(e + n);
+  double* fro_part = e + n + 8;
+  int* nonfin = (int*)(fro_part + fro_n);
+  // symmetric copy (lower triangle of X) via the ingest kernel, FP64 only
+  int nb = 0;
+  HIP_TRY(launch_ingest(X, ldx, n, 1.0, A, lda, nullptr, 0, fro_part, nonfin, s, &nb));
+  (void)nb;
+  {
+    ProfScope pscope(h, "fulleig");
+    if (rocsolver_dsyevd(h->rb, rocblas_evect_original, rocblas_fill_lower, n, A, lda, d, e, info) !=
+        rocblas_status_success)
+      return PSDP_ERR_HIP;
+  }
+  // count positive eigenvalues (ascending order)
+  psdp_status pp = ensure_pinned(h, sizeof(double) * (size_t)n + 64);
+  if (pp != PSDP_OK) return pp;
+  HIP_TRY(hipMemcpyAsync(h->h_pin, d, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h->h_pin + n, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int infov = 0;
+  std::memcpy(&infov, h->h_pin + n, sizeof(rocblas_int));
+  int npos = 0;
+  bool finite = true;
+  for (int i = 0; i < n; ++i) {
+    npos += (h->h_pin[i] > 0.0);
+    finite &= std::isfinite(h->h_pin[i]);
+  }
+  if (infov != 0 || !finite) return PSDP_ERR_NUMERICAL;
+  if (lambda_all) HIP_TRY(hipMemcpyAsync(lambda_all, d, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  {
+    ProfScope pscope(h, "rebuild", 8.0 * n * (double)n, (double)n * n * npos);
+    HIP_TRY(launch_rebuild(A + (size_t)(n - npos) * lda, lda, d + (n - npos), npos, n, nullptr, 0,
+                           0.0, Pi, ldpi, s));
+  }
+  if (V && m_out) {
+    int k = std::min(npos, m_cap);
+    // largest first
+    for (int j = 0; j < k; ++j) {
+      HIP_TRY(hipMemcpyAsync(V + (size_t)j * ldv, A + (size_t)(n - 1 - j) * lda, sizeof(double) * n,
+                             hipMemcpyDeviceToDevice, s));
+      HIP_TRY(hipMemcpyAsync(lambda_pos + j, d + (n - 1 - j), sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    *m_out = k;
+  }
+  if (npos_out) *npos_out = npos;
+  HIP_TRY(hipStreamSynchronize(s));
+  return PSDP_OK;
+}
+
+extern "C" psdp_status psdp_full_eig_project(psdp_handle h, int n, const double* X, int ldx,
+                                             double* lambda_all, double* Pi, int ldpi) {
+  if (!h || n < 1 || !X || !Pi || ldx < n || ldpi < n) return PSDP_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
+  return full_eig_core(h, n, X, ldx, lambda_all, Pi, ldpi, nullptr, 0, 0, nullptr, nullptr, nullptr);
+}
+
+// ---------------------------------------------------------- single cone ---
+static void fill_info_defaults(psdp_info* info) {
+  std::memset(info, 0, sizeof(*info));
+  info->err_bound = NAN;
+  info->res_fro = NAN;
+  info->tail_est = NAN;
+  info->pi_fro = NAN;
+  info->theta_guard = NAN;
+  info->n_pos_full = -1;
+}
+
+extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int ldx, double* V,
+                                    int ldv, int m_cap, int* m_inout, double* lambda, double* Pi,
+                                    int ldpi, const psdp_options* opt_in, psdp_info* info) {
+  psdp_info dummy;
+  if (!info) info = &dummy;
+  fill_info_defaults(info);
+  psdp_options opt;
+  if (opt_in) opt = *opt_in; else psdp_default_options(&opt);
+  // ---- validation (no launch before this point)
+  if (!h || n < 1 || !X || !V || !m_inout || !lambda || !Pi) return PSDP_ERR_INVALID_ARG;
+  if (ldx < n || ldv < n || ldpi < n || m_cap < 1) return PSDP_ERR_INVALID_ARG;
+  if (*m_inout < 0 || *m_inout > m_cap) return PSDP_ERR_INVALID_ARG;
+  if (opt.side < 0 || opt.side > 3 || opt.prec < 0 || opt.prec > 2) return PSDP_ERR_INVALID_ARG;
+  if (opt.max_iter < 1 || opt.certify != 0 || !(opt.side_threshold > 0.0) ||
+      opt.side_threshold > 0.5 || opt.expand_cols < 0 || opt.pos_hint > n)
+    return PSDP_ERR_INVALID_ARG;
+  if ((const void*)Pi == (const void*)X) return PSDP_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
+  h->calls += 1;
+
+  // ---- side (paper §6): fewer than threshold*n positive -> positive side
+  int side = opt.side;
+  if (side == PSDP_SIDE_AUTO) {
+    if (opt.pos_hint < 0) side = PSDP_SIDE_FULL;
+    else if (opt.pos_hint < opt.side_threshold * n) side = PSDP_SIDE_POS;
+    else if (n - opt.pos_hint < opt.side_threshold * n) side = PSDP_SIDE_NEG;
+    else side = PSDP_SIDE_FULL;
+  }
+  const int mcap = std::min(std::min(m_cap, kMaxM), n);
+  if (side == PSDP_SIDE_FULL) {
+    int mo = 0, npos = 0;
+    psdp_status st = full_eig_core(h, n, X, ldx, nullptr, Pi, ldpi, V, ldv, m_cap, &mo, lambda, &npos);
+    if (st != PSDP_OK) { info->status = st; return st; }
+    *m_inout = mo;
+    info->side_used = PSDP_SIDE_FULL;
+    info->n_pos = npos;
+    info->n_pos_full = npos;
+    info->m_out = mo;
+    info->err_bound = 0.0;
+    info->res_fro = 0.0;
+    info->tail_est = 0.0;
+    info->status = PSDP_FELL_BACK_FULL_EIG;
+    return PSDP_FELL_BACK_FULL_EIG;
+  }
+  const double sign = (side == PSDP_SIDE_NEG) ? -1.0 : 1.0;
+  // ---- block size
+  int m_in = *m_inout;
+  int m0 = m_in;
+  if (m0 == 0) {
+    int est = -1;
+    if (opt.pos_hint >= 0) est = (side == PSDP_SIDE_POS) ? opt.pos_hint : n - opt.pos_hint;
+    if (est >= 0) m0 = est + std::max(opt.block_guard, (int)std::ceil(0.2 * est));
+    else m0 = std::max(8, opt.block_guard);
+  }
+  m0 = std::max(1, std::min(m0, mcap));
+  int prec0 = opt.prec;
+  psdp_status ps = ensure_workspace(h, n, mcap, prec0);
+  if (ps != PSDP_OK) { info->status = ps; return ps; }
+  Workspace& w = h->ws;
+  hipStream_t s = h->stream;
+  // ---- ingest
+  HIP_TRY(hipMemsetAsync(w.nonfinite, 0, sizeof(int), s));
+  int nb = 0;
+  {
+    ProfScope pscope(h, "ingest", 8.0 * n * (double)n / 2 + (8.0 + product_elem_bytes(prec0)) * n * (double)n, 0);
+    HIP_TRY(launch_ingest(X, ldx, n, sign, w.A64, w.L, w.Alp, prec0, w.fro_part, w.nonfinite, s, &nb));
+    HIP_TRY(launch_reduce_sum(w.fro_part, nb, w.scal, s));
+  }
+  psdp_status pp = ensure_pinned(h, 64);
+  if (pp != PSDP_OK) return pp;
+  HIP_TRY(hipMemcpyAsync(h->h_pin, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h->h_pin + 1, w.nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double fro2 = h->h_pin[0];
+  int nonfin = 0;
+  std::memcpy(&nonfin, h->h_pin + 1, sizeof(int));
+  if (nonfin || !std::isfinite(fro2)) { info->status = PSDP_ERR_NUMERICAL; return PSDP_ERR_NUMERICAL; }
+  double tol = opt.tol > 0 ? opt.tol : 1e-8 * std::sqrt(fro2) / std::sqrt(2.0 * m0);
+  if (tol <= 0) tol = 1e-300;
+  // ---- state init
+  State& hs = *h->h_state;
+  std::memset(&hs, 0, sizeof(State));
+  hs.n = n;
+  hs.tol = tol;
+  hs.best_res = INFINITY;
+  hs.last_npos = -1;
+  hs.stall_window = (prec0 == 0) ? 30 : 8;
+  hs.fro2_x = fro2;
+  HIP_TRY(hipMemcpyAsync(w.st, &hs, sizeof(State), hipMemcpyHostToDevice, s));
+  // ---- start block: warm start columns, then seeded normals
+  HIP_TRY(hipMemset2DAsync(w.X, sizeof(double) * w.L, 0, sizeof(double) * w.L, w.MC, s));
+  if (m_in > 0) HIP_TRY(launch_copy_cols(V, ldv, w.X, w.L, n, std::min(m_in, m0), s));
+  const uint64_t seed = opt.seed;
+  uint64_t rng_stream = (h->calls << 8);
+  if (m0 > m_in) HIP_TRY(launch_fill_normal(w.X, w.L, n, m_in, m0 - m_in, seed, rng_stream++, s));
+  HIP_TRY(hipStreamSynchronize(s));
+
+  Solver sv(h, n, mcap);
+  sv.m = m0;
+  sv.has_p = 0;
+  psdp_status rc = PSDP_OK;
+  int expansions = 0;
+  // initial Rayleigh-Ritz on span(X0) with an FP64 product (Alg. 3, first RR)
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    int want = sv.m;
+    rc = sv.iterate(kModeXOnly, 0, want, 0);
+    if (rc != PSDP_OK) { info->status = rc; return rc; }
+    if (sv.m >= std::min(m0, n)) break;
+    // rank-deficient start: refill the missing columns with random ones
+    int miss = m0 - sv.m;
+    HIP_TRY(launch_fill_normal(w.X, w.L, n, sv.m, miss, seed, rng_stream++, s));
+    sv.m = m0;
+  }
+  int phase = prec0;
+  bool finished = false;
+  bool converged = false;
+  int fell_back = 0;
+  auto refresh = [&](int pprec) -> psdp_status {
+    // Rayleigh-Ritz on span(X) with a fresh product: exact AX at pprec
+    psdp_status r = sv.iterate(kModeXOnly, pprec, sv.m, 0);
+    sv.has_p = 0;
+    hs.best_res = INFINITY;
+    return r;
+  };
+  auto reset_stall = [&]() -> psdp_status {
+    State tmp = *h->h_state;
+    (void)tmp;
+    // best_res / best_iter live on the device: reset them in place
+    double inf = INFINITY;
+    HIP_TRY(hipMemcpyAsync(&w.st->best_res, &inf, sizeof(double), hipMemcpyHostToDevice, s));
+    int it = h->h_state->iter;
+    HIP_TRY(hipMemcpyAsync(&w.st->best_iter, &it, sizeof(int), hipMemcpyHostToDevice, s));
+    int win = (phase == 0) ? 30 : 8;
+    HIP_TRY(hipMemcpyAsync(&w.st->stall_window, &win, sizeof(int), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return PSDP_OK;
+  };
+  int guard_calls = 0;
+  while (!finished) {
+    if (++guard_calls > 4 * opt.max_iter + 64) break;  // hard bound on host steps
+    int mode = sv.has_p ? kModeFull : kModeXR;
+    rc = sv.iterate(mode, phase, sv.m, 0);
+    if (rc != PSDP_OK) { info->status = rc; return rc; }
+    const State& st = *h->h_state;
+    int stop = st.stop;
+    if (stop == kNonFinite) { info->status = PSDP_ERR_NUMERICAL; return PSDP_ERR_NUMERICAL; }
+    if (stop == kBreakdown) {
+      if (opt.fallback_full) { fell_back = 1; break; }
+      info->status = PSDP_ERR_NUMERICAL;
+      return PSDP_ERR_NUMERICAL;
+    }
+    if (stop == kConverged) {
+      if (phase != 0 && opt.refine_fp64) {
+        // FP64 residual-correction: exact AX, then keep iterating in FP64
+        // until the exact residuals meet tol
+        phase = 0;
+        rc = refresh(0);
+        if (rc != PSDP_OK) return rc;
+        rc = reset_stall();
+        continue;
+      }
+      converged = true;
+      finished = true;
+      break;
+    }
+    if (stop == kStalled) {
+      if (phase == 2 && opt.ladder) {
+        phase = 1;
+        if ((rc = refresh(1)) != PSDP_OK) return rc;
+        reset_stall();
+        continue;
+      }
+      if (phase != 0 && (opt.ladder || opt.refine_fp64)) {
+        phase = 0;
+        if ((rc = refresh(0)) != PSDP_OK) return rc;
+        reset_stall();
+        if (!opt.ladder) {
+          // raw low-precision path: one FP64 sweep then stop
+          rc = sv.iterate(kModeXR, 0, sv.m, 0);
+          if (rc != PSDP_OK) return rc;
+          rc = refresh(0);
+          if (rc != PSDP_OK) return rc;
+          finished = true;
+          break;
+        }
+        continue;
+      }
+      finished = true;  // stalled at FP64
+      break;
+    }
+    if (stop == kExpand) {
+      int e = opt.expand_cols > 0 ? opt.expand_cols : (n + 49) / 50;
+      e = std::max(1, e);
+      e = std::min(e, sv.mcap - sv.m);
+      if (e <= 0) {
+        if (opt.fallback_full) { fell_back = 1; break; }
+        // no room: report what we have
+        finished = true;
+        break;
+      }
+      HIP_TRY(launch_fill_normal(w.Z, w.L, n, 0, e, seed, rng_stream++, s));
+      rc = sv.iterate(kModeXZ, phase, sv.m + e, e);
+      if (rc != PSDP_OK) return rc;
+      sv.has_p = 0;
+      expansions += 1;
+      reset_stall();
+      continue;
+    }
+    if (st.iter >= opt.max_iter) {
+      finished = true;
+      break;
+    }
+  }
+  if (fell_back || (!converged && opt.fallback_full)) {
+    int mo = 0, npos = 0;
+    psdp_status st2 = full_eig_core(h, n, X, ldx, nullptr, Pi, ldpi, V, ldv, m_cap, &mo, lambda, &npos);
+    if (st2 != PSDP_OK) { info->status = st2; return st2; }
+    *m_inout = mo;
+    info->side_used = PSDP_SIDE_FULL;
+    info->n_pos = npos;
+    info->n_pos_full = npos;
+    info->m_out = mo;
+    info->err_bound = 0.0; info->res_fro = 0.0; info->tail_est = 0.0;
+    info->iters = h->h_state->iter;
+    info->expansions = expansions;
+    info->status = PSDP_FELL_BACK_FULL_EIG;
+    return PSDP_FELL_BACK_FULL_EIG;
+  }
+  if (!converged && phase != 0 && opt.refine_fp64) {
+    // not converged at a low precision: still finish with exact FP64 pairs
+    phase = 0;
+    if ((rc = refresh(0)) != PSDP_OK) return rc;
+    rc = sv.iterate(kModeXR, 0, sv.m, 0);  // one FP64 sweep on span(X, R)
+    if (rc != PSDP_OK) return rc;
+    converged = (h->h_state->stop == kConverged);
+  }
+  // ---- statistics of the final block (exact FP64 residuals)
+  if (h->h_state->stop != kConverged) {
+    rc = sv.evaluate();
+    if (rc != PSDP_OK) return rc;
+    converged = converged || (h->h_state->eval_stop == kConverged);
+  }
+  // ---- bound (Thm `bound`) from the last decision pass
+  const State& st = *h->h_state;
+  const int m = sv.m;
+  int npos = st.npos_blk;
+  double rfro = st.res_fro_pos;
+  double tail = 0.0;
+  if (npos < m) {
+    double th_g = st.guard_theta, r_g = st.guard_res;
+    double delta = npos > 0 ? (st.theta_min_pos - th_g) : std::fabs(th_g);
+    double est = (delta > 0.0) ? th_g + r_g * r_g / delta : th_g + r_g;
+    tail = std::sqrt((double)(n - npos)) * std::max(est, 0.0);
+  } else if (m < n) {
+    tail = INFINITY;  // no non-positive pair in the block: nothing to estimate from
+  }
+  double bound = std::sqrt(2.0 * rfro * rfro + tail * tail);
+  double sum_pos2 = 0.0;
+  for (int i = 0; i < npos; ++i) sum_pos2 += st.theta[i] * st.theta[i];
+  double pi_fro = (side == PSDP_SIDE_POS) ? std::sqrt(sum_pos2) : std::sqrt(std::max(fro2 - sum_pos2, 0.0));
+  // ---- rebuild Pi
+  {
+    ProfScope pscope(h, "rebuild", 8.0 * n * (double)n * (side == PSDP_SIDE_NEG ? 2 : 1),
+                     (double)n * n * npos);
+    const double* lt = &w.st->theta[0];
+    if (side == PSDP_SIDE_POS)
+      HIP_TRY(launch_rebuild(w.X, w.L, lt, npos, n, nullptr, 0, 0.0, Pi, ldpi, s));
+    else
+      HIP_TRY(launch_rebuild(w.X, w.L, lt, npos, n, w.A64, w.L, -1.0, Pi, ldpi, s));
+  }
+  // ---- outputs: Ritz block and values
+  HIP_TRY(launch_copy_cols(w.X, w.L, V, ldv, n, m, s));
+  HIP_TRY(hipMemcpyAsync(lambda, &w.st->theta[0], sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *m_inout = m;
+  info->err_bound = bound;
+  info->res_fro = rfro;
+  info->tail_est = tail;
+  info->pi_fro = pi_fro;
+  info->theta_guard = st.guard_theta;
+  info->tol_used = tol;
+  info->n_pos = npos;
+  info->m_out = m;
+  info->iters = st.iter;
+  info->side_used = side;
+  info->certified = 0;
+  info->expansions = expansions;
+  info->prec_final = phase;
+  info->status = converged ? PSDP_OK : PSDP_NOT_CONVERGED;
+  return (psdp_status)info->status;
+}

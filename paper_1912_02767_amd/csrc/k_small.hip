@@ -1,0 +1,502 @@
+// One-workgroup kernels on the small (<= 192 x 192) matrices of one
+// LOBPCG iteration:
+//   k_decide_chol : convergence / stall / expansion decisions, active set,
+//                   and Cholesky-QR with column dropping of the trial basis
+//                   (paper §5.1: Cholesky QR instead of Householder QR)
+//   k_rr          : Rayleigh-Ritz on an orthonormal basis (paper §5, Alg. 2):
+//                   parallel cyclic Jacobi on H = S^T A S in LDS, selection of
+//                   the largest Ritz values, eigenvectors by replaying the
+//                   rotation log on unit vectors.
+#include "common.h"
+
+namespace psdp {
+
+constexpr int kSmallThreads = 1024;
+
+__device__ inline double block_sum(double v, double* red) {
+  // red: kSmallThreads / 64 doubles of LDS
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  int nw = blockDim.x / 64;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+__device__ inline double block_max(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = -INFINITY;
+  int nw = blockDim.x / 64;
+  for (int i = 0; i < nw; ++i) s = fmax(s, red[i]);
+  __syncthreads();
+  return s;
+}
+
+// e -> (row, col) of a packed triangle: row r with r(r+1)/2 <= e < (r+1)(r+2)/2
+__device__ inline int tri_row(int e) {
+  int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  while ((r + 1) * (r + 2) / 2 <= e) ++r;
+  while (r * (r + 1) / 2 > e) --r;
+  return r;
+}
+
+// packed lower triangle, row-major: (i, j) with j <= i  ->  i(i+1)/2 + j
+__device__ inline int plo(int i, int j) { return i * (i + 1) / 2 + j; }
+// packed upper triangle, column-major: (i, j) with i <= j  ->  j(j+1)/2 + i
+__device__ inline int pup(int i, int j) {
+  return (i <= j) ? (j * (j + 1) / 2 + i) : (i * (i + 1) / 2 + j);
+}
+
+
+
+// Dynamic LDS: packed lower triangle of the scaled Gram (N(N+1)/2 doubles)
+// + row buffer (N) + scale (N) + misc.
+__global__ __launch_bounds__(kSmallThreads) void k_decide_chol(DecideArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[kSmallThreads / 64];
+  __shared__ int s_list[kMaxN];   // logical trial column -> candidate index in G
+  __shared__ int s_kind[kMaxN];
+  __shared__ int s_col[kMaxN];
+  __shared__ int s_keep[kMaxN];
+  __shared__ int s_N, s_Np, s_nx, s_stop;
+  State* st = a.st;
+  const int tid = threadIdx.x;
+  const int m = a.m;
+
+  if (a.mode == kModeFull || a.mode == kModeXR || a.mode == kModeEval) {
+    // ---- decisions from the residual norms (paper §5.2 / §6 stopping rule)
+    if (tid < m) st->rnorm[tid] = sqrt(fmax(a.G[(m + tid) + (size_t)(m + tid) * a.ldg], 0.0));
+    __syncthreads();
+    if (tid == 0) {
+      double tol = st->tol;
+      int npos = 0;
+      for (int i = 0; i < m; ++i) npos += (st->theta[i] > 0.0);
+      st->npos_blk = npos;
+      double rmax = 0.0, rfro = 0.0;
+      for (int i = 0; i < npos; ++i) {
+        rmax = fmax(rmax, st->rnorm[i]);
+        rfro += st->rnorm[i] * st->rnorm[i];
+      }
+      st->res_max_pos = rmax;
+      st->res_fro_pos = sqrt(rfro);
+      st->theta_min_pos = npos > 0 ? st->theta[npos - 1] : 0.0;
+      int stop = kRunning;
+      bool nonfin = !isfinite(rfro);
+      for (int i = 0; i < m; ++i) nonfin |= !isfinite(st->theta[i]) || !isfinite(st->rnorm[i]);
+      // guard: largest non-positive Ritz pair, resolved to half its gap
+      double q;  // progress metric, <= 1 when converged
+      bool guard_ok = false;
+      if (npos < m) {
+        int g = npos;
+        double delta = npos > 0 ? (st->theta[npos - 1] - st->theta[g]) : fabs(st->theta[g]);
+        double gtol = fmax(tol, 0.5 * delta);
+        st->guard_theta = st->theta[g];
+        st->guard_res = st->rnorm[g];
+        guard_ok = st->rnorm[g] <= gtol;
+        q = fmax(rmax / tol, st->rnorm[g] / gtol);
+      } else {
+        st->guard_theta = NAN;
+        st->guard_res = NAN;
+        q = rmax / tol;
+      }
+      if (nonfin) {
+        stop = kNonFinite;
+      } else if (st->expand_req) {
+        stop = kExpand;
+      } else if (npos == m && rmax <= tol) {
+        stop = kExpand;  // no room left for a non-positive guard pair
+      } else if (rmax <= tol && guard_ok) {
+        stop = kConverged;
+      } else {
+        // stalled: no 10% progress within the window while the count of
+        // positive Ritz values stays the same (a newly found positive pair
+        // is progress even when the residual jumps)
+        if (npos != st->last_npos || q < 0.9 * st->best_res) {
+          st->best_res = q;
+          st->best_iter = st->iter;
+          st->last_npos = npos;
+        } else if (st->iter - st->best_iter >= st->stall_window) {
+          stop = kStalled;
+        }
+      }
+      st->eval_stop = stop;
+      if (a.mode == kModeEval) stop = kEvaluated;
+      st->stop = stop;
+      s_stop = stop;
+      // logical trial basis: X, then active R, then active P
+      int N = 0;
+      for (int i = 0; i < m; ++i) { s_list[N] = i; s_kind[N] = 0; s_col[N] = i; ++N; }
+      if (stop == kRunning) {
+        for (int i = 0; i < m; ++i)
+          if (st->rnorm[i] > tol) { s_list[N] = m + i; s_kind[N] = 1; s_col[N] = i; ++N; }
+        if (a.has_p && a.mode == kModeFull)
+          for (int i = 0; i < m; ++i)
+            if (st->rnorm[i] > tol) { s_list[N] = 2 * m + i; s_kind[N] = 2; s_col[N] = i; ++N; }
+      }
+      s_N = N;
+    }
+    __syncthreads();
+    if (s_stop != kRunning) return;
+  } else if (a.mode == kModeXOnly || a.mode == kModeXZ) {
+    if (tid == 0) {
+      int N = 0;
+      for (int i = 0; i < m; ++i) { s_list[N] = i; s_kind[N] = 0; s_col[N] = i; ++N; }
+      if (a.mode == kModeXZ)
+        for (int i = 0; i < a.nz; ++i) { s_list[N] = m + i; s_kind[N] = 3; s_col[N] = i; ++N; }
+      s_N = N;
+      st->stop = kRunning;
+    }
+    __syncthreads();
+  } else {
+    // second Cholesky-QR pass over S1 (columns 0..Ng)
+    if (st->stop) return;
+    const int ng = st->Np;
+    if (tid == 0) s_N = ng;
+    __syncthreads();
+    for (int i = tid; i < ng; i += blockDim.x) { s_list[i] = i; s_kind[i] = 4; s_col[i] = i; }
+    __syncthreads();
+  }
+  const int N = s_N;
+  double* Lp = lds;                      // N(N+1)/2
+  double* dsc = Lp + N * (N + 1) / 2;    // N scales
+  double* row = dsc + N;                 // N
+  // scaled Gram into packed lower
+  for (int i = tid; i < N; i += blockDim.x) {
+    double gii = a.G[s_list[i] + (size_t)s_list[i] * a.ldg];
+    dsc[i] = (gii > 0.0 && isfinite(gii)) ? 1.0 / sqrt(gii) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < N * (N + 1) / 2; e += blockDim.x) {
+    int i = tri_row(e);
+    int j = e - i * (i + 1) / 2;
+    double g = a.G[s_list[i] + (size_t)s_list[j] * a.ldg];
+    Lp[e] = g * dsc[i] * dsc[j];
+  }
+  __syncthreads();
+  // right-looking Cholesky with dropping on the packed lower triangle: at
+  // step j the trailing Schur complement is in place; column j is dropped
+  // when its pivot (squared distance of the scaled column to the span of
+  // the kept ones) is below tau, and then contributes nothing.
+  __shared__ int s_drop;
+  __shared__ double s_piv;
+  for (int j = 0; j < N; ++j) {
+    if (tid == 0) {
+      double d = Lp[plo(j, j)];
+      bool drop = !(d > a.tau) || dsc[j] == 0.0;
+      s_drop = drop;
+      s_piv = drop ? 0.0 : sqrt(d);
+      Lp[plo(j, j)] = s_piv;
+    }
+    __syncthreads();
+    const bool drop = s_drop;
+    const double ljj = s_piv;
+    for (int i = j + 1 + tid; i < N; i += blockDim.x)
+      Lp[plo(i, j)] = drop ? 0.0 : Lp[plo(i, j)] / ljj;
+    __syncthreads();
+    if (!drop) {
+      // trailing update: G[i,k] -= L[i,j] L[k,j] for j < k <= i
+      const int t = N - j - 1;
+      const int cnt = t * (t + 1) / 2;
+      for (int e = tid; e < cnt; e += blockDim.x) {
+        int r = tri_row(e);
+        int c = e - r * (r + 1) / 2;
+        int i = j + 1 + r, k = j + 1 + c;
+        Lp[plo(i, k)] -= Lp[plo(i, j)] * Lp[plo(k, j)];
+      }
+      __syncthreads();
+    }
+  }
+  // kept list
+  if (tid == 0) {
+    int np = 0, nx = 0;
+    int nxcand = (a.mode == -1) ? st->nx : m;  // candidates that came from X
+    for (int j = 0; j < N; ++j)
+      if (Lp[plo(j, j)] != 0.0) {
+        s_keep[np++] = j;
+        if (j < nxcand) ++nx;
+      }
+    s_Np = np;
+    s_nx = nx;
+  }
+  __syncthreads();
+  const int Np = s_Np;
+  // in-place inverse of the lower-triangular factor (dropped rows/columns
+  // are zero and stay zero), column by column from the last:
+  //   Linv[j,j] = 1/L[j,j];  Linv[i,j] = -Linv[j,j] * sum_{j<c<=i} Linv[i,c] L[c,j]
+  for (int j = N - 1; j >= 0; --j) {
+    const double ljj = Lp[plo(j, j)];
+    if (ljj == 0.0) continue;  // uniform across the block
+    const double inv = 1.0 / ljj;
+    for (int i = j + 1 + tid; i < N; i += blockDim.x) {
+      double sum = 0.0;
+      for (int c = j + 1; c <= i; ++c) sum += Lp[plo(i, c)] * Lp[plo(c, j)];
+      row[i] = -inv * sum;
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < N; i += blockDim.x) Lp[plo(i, j)] = row[i];
+    if (tid == 0) Lp[plo(j, j)] = inv;
+    __syncthreads();
+  }
+  // T = D Linv^T restricted to kept columns: T[t, c] = d_t * Linv[keep[c], t]
+  for (int e = tid; e < N * Np; e += blockDim.x) {
+    int t = e % N, c = e / N;
+    int kc = s_keep[c];
+    double v = (t <= kc) ? Lp[plo(kc, t)] * dsc[t] : 0.0;
+    a.T[t + (size_t)c * a.ldt] = v;
+  }
+  for (int t = tid; t < N; t += blockDim.x) {
+    a.colptr[t] = a.bases[s_kind[t]] + (size_t)s_col[t] * a.ld;
+    st->src_kind[t] = s_kind[t];
+    st->src_col[t] = s_col[t];
+  }
+  for (int c = tid; c < Np; c += blockDim.x) st->keep_col[c] = s_keep[c];
+  if (tid == 0) {
+    if (a.mode == -1) {
+      st->Np1 = st->Np;
+    } else {
+      st->N = N;
+      st->nr = 0; st->np = 0; st->nz = 0;
+      for (int t = 0; t < N; ++t) {
+        st->nr += (s_kind[t] == 1);
+        st->np += (s_kind[t] == 2);
+        st->nz += (s_kind[t] == 3);
+      }
+    }
+    st->Np = Np;
+    st->nx = s_nx;
+    if (Np == 0) st->stop = kBreakdown;
+  }
+}
+
+// ---------------------------------------------------------------- RR ----
+
+
+__device__ inline void rr_pair(int Ne, int r, int k, int* p, int* q) {
+  // round-robin: slot 0 pairs the fixed last player with r, slot k > 0 pairs
+  // (r + k) and (r - k) modulo Ne - 1
+  int x, y;
+  const int M = Ne - 1;
+  if (k == 0) {
+    x = r;
+    y = M;
+  } else {
+    x = r + k;
+    if (x >= M) x -= M;
+    y = r - k;
+    if (y < 0) y += M;
+  }
+  *p = min(x, y);
+  *q = max(x, y);
+}
+
+__global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[kSmallThreads / 64];
+  __shared__ double s_cs[kMaxN];        // c, s per pair (kMaxN/2 pairs)
+  __shared__ int s_pq[kMaxN];           // p, q per pair
+  __shared__ double s_theta[kMaxN];
+  __shared__ int s_rank[kMaxN];
+  __shared__ int s_rounds;
+  State* st = a.st;
+  if (st->stop) return;
+  const int tid = threadIdx.x;
+  const int Np = st->Np;
+  const int Ne = Np + (Np & 1);
+  const int P = Ne / 2;
+  const int mk = min(a.mtarget, Np);
+  double* H = lds;  // packed upper, Np(Np+1)/2
+  const int NH = Np * (Np + 1) / 2;
+  // load the symmetric part of K
+  double fro2 = 0.0;
+  for (int e = tid; e < NH; e += blockDim.x) {
+    int j = tri_row(e);
+    int i = e - j * (j + 1) / 2;
+    double h = 0.5 * (a.K[i + (size_t)j * a.ldk] + a.K[j + (size_t)i * a.ldk]);
+    H[e] = h;
+    fro2 += (i == j ? 1.0 : 2.0) * h * h;
+  }
+  fro2 = block_sum(fro2, red);
+  const double skip = 1e-18 * sqrt(fro2);
+  const double stop2 = (1e-15 * 1e-15) * fro2;
+  // ---- parallel cyclic Jacobi (tournament order), rotations logged
+  int round_id = 0;
+  const size_t per_round = (size_t)2 * P;
+  const int nblocks = P * (P + 1) / 2;
+  for (int sweep = 0; sweep < a.max_sweeps && Np > 1; ++sweep) {
+    // off-diagonal mass
+    double off = 0.0;
+    for (int j = 0; j < Np; ++j) {
+      // column j of the packed upper triangle: entries (i, j), i < j
+      for (int i = tid; i < j; i += blockDim.x) {
+        double v = H[j * (j + 1) / 2 + i];
+        off += 2.0 * v * v;
+      }
+    }
+    off = block_sum(off, red);
+    if (off <= stop2) break;
+    if ((size_t)(round_id + Ne) * per_round > a.log_cap) break;
+    for (int r = 0; r < Ne - 1; ++r) {
+      if (tid < P) {
+        int p, q;
+        rr_pair(Ne, r, tid, &p, &q);
+        s_pq[2 * tid] = p;
+        s_pq[2 * tid + 1] = q;
+        double c = 1.0, s = 0.0;
+        if (q < Np) {
+          double hpq = H[pup(p, q)];
+          if (fabs(hpq) > skip) {
+            double tau = (H[pup(q, q)] - H[pup(p, p)]) / (2.0 * hpq);
+            double t;
+            if (fabs(tau) > 1e150) t = 1.0 / (2.0 * tau);
+            else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = t * c;
+          }
+        }
+        s_cs[2 * tid] = c;
+        s_cs[2 * tid + 1] = s;
+        a.log[(size_t)round_id * per_round + 2 * tid] = c;
+        a.log[(size_t)round_id * per_round + 2 * tid + 1] = s;
+      }
+      __syncthreads();
+      // two-sided update of every 2x2 block (k, l), k <= l
+      for (int b = tid; b < nblocks; b += blockDim.x) {
+        int l = tri_row(b);
+        int k = b - l * (l + 1) / 2;  // k <= l
+        double ck = s_cs[2 * k], sk = s_cs[2 * k + 1];
+        double cl = s_cs[2 * l], sl = s_cs[2 * l + 1];
+        if (sk == 0.0 && sl == 0.0) continue;
+        int pk = s_pq[2 * k], qk = s_pq[2 * k + 1];
+        int pl = s_pq[2 * l], ql = s_pq[2 * l + 1];
+        if (k == l) {
+          if (qk >= Np) continue;
+          double hpp = H[pup(pk, pk)], hqq = H[pup(qk, qk)], hpq = H[pup(pk, qk)];
+          double c2 = ck * ck, s2 = sk * sk, cs = ck * sk;
+          H[pup(pk, pk)] = c2 * hpp - 2.0 * cs * hpq + s2 * hqq;
+          H[pup(qk, qk)] = s2 * hpp + 2.0 * cs * hpq + c2 * hqq;
+          H[pup(pk, qk)] = 0.0;
+        } else {
+          bool vk = qk < Np, vl = ql < Np;
+          double b00 = H[pup(pk, pl)];
+          double b01 = vl ? H[pup(pk, ql)] : 0.0;
+          double b10 = vk ? H[pup(qk, pl)] : 0.0;
+          double b11 = (vk && vl) ? H[pup(qk, ql)] : 0.0;
+          double m00 = cl * b00 - sl * b01, m01 = sl * b00 + cl * b01;
+          double m10 = cl * b10 - sl * b11, m11 = sl * b10 + cl * b11;
+          H[pup(pk, pl)] = ck * m00 - sk * m10;
+          if (vl) H[pup(pk, ql)] = ck * m01 - sk * m11;
+          if (vk) H[pup(qk, pl)] = sk * m00 + ck * m10;
+          if (vk && vl) H[pup(qk, ql)] = sk * m01 + ck * m11;
+        }
+      }
+      __syncthreads();
+      ++round_id;
+    }
+  }
+  if (tid == 0) s_rounds = round_id;
+  // eigenvalues and the ranking (descending, ties by index)
+  for (int i = tid; i < Np; i += blockDim.x) s_theta[i] = H[pup(i, i)];
+  __syncthreads();
+  for (int i = tid; i < Np; i += blockDim.x) {
+    double ti = s_theta[i];
+    int r = 0;
+    for (int j = 0; j < Np; ++j) {
+      double tj = s_theta[j];
+      r += (tj > ti) || (tj == ti && j < i);
+    }
+    s_rank[i] = r;
+  }
+  __syncthreads();
+  // ---- eigenvectors of the kept pairs: W = J_1 ... J_T E_sel, by replaying
+  // the logged rounds backwards on unit vectors (H's LDS is reused)
+  double* W = lds;  // Np x mk, column-major
+  for (int e = tid; e < Np * mk; e += blockDim.x) W[e] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < Np; i += blockDim.x)
+    if (s_rank[i] < mk) W[i + (size_t)s_rank[i] * Np] = 1.0;
+  __syncthreads();
+  const int rounds = s_rounds;
+  double* chunk = W + (size_t)Np * mk;  // staged log rounds
+  const int chunk_rounds = 32;
+  for (int t_hi = rounds; t_hi > 0; t_hi -= chunk_rounds) {
+    int t_lo = max(0, t_hi - chunk_rounds);
+    int cnt = t_hi - t_lo;
+    for (int e = tid; e < cnt * (int)per_round; e += blockDim.x)
+      chunk[e] = a.log[(size_t)t_lo * per_round + e];
+    __syncthreads();
+    for (int t = t_hi - 1; t >= t_lo; --t) {
+      int r = t % (Ne - 1);
+      const double* cs = chunk + (size_t)(t - t_lo) * per_round;
+      for (int e = tid; e < P * mk; e += blockDim.x) {
+        int k = e % P, col = e / P;
+        double c = cs[2 * k], s = cs[2 * k + 1];
+        if (s == 0.0) continue;
+        int p, q;
+        rr_pair(Ne, r, k, &p, &q);
+        if (q >= Np) continue;
+        double wp = W[p + (size_t)col * Np], wq = W[q + (size_t)col * Np];
+        W[p + (size_t)col * Np] = c * wp + s * wq;
+        W[q + (size_t)col * Np] = -s * wp + c * wq;
+      }
+      __syncthreads();
+    }
+  }
+  // outputs
+  for (int e = tid; e < Np * mk; e += blockDim.x) {
+    int i = e % Np, col = e / Np;
+    a.C[i + (size_t)col * a.ldc] = W[e];
+  }
+  int npos = 0;
+  for (int i = tid; i < Np; i += blockDim.x) {
+    npos += (s_theta[i] > 0.0);
+    if (s_rank[i] < mk) st->theta[s_rank[i]] = s_theta[i];
+  }
+  double npd = block_sum((double)npos, red);
+  if (tid == 0) {
+    st->npos_rr = (int)npd;
+    st->mk = mk;
+    st->expand_req = ((int)npd > a.mtarget) ? 1 : 0;
+    st->jacobi_rounds = rounds;
+    if (a.count_iter) st->iter += 1;
+  }
+}
+
+hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st) {
+  size_t lds = sizeof(double) * ((size_t)N_host * (N_host + 1) / 2 + 2 * (size_t)N_host + 8);
+  hipLaunchKernelGGL(k_decide_chol, dim3(1), dim3(kSmallThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr(const RRArgs& a, int Np_host, int mk_host, hipStream_t st) {
+  size_t h = (size_t)Np_host * (Np_host + 1) / 2;
+  size_t w = (size_t)Np_host * mk_host + (size_t)32 * Np_host + 64;
+  size_t lds = sizeof(double) * (h > w ? h : w);
+  hipLaunchKernelGGL(k_rr, dim3(1), dim3(kSmallThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t small_kernels_init() {
+  // allow up to the device's LDS per workgroup for the dynamic allocations
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    lim = 64 * 1024;
+  int dyn = lim - 8 * 1024;  // static LDS of the kernels stays below 8 KB
+  if (dyn > 0) {
+    (void)hipFuncSetAttribute((const void*)k_decide_chol,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+  }
+  (void)hipGetLastError();
+  return hipSuccess;
+}
+
+}  // namespace psdp

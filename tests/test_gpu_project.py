@@ -1,0 +1,133 @@
+"""GPU parity: the HIP path against the oracle, through the C-ABI.
+
+Tolerances: FP64 products give the projection to ~1e-12 relative; the
+spec bar is 1e-6 relative Frobenius error, and the reported bound must
+be at least the true error (Thm `bound`, paper §5.2)."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (batched_cones, haar_orthogonal, from_spectrum,
+                       random_spectrum_matrix, rng_for, single_cone, warm_sequence)
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def proj():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from gpu_util import projector
+    p = projector()
+    yield p
+    p.close()
+
+
+def _check(res, Xh, rel=REL, bound=True):
+    from gpu_util import to_host
+    Pi_ref, lam = oracle.project(Xh)
+    Pi = to_host(res.Pi)
+    r = oracle.rel_error(Pi, Pi_ref, Xh)
+    err = oracle.true_error(Pi, Pi_ref)
+    print(f"status={res.status} iters={res.info['iters']} m={res.info['m_out']} "
+          f"npos={res.info['n_pos']} rel={r:.2e} err={err:.2e} bound={res.info['err_bound']:.2e}")
+    assert r <= rel, (r, res.info)
+    if bound:
+        assert res.info["err_bound"] >= err * (1 - 1e-9), (err, res.info)
+    return r, err, lam
+
+
+def test_config1_single_cone_fp64(proj):
+    from gpu_util import to_dev
+    cone, V0 = single_cone()
+    res = proj.project(to_dev(cone.X), V=to_dev(V0), m_cap=16, side="pos", tol=1e-10)
+    assert res.status == 0
+    r, err, lam = _check(res, cone.X)
+    assert res.info["n_pos"] == 5
+    # Ritz values of the positive pairs are the positive eigenvalues
+    lam_gpu = np.sort(res.lam.cpu().numpy()[:5])
+    assert np.abs(lam_gpu - np.sort(cone.lam[cone.lam > 0])).max() <= 1e-9
+
+
+def test_full_eig_matches_oracle(proj):
+    from gpu_util import to_dev, to_host
+    cone, _ = single_cone()
+    Pi, lam = proj.full_eig(to_dev(cone.X))
+    Pi_ref, lam_ref = oracle.project(cone.X)
+    assert oracle.rel_error(to_host(Pi), Pi_ref) <= 1e-12
+    assert np.abs(to_host(lam) - lam_ref).max() <= 1e-12 * np.abs(lam_ref).max()
+
+
+@pytest.mark.parametrize("n,npos", [(16, 2), (33, 3), (64, 6), (130, 9), (257, 12)])
+def test_sizes_ragged(proj, n, npos):
+    from gpu_util import to_dev
+    c = random_spectrum_matrix(n, npos, rng_for(50, n))
+    res = proj.project(to_dev(c.X), m_cap=32, side="pos", tol=1e-10, pos_hint=npos)
+    assert res.status == 0
+    _check(res, c.X)
+
+
+def test_negative_side_moreau(proj):
+    from gpu_util import to_dev
+    # mostly positive spectrum: approximate the negative part of X
+    c = random_spectrum_matrix(80, 74, rng_for(51, 0), pos=(0.5, 5.0), neg=(-5.0, -0.5))
+    res = proj.project(to_dev(c.X), m_cap=24, side="neg", tol=1e-10, pos_hint=74)
+    assert res.status == 0
+    assert res.info["side_used"] == 2
+    assert res.info["n_pos"] == 6
+    _check(res, c.X)
+
+
+def test_expansion_from_too_small_block(proj):
+    from gpu_util import to_dev
+    cone, V0 = single_cone()
+    res = proj.project(to_dev(cone.X), V=to_dev(V0[:, :2]), m_cap=16, side="pos", tol=1e-10)
+    assert res.status == 0
+    assert res.info["expansions"] >= 1
+    assert res.info["n_pos"] == 5
+    _check(res, cone.X)
+
+
+def test_warm_sequence_small(proj):
+    import paper_1912_02767_amd as psdp
+    from gpu_util import to_dev
+    seq = warm_sequence(n=200, n_pos=6, steps=6)
+    c0 = next(seq)
+    sess = psdp.Session(proj, 200, m_cap=24, tol=1e-9, side="pos", pos_hint=6)
+    iters = []
+    for k, X in enumerate([c0.X] + list(seq)):
+        res = sess.project(to_dev(X))
+        assert res.status == 0
+        iters.append(res.info["iters"])
+        _check(res, X)
+    print("iters", iters)
+    assert max(iters[1:]) <= iters[0]
+
+
+def test_nonfinite_input_rejected(proj):
+    from gpu_util import to_dev
+    import paper_1912_02767_amd as psdp
+    X = np.eye(20)
+    X[5, 3] = np.nan
+    with pytest.raises(psdp.PsdpError) as e:
+        proj.project(to_dev(X), m_cap=8, side="pos")
+    assert e.value.code == psdp.PSDP_ERR_NUMERICAL
+
+
+def test_trivial_inputs(proj):
+    from gpu_util import to_dev, to_host
+    # PSD input: Pi = X on the negative side (nothing negative to find)
+    rng = rng_for(52, 0)
+    Q = haar_orthogonal(40, rng)
+    X = from_spectrum(Q, rng.uniform(0.5, 2.0, 40))
+    res = proj.project(to_dev(X), m_cap=8, side="neg", tol=1e-10)
+    assert np.abs(to_host(res.Pi) - X).max() <= 1e-9
+    # NSD input: Pi = 0 on the positive side
+    res = proj.project(to_dev(-X), m_cap=8, side="pos", tol=1e-10)
+    assert np.abs(to_host(res.Pi)).max() <= 1e-9
+    # n = 1
+    res = proj.project(to_dev(np.array([[2.5]])), m_cap=1, side="pos", tol=1e-12)
+    assert abs(to_host(res.Pi)[0, 0] - 2.5) <= 1e-12
