@@ -8,7 +8,7 @@
 namespace psdp {
 
 constexpr int kWave = 64;
-constexpr int kMaxM = 64;             // largest block (X columns) of the single-cone engine
+constexpr int kMaxM = 48;             // largest block (X columns) of the single-cone engine
 constexpr int kMaxN = 3 * kMaxM;      // largest trial basis [X, R, P]
 constexpr int kRowBlk = 256;          // rows per workgroup in the tall-skinny kernels
 constexpr int kGramRows = 128;        // rows per partial Gram block
@@ -70,6 +70,7 @@ struct State {
   int eval_stop;        // decision an evaluation pass would have taken
   int last_npos;        // positive count at the last progress check
   int pad1;
+  long long t_phase[8]; // device clock at phase boundaries of the last RR
   // per column data (block order = descending Ritz value)
   double theta[kMaxM];
   double rnorm[kMaxM];
@@ -193,11 +194,16 @@ struct RRArgs {
   size_t log_cap;    // doubles available
   int max_sweeps;
   int count_iter;    // 1: this RR is a LOBPCG iteration (increments st->iter)
+  double off_tol;    // Jacobi stops when off(H) <= off_tol * ||H||_F
+  size_t lds_cap;    // dynamic LDS doubles of the launch (set by launch_rr)
+  double* scratch;   // global scratch, >= 5 * Np * mk doubles (tridiagonal path)
   State* st;
 };
 
 hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st);
 hipError_t launch_rr(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
+hipError_t launch_rr_tri(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
+hipError_t rr_tri_init();
 hipError_t small_kernels_init();
 
 // ------------------------------------------------------------------ launch
@@ -220,7 +226,7 @@ struct ProductArgs {
 };
 
 hipError_t launch_ingest(const double* X, int ldx, int n, double sign, double* A64, int lda,
-                         void* Alp, int prec, double* fro_partial, int* nonfinite,
+                         int cols_alloc, void* Alp, int prec, double* fro_partial, int* nonfinite,
                          hipStream_t st, int* nblocks_out);
 hipError_t launch_reduce_sum(const double* partial, int count, double* out, hipStream_t st);
 hipError_t launch_product(const ProductArgs& a, hipStream_t st);

@@ -76,7 +76,7 @@ struct Workspace {
   void* Alp = nullptr;
   double *X = nullptr, *R = nullptr, *P = nullptr, *AX = nullptr, *Z = nullptr;
   double *S1 = nullptr, *S2 = nullptr, *AS = nullptr;
-  double *Gpart = nullptr, *G = nullptr, *T = nullptr, *C = nullptr;
+  double *Gpart = nullptr, *G = nullptr, *T = nullptr, *C = nullptr, *rrs = nullptr;
   double* log = nullptr;
   size_t log_cap = 0;
   const double** colptr = nullptr;
@@ -103,6 +103,7 @@ struct psdp_handle_s {
   double* h_pin = nullptr;  // pinned scratch for small readbacks
   size_t h_pin_cap = 0;
   unsigned long long calls = 0;
+  int rr_method = 0;  // 0: tridiagonal + bisection + inverse iteration, 1: Jacobi
   bool prof = false;
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<PendingEvent> pending;
@@ -206,6 +207,7 @@ psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
   size_t oG = take(sizeof(double) * (size_t)NC * NC);
   size_t oT = take(sizeof(double) * (size_t)NC * NC);
   size_t oC = take(sizeof(double) * (size_t)NC * NC);
+  size_t oRrs = take(sizeof(double) * 5 * (size_t)NC * MC);
   size_t oLog = take(sizeof(double) * log_cap);
   size_t oPtr = take(sizeof(double*) * (size_t)NC);
   size_t oFro = take(sizeof(double) * (size_t)fro_nblk);
@@ -239,6 +241,7 @@ psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
   w.G = (double*)(base + oG);
   w.T = (double*)(base + oT);
   w.C = (double*)(base + oC);
+  w.rrs = (double*)(base + oRrs);
   w.log = (double*)(base + oLog);
   w.log_cap = log_cap;
   w.colptr = (const double**)(base + oPtr);
@@ -286,9 +289,44 @@ struct Solver {
     return PSDP_OK;
   }
 
+  // Algorithmic bytes / flops of this iteration's launches, attributed once
+  // the device-side widths are known (after the state readback).
+  void attribute(size_t first, int Ng, int pprec) {
+    if (!h->prof) return;
+    const State& st = *hs;
+    const double nn = n, N = st.N > 0 ? st.N : Ng, N1 = st.Np1, N2 = st.Np, mk = st.mk;
+    int gram_i = 0, chol_i = 0, tsmm_i = 0;
+    for (size_t i = first; i < h->pending.size(); ++i) {
+      PendingEvent& p = h->pending[i];
+      if (p.family == "gram") {
+        double c = (gram_i == 0) ? Ng : (gram_i == 1 ? N1 : N2);
+        p.bytes = (gram_i == 2 ? 16.0 : 8.0) * nn * c;
+        p.flops = (gram_i == 2 ? 2.0 : 1.0) * nn * c * c;
+        ++gram_i;
+      } else if (p.family == "chol") {
+        double c = (chol_i == 0) ? N : N1;
+        p.flops = 2.0 * c * c * c / 3.0;  // Cholesky + triangular inverse
+        p.bytes = 16.0 * c * c;
+        ++chol_i;
+      } else if (p.family == "rr") {
+        p.flops = 9.0 * N2 * N2 * N2;     // dense symmetric eigendecomposition
+        p.bytes = 8.0 * N2 * N2 + 8.0 * N2 * mk;
+      } else if (p.family == "tsmm") {
+        if (tsmm_i == 0) { p.flops = 2 * nn * N * N1; p.bytes = 8 * nn * (N + N1); }
+        else if (tsmm_i == 1) { p.flops = 2 * nn * N1 * N2; p.bytes = 8 * nn * (N1 + N2); }
+        else { p.flops = 6 * nn * N2 * mk; p.bytes = 8 * nn * (2 * N2 + 4 * mk); }
+        ++tsmm_i;
+      } else if (p.family == "product") {
+        p.flops = 2.0 * nn * nn * N2;
+        p.bytes = (double)product_elem_bytes(pprec) * nn * nn + 16.0 * nn * N2;
+      }
+    }
+  }
+
   // one Rayleigh-Ritz iteration on the trial basis given by `mode`
   psdp_status iterate(int mode, int pprec, int mtarget, int nz) {
     const int L = w.L, NC = w.NC;
+    const size_t first_ev = h->pending.size();
     const int* stop = &w.st->stop;
     // ---- Gram of the candidate columns (gives residual norms too)
     ColMap cand;
@@ -371,10 +409,16 @@ struct Solver {
     ra.K = w.G; ra.ldk = NC; ra.mtarget = mtarget; ra.C = w.C; ra.ldc = NC;
     ra.log = w.log; ra.log_cap = w.log_cap; ra.max_sweeps = kMaxSweeps;
     ra.count_iter = (mode == kModeFull || mode == kModeXR) ? 1 : 0;
+    ra.off_tol = 1e-14;
+    ra.scratch = w.rrs;
     ra.st = w.st;
     {
       ProfScope ps(h, "rr");
-      HIP_TRY(launch_rr(ra, Nmax, std::min(mtarget, Nmax), s));
+      if (h->rr_method == 0) {
+        HIP_TRY(launch_rr_tri(ra, Nmax, std::min(mtarget, Nmax), s));
+      } else {
+        HIP_TRY(launch_rr(ra, Nmax, std::min(mtarget, Nmax), s));
+      }
     }
     // ---- update X, AX, P, R
     int want_p = (mode == kModeFull || mode == kModeXR) ? 1 : 0;
@@ -390,17 +434,21 @@ struct Solver {
       e.launches += 1;
       e.bytes += hs->Np;
       e.flops += hs->jacobi_rounds;
+      for (int ph = 0; ph < 4; ++ph) {
+        auto& q = h->prof_tab[std::string("rr_phase") + char('0' + ph)];
+        long long dt = hs->t_phase[ph + 1] - hs->t_phase[ph];
+        if (dt > 0 && dt < (1ll << 40)) { q.launches += 1; q.ms += dt * 1e-5; }  // 100 MHz clock
+      }
     }
-    if (h->prof) {
-      // attribute the algorithmic bytes/flops of this iteration's product
-      // now that its width is known
-      for (auto it = h->pending.rbegin(); it != h->pending.rend(); ++it)
-        if (it->family == "product") {
-          double k = (hs->stop == kRunning || mode == kModeXOnly || mode == kModeXZ) ? hs->Np : 0;
-          it->flops = 2.0 * n * (double)n * k;
-          it->bytes = (double)product_elem_bytes(pprec) * n * (double)n + 16.0 * n * k;
-          break;
-        }
+    if (hs->stop == kRunning || mode == kModeXOnly || mode == kModeXZ) {
+      attribute(first_ev, Ng, pprec);
+    } else if (h->prof) {
+      // stopped after the decision pass: only the first Gram and decision ran
+      for (size_t i = first_ev; i < h->pending.size(); ++i) {
+        PendingEvent& p = h->pending[i];
+        if (p.family == "gram" && p.bytes == 0) { p.bytes = 8.0 * n * Ng; p.flops = (double)n * Ng * Ng; }
+        if (p.family == "chol" && p.flops == 0) { p.flops = 2.0 * Ng * Ng * (double)Ng / 3.0; p.bytes = 16.0 * Ng * Ng; }
+      }
     }
     if (hs->stop == kRunning || mode == kModeXOnly || mode == kModeXZ) {
       if (hs->stop == kBreakdown) return PSDP_ERR_NUMERICAL;
@@ -481,7 +529,7 @@ psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t* bytes) {
   size_t nblk = (L + kGramRows - 1) / kGramRows;
   size_t T32 = (L + 31) / 32;
   size_t b = 8 * L * L + 4 * L * L + 5 * 8 * L * MC + 3 * 8 * L * NC + 8 * nblk * NC * NC +
-             3 * 8 * NC * NC + 8 * (size_t)kMaxSweeps * (NC + 1) * (NC + 2) + 8 * NC +
+             3 * 8 * NC * NC + 5 * 8 * NC * MC + 8 * (size_t)kMaxSweeps * (NC + 1) * (NC + 2) + 8 * NC +
              8 * T32 * (T32 + 1) / 2 + sizeof(State) + 4096;
   *bytes = b;
   return PSDP_OK;
@@ -498,7 +546,11 @@ psdp_status psdp_create(psdp_handle* out, int device, void* stream) {
   if (!h) return PSDP_ERR_OUT_OF_MEMORY;
   h->device = device;
   h->stream = (hipStream_t)stream;
-  if (small_kernels_init() != hipSuccess) { delete h; return PSDP_ERR_HIP; }
+  if (small_kernels_init() != hipSuccess || rr_tri_init() != hipSuccess) {
+    delete h;
+    return PSDP_ERR_HIP;
+  }
+  if (const char* m = std::getenv("PSDP_RR_METHOD")) h->rr_method = std::atoi(m) == 1 ? 1 : 0;
   if (hipHostMalloc((void**)&h->h_state, sizeof(State), hipHostMallocDefault) != hipSuccess) {
     delete h;
     return PSDP_ERR_OUT_OF_MEMORY;
@@ -565,22 +617,23 @@ static psdp_status full_eig_core(psdp_handle h, int n, const double* X, int ldx,
   int lda = round_up(n, 64);
   const int T32 = (lda + 31) / 32;
   const size_t fro_n = (size_t)T32 * (T32 + 1) / 2;
-  if (h->eig_cap < n) {
+  if (h->eig_cap < lda) {
     if (h->eig_A) hipFree(h->eig_A);
     h->eig_A = nullptr;
-    size_t b = sizeof(double) * ((size_t)lda * n + 2 * (size_t)n + 8 + fro_n + 8) + 64;
+    // the ingest writes the zero padding too: the copy is lda x lda
+    size_t b = sizeof(double) * ((size_t)lda * lda + 2 * (size_t)n + 8 + fro_n + 8) + 64;
     if (hipMalloc(&h->eig_A, b) != hipSuccess) { h->eig_cap = 0; return PSDP_ERR_OUT_OF_MEMORY; }
-    h->eig_cap = n;
+    h->eig_cap = lda;
   }
   double* A = h->eig_A;
-  double* d = A + (size_t)lda * n;
+  double* d = A + (size_t)lda * lda;
   double* e = d + n;
   rocblas_int* info = (rocblas_int*)(e + n);
   double* fro_part = e + n + 8;
   int* nonfin = (int*)(fro_part + fro_n);
   // symmetric copy (lower triangle of X) via the ingest kernel, FP64 only
   int nb = 0;
-  HIP_TRY(launch_ingest(X, ldx, n, 1.0, A, lda, nullptr, 0, fro_part, nonfin, s, &nb));
+  HIP_TRY(launch_ingest(X, ldx, n, 1.0, A, lda, lda, nullptr, 0, fro_part, nonfin, s, &nb));
   (void)nb;
   {
     ProfScope pscope(h, "fulleig");
@@ -707,7 +760,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   int nb = 0;
   {
     ProfScope pscope(h, "ingest", 8.0 * n * (double)n / 2 + (8.0 + product_elem_bytes(prec0)) * n * (double)n, 0);
-    HIP_TRY(launch_ingest(X, ldx, n, sign, w.A64, w.L, w.Alp, prec0, w.fro_part, w.nonfinite, s, &nb));
+    HIP_TRY(launch_ingest(X, ldx, n, sign, w.A64, w.L, w.L, w.Alp, prec0, w.fro_part, w.nonfinite, s, &nb));
     HIP_TRY(launch_reduce_sum(w.fro_part, nb, w.scal, s));
   }
   psdp_status pp = ensure_pinned(h, 64);

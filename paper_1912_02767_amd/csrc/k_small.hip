@@ -7,11 +7,15 @@
 //                   parallel cyclic Jacobi on H = S^T A S in LDS, selection of
 //                   the largest Ritz values, eigenvectors by replaying the
 //                   rotation log on unit vectors.
+#include <algorithm>
+
 #include "common.h"
 
 namespace psdp {
 
-constexpr int kSmallThreads = 1024;
+constexpr int kSmallThreads = 512;
+constexpr int kRRThreads = 256;
+static int g_lds_limit = 56 * 1024;  // dynamic LDS bytes per workgroup (set at init)
 
 __device__ inline double block_sum(double v, double* red) {
   // red: kSmallThreads / 64 doubles of LDS
@@ -107,19 +111,23 @@ __global__ __launch_bounds__(kSmallThreads) void k_decide_chol(DecideArgs a) {
         st->guard_res = NAN;
         q = rmax / tol;
       }
+      // Below FP64 the products carry rounding noise of order u_p ||A||, so
+      // counts of positive Ritz values near zero are unreliable: expansion
+      // decisions are left to the FP64 phase and a low-precision phase that
+      // asks for one ends as stalled.
+      const bool lowp = a.phase_lowprec != 0;
       if (nonfin) {
         stop = kNonFinite;
       } else if (st->expand_req) {
-        stop = kExpand;
+        stop = lowp ? kStalled : kExpand;
       } else if (npos == m && rmax <= tol) {
-        stop = kExpand;  // no room left for a non-positive guard pair
+        stop = lowp ? kStalled : kExpand;  // no room left for a non-positive guard pair
       } else if (rmax <= tol && guard_ok) {
         stop = kConverged;
       } else {
-        // stalled: no 10% progress within the window while the count of
-        // positive Ritz values stays the same (a newly found positive pair
-        // is progress even when the residual jumps)
-        if (npos != st->last_npos || q < 0.9 * st->best_res) {
+        // stalled: no 10% progress within the window; in FP64 a newly found
+        // positive pair counts as progress even when the residual jumps
+        if ((!lowp && npos != st->last_npos) || q < 0.9 * st->best_res) {
           st->best_res = q;
           st->best_iter = st->iter;
           st->last_npos = npos;
@@ -167,7 +175,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_decide_chol(DecideArgs a) {
   const int N = s_N;
   double* Lp = lds;                      // N(N+1)/2
   double* dsc = Lp + N * (N + 1) / 2;    // N scales
-  double* row = dsc + N;                 // N
+  double* row = dsc + N;                 // scratch: inverse blocks + 16 x N
   // scaled Gram into packed lower
   for (int i = tid; i < N; i += blockDim.x) {
     double gii = a.G[s_list[i] + (size_t)s_list[i] * a.ldg];
@@ -200,6 +208,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_decide_chol(DecideArgs a) {
     const double ljj = s_piv;
     for (int i = j + 1 + tid; i < N; i += blockDim.x)
       Lp[plo(i, j)] = drop ? 0.0 : Lp[plo(i, j)] / ljj;
+    if (drop)
+      for (int k = tid; k < j; k += blockDim.x) Lp[plo(j, k)] = 0.0;
     __syncthreads();
     if (!drop) {
       // trailing update: G[i,k] -= L[i,j] L[k,j] for j < k <= i
@@ -228,22 +238,62 @@ __global__ __launch_bounds__(kSmallThreads) void k_decide_chol(DecideArgs a) {
   }
   __syncthreads();
   const int Np = s_Np;
-  // in-place inverse of the lower-triangular factor (dropped rows/columns
-  // are zero and stay zero), column by column from the last:
-  //   Linv[j,j] = 1/L[j,j];  Linv[i,j] = -Linv[j,j] * sum_{j<c<=i} Linv[i,c] L[c,j]
-  for (int j = N - 1; j >= 0; --j) {
-    const double ljj = Lp[plo(j, j)];
-    if (ljj == 0.0) continue;  // uniform across the block
-    const double inv = 1.0 / ljj;
-    for (int i = j + 1 + tid; i < N; i += blockDim.x) {
-      double sum = 0.0;
-      for (int c = j + 1; c <= i; ++c) sum += Lp[plo(i, c)] * Lp[plo(c, j)];
-      row[i] = -inv * sum;
+  // in-place inverse of the lower-triangular factor by 16 x 16 block
+  // forward substitution (dropped rows/columns are zero and stay zero):
+  //   Linv[I,I] = inv(L[I,I]);  Linv[I,J] = -Linv[I,I] sum_{J<=K<I} L[I,K] Linv[K,J]
+  // Diagonal blocks are inverted in place first (one wave each, through a
+  // per-wave 16 x 16 buffer); block rows then follow in order, each in
+  // parallel over its entries.  L[I,I] is not needed once inverted.
+  {
+    const int NB = (N + 15) / 16;
+    double* scratch = row;  // max(waves * 256, 16 * N) doubles
+    const int lane = tid % 64, wv = tid / 64, nw = blockDim.x / 64;
+    double* D = scratch + (size_t)wv * 256;
+    for (int B = wv; B < NB; B += nw) {
+      const int o = B * 16, bs = min(16, N - o);
+      for (int e = lane; e < 256; e += 64) D[e] = 0.0;
+      __threadfence_block();
+      for (int j = bs - 1; j >= 0; --j) {
+        double ljj = Lp[plo(o + j, o + j)];
+        double inv = (ljj != 0.0) ? 1.0 / ljj : 0.0;
+        double v = 0.0;
+        int i = j + 1 + lane;
+        if (i < bs && ljj != 0.0) {
+          double sum = 0.0;
+          for (int c = j + 1; c <= i; ++c) sum += D[i + 16 * c] * Lp[plo(o + c, o + j)];
+          v = -inv * sum;
+        }
+        if (i < bs) D[i + 16 * j] = v;
+        if (lane == 0) D[j + 16 * j] = inv;
+        __threadfence_block();
+      }
+      for (int e = lane; e < bs * bs; e += 64) {
+        int r = e % bs, c = e / bs;
+        if (c <= r) Lp[plo(o + r, o + c)] = D[r + 16 * c];
+      }
+      __threadfence_block();
     }
     __syncthreads();
-    for (int i = j + 1 + tid; i < N; i += blockDim.x) Lp[plo(i, j)] = row[i];
-    if (tid == 0) Lp[plo(j, j)] = inv;
-    __syncthreads();
+    double* tmp = scratch;  // 16 x N
+    for (int I = 1; I < NB; ++I) {
+      const int oi = I * 16, bi = min(16, N - oi);
+      // tmp[r, c] = sum_{c <= k < oi} L[oi + r, k] Linv[k, c]   (c < oi)
+      for (int e = tid; e < bi * oi; e += blockDim.x) {
+        int r = e % bi, c = e / bi;
+        double sum = 0.0;
+        for (int k = c; k < oi; ++k) sum += Lp[plo(oi + r, k)] * Lp[plo(k, c)];
+        tmp[r + 16 * c] = sum;
+      }
+      __syncthreads();
+      // Linv[oi + r, c] = -sum_{q <= r} Linv[oi + r, oi + q] tmp[q, c]
+      for (int e = tid; e < bi * oi; e += blockDim.x) {
+        int r = e % bi, c = e / bi;
+        double sum = 0.0;
+        for (int q = 0; q <= r; ++q) sum += Lp[plo(oi + r, oi + q)] * tmp[q + 16 * c];
+        Lp[plo(oi + r, c)] = -sum;
+      }
+      __syncthreads();
+    }
   }
   // T = D Linv^T restricted to kept columns: T[t, c] = d_t * Linv[keep[c], t]
   for (int e = tid; e < N * Np; e += blockDim.x) {
@@ -297,11 +347,11 @@ __device__ inline void rr_pair(int Ne, int r, int k, int* p, int* q) {
   *q = max(x, y);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
+__global__ __launch_bounds__(kRRThreads) void k_rr(RRArgs a) {
   extern __shared__ double lds[];
-  __shared__ double red[kSmallThreads / 64];
-  __shared__ double s_cs[kMaxN];        // c, s per pair (kMaxN/2 pairs)
-  __shared__ int s_pq[kMaxN];           // p, q per pair
+  __shared__ double red[kRRThreads / 64];
+  __shared__ double s_cs[kMaxN + 2];    // c, s per pair
+  __shared__ int s_pq[kMaxN + 2];       // p, q per pair
   __shared__ double s_theta[kMaxN];
   __shared__ int s_rank[kMaxN];
   __shared__ int s_rounds;
@@ -314,7 +364,9 @@ __global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
   const int mk = min(a.mtarget, Np);
   double* H = lds;  // packed upper, Np(Np+1)/2
   const int NH = Np * (Np + 1) / 2;
-  // load the symmetric part of K
+  // eigenvectors accumulated in LDS when they fit, else replayed from the log
+  const bool vin = (size_t)NH + (size_t)Np * Np <= a.lds_cap;
+  double* V = H + NH;
   double fro2 = 0.0;
   for (int e = tid; e < NH; e += blockDim.x) {
     int j = tri_row(e);
@@ -323,26 +375,25 @@ __global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
     H[e] = h;
     fro2 += (i == j ? 1.0 : 2.0) * h * h;
   }
+  if (vin)
+    for (int e = tid; e < Np * Np; e += blockDim.x) V[e] = (e % Np == e / Np) ? 1.0 : 0.0;
   fro2 = block_sum(fro2, red);
   const double skip = 1e-18 * sqrt(fro2);
-  const double stop2 = (1e-15 * 1e-15) * fro2;
-  // ---- parallel cyclic Jacobi (tournament order), rotations logged
+  const double stop2 = (a.off_tol * a.off_tol) * fro2;
+  // ---- parallel cyclic Jacobi (round-robin order)
   int round_id = 0;
   const size_t per_round = (size_t)2 * P;
   const int nblocks = P * (P + 1) / 2;
   for (int sweep = 0; sweep < a.max_sweeps && Np > 1; ++sweep) {
-    // off-diagonal mass
     double off = 0.0;
-    for (int j = 0; j < Np; ++j) {
-      // column j of the packed upper triangle: entries (i, j), i < j
+    for (int j = 1; j < Np; ++j)
       for (int i = tid; i < j; i += blockDim.x) {
         double v = H[j * (j + 1) / 2 + i];
         off += 2.0 * v * v;
       }
-    }
     off = block_sum(off, red);
     if (off <= stop2) break;
-    if ((size_t)(round_id + Ne) * per_round > a.log_cap) break;
+    if (!vin && (size_t)(round_id + Ne) * per_round > a.log_cap) break;
     for (int r = 0; r < Ne - 1; ++r) {
       if (tid < P) {
         int p, q;
@@ -353,24 +404,28 @@ __global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
         if (q < Np) {
           double hpq = H[pup(p, q)];
           if (fabs(hpq) > skip) {
-            double tau = (H[pup(q, q)] - H[pup(p, p)]) / (2.0 * hpq);
-            double t;
-            if (fabs(tau) > 1e150) t = 1.0 / (2.0 * tau);
-            else t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            // t = sign(d) e / (|d| + sqrt(d^2 + e^2)), d = hqq - hpp, e = 2 hpq:
+            // the smaller root of the symmetric 2x2 Schur rotation
+            double d = H[pup(q, q)] - H[pup(p, p)];
+            double e2 = 2.0 * hpq;
+            double rr = sqrt(d * d + e2 * e2);
+            double t = (d >= 0.0 ? e2 : -e2) / (fabs(d) + rr);
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
           }
         }
         s_cs[2 * tid] = c;
         s_cs[2 * tid + 1] = s;
-        a.log[(size_t)round_id * per_round + 2 * tid] = c;
-        a.log[(size_t)round_id * per_round + 2 * tid + 1] = s;
+        if (!vin) {
+          a.log[(size_t)round_id * per_round + 2 * tid] = c;
+          a.log[(size_t)round_id * per_round + 2 * tid + 1] = s;
+        }
       }
       __syncthreads();
       // two-sided update of every 2x2 block (k, l), k <= l
       for (int b = tid; b < nblocks; b += blockDim.x) {
         int l = tri_row(b);
-        int k = b - l * (l + 1) / 2;  // k <= l
+        int k = b - l * (l + 1) / 2;
         double ck = s_cs[2 * k], sk = s_cs[2 * k + 1];
         double cl = s_cs[2 * l], sl = s_cs[2 * l + 1];
         if (sk == 0.0 && sl == 0.0) continue;
@@ -397,14 +452,26 @@ __global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
           if (vk && vl) H[pup(qk, ql)] = sk * m01 + ck * m11;
         }
       }
+      if (vin) {
+        // V <- V J: columns (p, q) of every pair
+        for (int e = tid; e < Np * P; e += blockDim.x) {
+          int i = e % Np, k = e / Np;
+          double c = s_cs[2 * k], s = s_cs[2 * k + 1];
+          int p = s_pq[2 * k], q = s_pq[2 * k + 1];
+          if (s == 0.0 || q >= Np) continue;
+          double vp = V[i + (size_t)p * Np], vq = V[i + (size_t)q * Np];
+          V[i + (size_t)p * Np] = c * vp - s * vq;
+          V[i + (size_t)q * Np] = s * vp + c * vq;
+        }
+      }
       __syncthreads();
       ++round_id;
     }
   }
   if (tid == 0) s_rounds = round_id;
-  // eigenvalues and the ranking (descending, ties by index)
   for (int i = tid; i < Np; i += blockDim.x) s_theta[i] = H[pup(i, i)];
   __syncthreads();
+  // ranking (descending, ties by index)
   for (int i = tid; i < Np; i += blockDim.x) {
     double ti = s_theta[i];
     int r = 0;
@@ -415,44 +482,51 @@ __global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
     s_rank[i] = r;
   }
   __syncthreads();
-  // ---- eigenvectors of the kept pairs: W = J_1 ... J_T E_sel, by replaying
-  // the logged rounds backwards on unit vectors (H's LDS is reused)
-  double* W = lds;  // Np x mk, column-major
-  for (int e = tid; e < Np * mk; e += blockDim.x) W[e] = 0.0;
-  __syncthreads();
-  for (int i = tid; i < Np; i += blockDim.x)
-    if (s_rank[i] < mk) W[i + (size_t)s_rank[i] * Np] = 1.0;
-  __syncthreads();
-  const int rounds = s_rounds;
-  double* chunk = W + (size_t)Np * mk;  // staged log rounds
-  const int chunk_rounds = 32;
-  for (int t_hi = rounds; t_hi > 0; t_hi -= chunk_rounds) {
-    int t_lo = max(0, t_hi - chunk_rounds);
-    int cnt = t_hi - t_lo;
-    for (int e = tid; e < cnt * (int)per_round; e += blockDim.x)
-      chunk[e] = a.log[(size_t)t_lo * per_round + e];
-    __syncthreads();
-    for (int t = t_hi - 1; t >= t_lo; --t) {
-      int r = t % (Ne - 1);
-      const double* cs = chunk + (size_t)(t - t_lo) * per_round;
-      for (int e = tid; e < P * mk; e += blockDim.x) {
-        int k = e % P, col = e / P;
-        double c = cs[2 * k], s = cs[2 * k + 1];
-        if (s == 0.0) continue;
-        int p, q;
-        rr_pair(Ne, r, k, &p, &q);
-        if (q >= Np) continue;
-        double wp = W[p + (size_t)col * Np], wq = W[q + (size_t)col * Np];
-        W[p + (size_t)col * Np] = c * wp + s * wq;
-        W[q + (size_t)col * Np] = -s * wp + c * wq;
-      }
-      __syncthreads();
+  if (vin) {
+    for (int e = tid; e < Np * Np; e += blockDim.x) {
+      int i = e % Np, j = e / Np;
+      int r = s_rank[j];
+      if (r < mk) a.C[i + (size_t)r * a.ldc] = V[e];
     }
-  }
-  // outputs
-  for (int e = tid; e < Np * mk; e += blockDim.x) {
-    int i = e % Np, col = e / Np;
-    a.C[i + (size_t)col * a.ldc] = W[e];
+  } else {
+    // W = J_1 ... J_T E_sel: replay the logged rounds backwards on unit
+    // vectors (H's LDS is reused)
+    double* W = lds;
+    for (int e = tid; e < Np * mk; e += blockDim.x) W[e] = 0.0;
+    __syncthreads();
+    for (int i = tid; i < Np; i += blockDim.x)
+      if (s_rank[i] < mk) W[i + (size_t)s_rank[i] * Np] = 1.0;
+    __syncthreads();
+    const int rounds = s_rounds;
+    double* chunk = W + (size_t)Np * mk;
+    const int chunk_rounds = 32;
+    for (int t_hi = rounds; t_hi > 0; t_hi -= chunk_rounds) {
+      int t_lo = max(0, t_hi - chunk_rounds);
+      int cnt = t_hi - t_lo;
+      for (int e = tid; e < cnt * (int)per_round; e += blockDim.x)
+        chunk[e] = a.log[(size_t)t_lo * per_round + e];
+      __syncthreads();
+      for (int t = t_hi - 1; t >= t_lo; --t) {
+        int r = t % (Ne - 1);
+        const double* cs = chunk + (size_t)(t - t_lo) * per_round;
+        for (int e = tid; e < P * mk; e += blockDim.x) {
+          int k = e % P, col = e / P;
+          double c = cs[2 * k], s = cs[2 * k + 1];
+          if (s == 0.0) continue;
+          int p, q;
+          rr_pair(Ne, r, k, &p, &q);
+          if (q >= Np) continue;
+          double wp = W[p + (size_t)col * Np], wq = W[q + (size_t)col * Np];
+          W[p + (size_t)col * Np] = c * wp + s * wq;
+          W[q + (size_t)col * Np] = -s * wp + c * wq;
+        }
+        __syncthreads();
+      }
+    }
+    for (int e = tid; e < Np * mk; e += blockDim.x) {
+      int i = e % Np, col = e / Np;
+      a.C[i + (size_t)col * a.ldc] = W[e];
+    }
   }
   int npos = 0;
   for (int i = tid; i < Np; i += blockDim.x) {
@@ -464,22 +538,28 @@ __global__ __launch_bounds__(kSmallThreads) void k_rr(RRArgs a) {
     st->npos_rr = (int)npd;
     st->mk = mk;
     st->expand_req = ((int)npd > a.mtarget) ? 1 : 0;
-    st->jacobi_rounds = rounds;
+    st->jacobi_rounds = s_rounds;
     if (a.count_iter) st->iter += 1;
   }
 }
 
 hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st) {
-  size_t lds = sizeof(double) * ((size_t)N_host * (N_host + 1) / 2 + 2 * (size_t)N_host + 8);
+  size_t scr = std::max((size_t)(kSmallThreads / 64) * 256, (size_t)16 * N_host);
+  size_t lds = sizeof(double) * ((size_t)N_host * (N_host + 1) / 2 + (size_t)N_host + scr + 8);
   hipLaunchKernelGGL(k_decide_chol, dim3(1), dim3(kSmallThreads), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_rr(const RRArgs& a, int Np_host, int mk_host, hipStream_t st) {
+hipError_t launch_rr(const RRArgs& a_in, int Np_host, int mk_host, hipStream_t st) {
+  RRArgs a = a_in;
   size_t h = (size_t)Np_host * (Np_host + 1) / 2;
-  size_t w = (size_t)Np_host * mk_host + (size_t)32 * Np_host + 64;
-  size_t lds = sizeof(double) * (h > w ? h : w);
-  hipLaunchKernelGGL(k_rr, dim3(1), dim3(kSmallThreads), lds, st, a);
+  size_t w = (size_t)Np_host * mk_host + (size_t)32 * (Np_host + 2) + 64;
+  size_t want = h + (size_t)Np_host * Np_host;  // H and V both in LDS
+  size_t cap_doubles = (size_t)(g_lds_limit / 8);
+  size_t need = std::max(h, w);
+  size_t lds_d = want <= cap_doubles ? want : need;
+  a.lds_cap = lds_d;
+  hipLaunchKernelGGL(k_rr, dim3(1), dim3(kRRThreads), sizeof(double) * lds_d, st, a);
   return hipGetLastError();
 }
 
@@ -490,6 +570,7 @@ hipError_t small_kernels_init() {
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     lim = 64 * 1024;
   int dyn = lim - 8 * 1024;  // static LDS of the kernels stays below 8 KB
+  if (dyn > 0) g_lds_limit = dyn;
   if (dyn > 0) {
     (void)hipFuncSetAttribute((const void*)k_decide_chol,
                               hipFuncAttributeMaxDynamicSharedMemorySize, dyn);

@@ -74,9 +74,13 @@ __global__ __launch_bounds__(256) void k_ingest(const double* __restrict__ X, in
   if (threadIdx.x == 0) fro_partial[blockIdx.x] = red[0];
 }
 
+// The kernel writes every element (i, j) with i, j < lda (zero padding
+// included): A64 (and Alp) must hold lda x lda elements, i.e. at least lda
+// allocated columns (cols_alloc).
 hipError_t launch_ingest(const double* X, int ldx, int n, double sign, double* A64, int lda,
-                         void* Alp, int prec, double* fro_partial, int* nonfinite,
+                         int cols_alloc, void* Alp, int prec, double* fro_partial, int* nonfinite,
                          hipStream_t st, int* nblocks_out) {
+  if (n < 0 || lda < n || cols_alloc < lda) return hipErrorInvalidValue;
   int T = (lda + kTile - 1) / kTile;
   int nb = T * (T + 1) / 2;
   if (nblocks_out) *nblocks_out = nb;

@@ -36,7 +36,10 @@ def _check(res, Xh, rel=REL, bound=True):
           f"npos={res.info['n_pos']} rel={r:.2e} err={err:.2e} bound={res.info['err_bound']:.2e}")
     assert r <= rel, (r, res.info)
     if bound:
-        assert res.info["err_bound"] >= err * (1 - 1e-9), (err, res.info)
+        # Thm `bound` holds in exact arithmetic for the computed Ritz pairs;
+        # the rebuild and the oracle each add rounding of order n u ||X||_F
+        slack = 10 * Xh.shape[0] * np.finfo(float).eps * np.linalg.norm(Xh)
+        assert res.info["err_bound"] + slack >= err, (err, res.info)
     return r, err, lam
 
 
@@ -131,3 +134,26 @@ def test_trivial_inputs(proj):
     # n = 1
     res = proj.project(to_dev(np.array([[2.5]])), m_cap=1, side="pos", tol=1e-12)
     assert abs(to_host(res.Pi)[0, 0] - 2.5) <= 1e-12
+
+
+def test_rr_methods_agree():
+    """The Jacobi Rayleigh-Ritz (kept as a cross-check) and the tridiagonal
+    one give the same projection to the parity bar."""
+    import os
+    import torch
+    import paper_1912_02767_amd as psdp
+    from gpu_util import to_dev, to_host
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = random_spectrum_matrix(120, 10, rng_for(53, 0))
+    outs = []
+    for method in ("1", "0"):
+        os.environ["PSDP_RR_METHOD"] = method
+        p = psdp.Projector(0)
+        res = p.project(to_dev(c.X), m_cap=24, side="pos", tol=1e-10, pos_hint=10)
+        assert res.status == 0
+        outs.append(to_host(res.Pi))
+        _check(res, c.X)
+        p.close()
+    os.environ.pop("PSDP_RR_METHOD", None)
+    assert np.abs(outs[0] - outs[1]).max() <= 1e-8
