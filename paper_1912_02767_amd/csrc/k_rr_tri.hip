@@ -1,22 +1,26 @@
 // Rayleigh-Ritz step (paper §5, Alg. 2) for one small projected matrix
-// H = S^T A S (S orthonormal), one workgroup, FP64 throughout:
-//   1. Householder tridiagonalization H = Q T Q^T in LDS (packed lower
-//      triangle; Golub & Van Loan §8.3.1), reflectors kept in place
-//   2. the largest mk eigenvalues of T by multisection on Sturm counts
-//      (every thread evaluates one LDL^T inertia count per round), plus the
+// H = S^T A S (S orthonormal), one workgroup of four waves, FP64:
+//   1. Householder tridiagonalization H = Q T Q^T (Golub & Van Loan §8.3.1)
+//      by one wave, lanes over rows, so that no step needs a workgroup
+//      barrier; H is stored full (column-major) when it fits, packed
+//      otherwise; the reflectors stay in place
+//   2. the largest mk eigenvalues of T by multisection on Sturm counts (all
+//      four waves, one LDL^T inertia count per thread and round), plus the
 //      count of positive eigenvalues of H
-//   3. eigenvectors of T by inverse iteration (two steps) with modified
-//      Gram-Schmidt inside clusters of close eigenvalues
-//   4. back-transformation Z = Q Y and Rayleigh quotients for the values
-// The outputs are the coefficients C (Np x mk) of the kept Ritz vectors in
-// the basis S and their Ritz values in descending order.
+//   3. eigenvectors of T by inverse iteration (Gaussian elimination with
+//      partial pivoting of T - sigma I, two steps), modified Gram-Schmidt
+//      inside clusters of close eigenvalues, Rayleigh quotients for values
+//   4. back-transformation Z = Q Y, the columns split over the waves
+// Outputs: coefficients C (Np x mk) of the kept Ritz vectors in the basis S
+// and their Ritz values in descending order.
 #include <algorithm>
 
 #include "common.h"
 
 namespace psdp {
 
-constexpr int kTriThreads = 512;
+constexpr int kTriThreads = 256;
+constexpr int kFullMaxN = 112;  // full storage of H up to this order
 
 __device__ inline int tri_row2(int e) {
   int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
@@ -24,25 +28,61 @@ __device__ inline int tri_row2(int e) {
   while (r * (r + 1) / 2 > e) --r;
   return r;
 }
-// packed lower triangle, row-major: (i, j), j <= i
-__device__ inline int pl(int i, int j) { return i * (i + 1) / 2 + j; }
-// symmetric access in the packed lower triangle
-__device__ inline int ps(int i, int j) { return i >= j ? pl(i, j) : pl(j, i); }
 
-__device__ inline double wg_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = threadIdx.x / 64;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < (int)blockDim.x / 64; ++i) s += red[i];
-  __syncthreads();
-  return s;
+template <bool FULL>
+struct SymStore {
+  double* a;
+  int ld;
+  __device__ inline double& at(int i, int j) const {  // any (i, j)
+    if (FULL) return a[i + (size_t)j * ld];
+    return (i >= j) ? a[i * (i + 1) / 2 + j] : a[j * (j + 1) / 2 + i];
+  }
+  __device__ inline double& low(int i, int j) const {  // i >= j
+    if (FULL) return a[i + (size_t)j * ld];
+    return a[i * (i + 1) / 2 + j];
+  }
+};
+
+// Sum over the 64 lanes of a wave, result in every lane: DPP within rows
+// of 16 lanes (quad permutes and mirrors), a swizzle across the two rows of
+// each half, and two lane reads across the halves.
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  int2 x = __builtin_bit_cast(int2, v);
+  x.x = __builtin_amdgcn_mov_dpp(x.x, CTRL, 0xF, 0xF, false);
+  x.y = __builtin_amdgcn_mov_dpp(x.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, x);
+}
+__device__ inline double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+  v += dpp_d<0x141>(v);  // row_half_mirror: the other quad of each 8
+  v += dpp_d<0x140>(v);  // row_mirror: the other 8 of each 16
+  int2 x = __builtin_bit_cast(int2, v);
+  x.x = __builtin_amdgcn_ds_swizzle(x.x, 0x401F);  // lane ^ 16 within 32
+  x.y = __builtin_amdgcn_ds_swizzle(x.y, 0x401F);
+  v += __builtin_bit_cast(double, x);
+  int2 y = __builtin_bit_cast(int2, v);
+  int2 lo, hi;
+  lo.x = __builtin_amdgcn_readlane(y.x, 0);
+  lo.y = __builtin_amdgcn_readlane(y.y, 0);
+  hi.x = __builtin_amdgcn_readlane(y.x, 32);
+  hi.y = __builtin_amdgcn_readlane(y.y, 32);
+  return __builtin_bit_cast(double, lo) + __builtin_bit_cast(double, hi);
+}
+
+// a / b through the hardware reciprocal and one Newton step (relative error
+// a few units in the last place; used in the Sturm and inverse-iteration
+// recurrences, where the result only steers inertia counts and directions)
+__device__ inline double fast_div(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(fma(-b, r, 1.0), r, r);
+  r = fma(fma(-b, r, 1.0), r, r);
+  return a * r;
 }
 
 // number of eigenvalues of T (d, e2 = e^2) below x, LDL^T inertia with a
-// floor on the pivots (pivmin)
+// floor on the pivots
 __device__ inline int sturm_count(const double* d, const double* e2, int N, double x,
                                   double pivmin) {
   int cnt = 0;
@@ -50,7 +90,7 @@ __device__ inline int sturm_count(const double* d, const double* e2, int N, doub
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += (q < 0.0);
   for (int i = 1; i < N; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+    q = d[i] - x - fast_div(e2[i - 1], q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += (q < 0.0);
   }
@@ -64,109 +104,196 @@ __device__ inline double start_entry(int i, int j) {
   return 1.0 + 0.5 * ((double)(h & 0xFFFFFF) / 16777216.0 - 0.5);
 }
 
+// One inverse-iteration solve (T - sigma I) y_new = y: Gaussian elimination
+// with partial pivoting fused with the forward substitution, U's three
+// diagonals in U0/U1/U2 (stride us between entries), then back
+// substitution.  Pivots below pfloor in magnitude are replaced by pfloor.
+__device__ inline void tri_solve(const double* d, const double* e, int N, double sigma,
+                                 double pfloor, double* y, double* U0, double* U1, double* U2,
+                                 size_t us) {
+  double di = d[0] - sigma;                 // current row i: (di, ui) after elimination
+  double ui = (N > 1) ? e[0] : 0.0;
+  double bi = y[0];
+  for (int i = 0; i + 1 < N; ++i) {
+    const double li = e[i];                 // entry (i+1, i)
+    const double dn = d[i + 1] - sigma;     // entry (i+1, i+1)
+    const double un = (i + 2 < N) ? e[i + 1] : 0.0;  // entry (i+1, i+2)
+    const double bn = y[i + 1];
+    if (fabs(di) >= fabs(li)) {
+      const double piv = (di == 0.0) ? pfloor : di;
+      const double f = fast_div(li, piv);
+      U0[i * us] = piv;
+      U1[i * us] = ui;
+      U2[i * us] = 0.0;
+      y[i] = bi;
+      di = dn - f * ui;
+      ui = un;
+      bi = bn - f * bi;
+    } else {
+      // interchange rows i and i+1
+      const double f = fast_div(di, li);
+      U0[i * us] = li;
+      U1[i * us] = dn;
+      U2[i * us] = un;
+      y[i] = bn;
+      di = ui - f * dn;
+      ui = -f * un;
+      bi = bi - f * bn;
+    }
+  }
+  if (fabs(di) < pfloor) di = (di < 0.0) ? -pfloor : pfloor;
+  U0[(size_t)(N - 1) * us] = di;
+  y[N - 1] = bi / di;
+  for (int i = N - 2; i >= 0; --i) {
+    double u0 = U0[i * us];
+    if (fabs(u0) < pfloor) u0 = (u0 < 0.0) ? -pfloor : pfloor;
+    double s = y[i] - U1[i * us] * y[i + 1];
+    if (i + 2 < N) s -= U2[i * us] * y[i + 2];
+    y[i] = fast_div(s, u0);
+  }
+}
+
+template <bool FULL>
 __global__ __launch_bounds__(kTriThreads) void k_rr_tri(RRArgs a) {
   extern __shared__ double lds[];
-  __shared__ double red[kTriThreads / 64];
   __shared__ double s_lo[kMaxM], s_hi[kMaxM];
   __shared__ int s_npos;
   __shared__ double s_tnorm, s_pivmin;
   State* st = a.st;
   if (st->stop) return;
-  const int tid = threadIdx.x;
-  const int nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
   const int N = st->Np;
   const int mk = min(a.mtarget, N);
   // ---- LDS layout
-  double* Hp = lds;                              // N(N+1)/2
-  double* d = Hp + N * (N + 1) / 2;              // N
-  double* e = d + N;                             // N   (sub-diagonal)
-  double* e2 = e + N;                            // N
-  double* tau = e2 + N;                          // N
-  double* pv = tau + N;                          // N   (p, then w)
-  double* part = pv + N;                         // 8 N (segment partial sums)
-  double* Y = part + 8 * N;                      // N x mk eigenvectors (col-major)
-  double* cnt_buf = Y + (size_t)N * mk;          // nt counts / dot products
-
+  const size_t hsz = FULL ? (size_t)N * N : (size_t)N * (N + 1) / 2;
+  double* Hraw = lds;
+  double* d = Hraw + hsz;         // N
+  double* e = d + N;              // N (sub-diagonal)
+  double* e2 = e + N;             // N
+  double* tau = e2 + N;           // N
+  double* pv = tau + N;           // N (p, then w; then the Ritz values)
+  double* vbuf = pv + N;          // N (current reflector)
+  double* wbuf = vbuf + N;        // 4 N (per-wave w)
+  double* part = wbuf + 4 * N;    // 4 N (per-wave partial products)
+  const int ldy = N + 1;          // odd leading dimension: lanes over columns
+  double* Y = part + 4 * N;       // ldy x mk eigenvectors, column-major
+  int* cnts = (int*)(Y + (size_t)ldy * mk);           // nt ints
+  double* ufac = (double*)(cnts + nt + (nt & 1));     // 3 N mk in LDS when it fits
+  const bool fac_lds = a.lds_cap >= (size_t)(ufac - lds) + 3 * (size_t)N * mk;
+  SymStore<FULL> H{Hraw, N};
   if (tid == 0) st->t_phase[0] = wall_clock64();
-  // load the symmetric part of K into the packed lower triangle
-  for (int x = tid; x < N * (N + 1) / 2; x += nt) {
-    int i = tri_row2(x), j = x - i * (i + 1) / 2;
-    Hp[x] = 0.5 * (a.K[i + (size_t)j * a.ldk] + a.K[j + (size_t)i * a.ldk]);
+  if (FULL) {
+    for (int x = tid; x < N * N; x += nt) {
+      int i = x % N, j = x / N;
+      Hraw[x] = 0.5 * (a.K[i + (size_t)j * a.ldk] + a.K[j + (size_t)i * a.ldk]);
+    }
+  } else {
+    for (int x = tid; x < N * (N + 1) / 2; x += nt) {
+      int i = tri_row2(x), j = x - i * (i + 1) / 2;
+      Hraw[x] = 0.5 * (a.K[i + (size_t)j * a.ldk] + a.K[j + (size_t)i * a.ldk]);
+    }
   }
   __syncthreads();
 
-  // ---- 1. tridiagonalization (lower): H_k = I - tau v v^T, v(0) = 1 at row k+1
-  for (int k = 0; k + 2 < N; ++k) {
-    const int m = N - k - 1;  // length of x = H[k+1:N, k]
-    double part_sq = 0.0;
-    for (int i = k + 2 + tid; i < N; i += nt) {
-      double x = Hp[pl(i, k)];
-      part_sq += x * x;
-    }
-    const double xnorm2 = wg_sum(part_sq, red);
-    const double alpha = Hp[pl(k + 1, k)];
-    double t = 0.0, beta = alpha, scale = 0.0;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
-    }
-    // v into column k (v(0) = 1 stored explicitly)
-    for (int i = k + 1 + tid; i < N; i += nt)
-      Hp[pl(i, k)] = (i == k + 1) ? 1.0 : Hp[pl(i, k)] * scale;
-    if (tid == 0) { tau[k] = t; e[k] = beta; }
-    __syncthreads();
-    if (t != 0.0) {
-      // p = t * A22 v, A22 = H[k+1:, k+1:]; rows split into 4 segments of j
-      const int seg = (m + 3) / 4;
-      for (int x = tid; x < 4 * m; x += nt) {
-        int r = x % m, sgi = x / m;
-        int i = k + 1 + r;
-        int j0 = k + 1 + sgi * seg, j1 = min(N, j0 + seg);
-        double s = 0.0;
-        for (int j = j0; j < j1; ++j) s += Hp[ps(i, j)] * Hp[pl(j, k)];
-        part[sgi * N + i] = s;
+  // ---- 1. tridiagonalization: lanes over rows, the four waves over column
+  // segments of each step.  Per step: every wave forms the reflector v
+  // (redundantly), partial products of its column segment go to LDS
+  // (barrier), every wave combines them into p and w = p - (t/2)(p.v) v in
+  // its own copy, then updates its column segment of the trailing rows
+  // (barrier).  Reflectors stay in column k.
+  {
+    const int nw = nt / 64;
+    double* __restrict__ vv = vbuf;                  // N, written by wave 0
+    double* __restrict__ ww = wbuf + (size_t)wv * N; // per-wave copy of w
+    double* __restrict__ pp = part;                  // nw x N partial products
+    for (int k = 0; k + 2 < N; ++k) {
+      const int m = N - k - 1;
+      double xs = 0.0;
+      for (int i = k + 2 + lane; i < N; i += 64) {
+        const double x = H.low(i, k);
+        xs += x * x;
+      }
+      const double xnorm2 = wave_sum(xs);
+      const double alpha = H.low(k + 1, k);
+      double t = 0.0, beta = alpha, scale = 0.0;
+      if (xnorm2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        t = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      // the reflector, in registers of every wave and in vv (wave 0 writes)
+      if (t == 0.0) {
+        // column k is already reduced: no reflection (same decision in
+        // every wave, so the whole workgroup skips the step)
+        if (wv == 0 && lane == 0) { tau[k] = 0.0; e[k] = beta; }
+        continue;
+      }
+      const int seg = (m + nw - 1) / nw;
+      const int j0 = k + 1 + wv * seg, j1 = min(N, j0 + seg);
+      for (int i = k + 1 + lane; i < N; i += 64) {
+        const double v = (i == k + 1) ? 1.0 : H.low(i, k) * scale;
+        if (wv == 0) vv[i] = v;
+      }
+      __syncthreads();  // vv complete; everybody has read column k
+      if (wv == 0) {
+        for (int i = k + 1 + lane; i < N; i += 64) H.low(i, k) = vv[i];
+        if (lane == 0) { tau[k] = t; e[k] = beta; }
+      }
+      // partial products over this wave's column segment
+      for (int i = k + 1 + lane; i < N; i += 64) {
+        double s0 = 0.0, s1 = 0.0;
+        int j = j0;
+        for (; j + 1 < j1; j += 2) {
+          s0 += H.at(i, j) * vv[j];
+          s1 += H.at(i, j + 1) * vv[j + 1];
+        }
+        if (j < j1) s0 += H.at(i, j) * vv[j];
+        pp[(size_t)wv * N + i] = s0 + s1;
       }
       __syncthreads();
-      double dot_part = 0.0;
-      for (int i = k + 1 + tid; i < N; i += nt) {
-        double p = t * (part[i] + part[N + i] + part[2 * N + i] + part[3 * N + i]);
-        pv[i] = p;
-        dot_part += p * Hp[pl(i, k)];
+      // p and w for all rows, in this wave's copy
+      double dp = 0.0;
+      for (int i = k + 1 + lane; i < N; i += 64) {
+        double sum = 0.0;
+        for (int q = 0; q < nw; ++q) sum += pp[(size_t)q * N + i];
+        const double p = t * sum;
+        ww[i] = p;
+        dp += p * vv[i];
       }
-      const double pdotv = wg_sum(dot_part, red);
-      const double al = -0.5 * t * pdotv;
-      for (int i = k + 1 + tid; i < N; i += nt) pv[i] += al * Hp[pl(i, k)];
-      __syncthreads();
-      // A22 -= v w^T + w v^T (lower part)
-      const int cnt = m * (m + 1) / 2;
-      for (int x = tid; x < cnt; x += nt) {
-        int r = tri_row2(x), c = x - r * (r + 1) / 2;
-        int i = k + 1 + r, j = k + 1 + c;
-        double vi = Hp[pl(i, k)], vj = Hp[pl(j, k)];
-        Hp[pl(i, j)] -= vi * pv[j] + pv[i] * vj;
+      const double al = -0.5 * t * wave_sum(dp);
+      for (int i = k + 1 + lane; i < N; i += 64) ww[i] += al * vv[i];
+      __threadfence_block();
+      // A22 -= v w^T + w v^T on this wave's column segment (both triangles
+      // when stored full, the lower one otherwise)
+      for (int i = k + 1 + lane; i < N; i += 64) {
+        const double vi = vv[i], wi = ww[i];
+        const int jb = j0, je = FULL ? j1 : min(j1, i + 1);
+        for (int j = jb; j < je; ++j) H.at(i, j) -= vi * ww[j] + wi * vv[j];
       }
       __syncthreads();
     }
   }
-  for (int i = tid; i < N; i += nt) d[i] = Hp[pl(i, i)];
-  if (tid == 0) st->t_phase[1] = wall_clock64();
-  if (tid == 0 && N >= 2) { e[N - 2] = Hp[pl(N - 1, N - 2)]; tau[N - 2] = 0.0; }
-  __syncthreads();
-  for (int i = tid; i + 1 < N; i += nt) e2[i] = e[i] * e[i];
-  // norm and pivot floor
-  if (tid == 0) {
-    double tn = 0.0, emax2 = 0.0;
-    for (int i = 0; i < N; ++i) {
-      double r = fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
-      tn = fmax(tn, r);
-      if (i + 1 < N) emax2 = fmax(emax2, e[i] * e[i]);
+  if (wv == 0) {
+    for (int i = lane; i < N; i += 64) d[i] = H.low(i, i);
+    if (lane == 0 && N >= 2) { e[N - 2] = H.low(N - 1, N - 2); tau[N - 2] = 0.0; }
+    __threadfence_block();
+    for (int i = lane; i + 1 < N; i += 64) e2[i] = e[i] * e[i];
+    __threadfence_block();
+    if (lane == 0) {
+      double tn = 0.0, emax2 = 0.0;
+      for (int i = 0; i < N; ++i) {
+        double r = fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
+        tn = fmax(tn, r);
+        if (i + 1 < N) emax2 = fmax(emax2, e2[i]);
+      }
+      s_tnorm = tn;
+      s_pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
     }
-    s_tnorm = tn;
-    s_pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
   }
   __syncthreads();
   const double tnorm = s_tnorm, pivmin = s_pivmin;
+  if (tid == 0) st->t_phase[1] = wall_clock64();
 
   // ---- 2. multisection for the top mk eigenvalues (+ count of positives)
   {
@@ -180,19 +307,17 @@ __global__ __launch_bounds__(kTriThreads) void k_rr_tri(RRArgs a) {
     gl -= pad;
     gu += pad;
     for (int j = tid; j < mk; j += nt) { s_lo[j] = gl; s_hi[j] = gu; }
-    if (tid == 0) s_npos = N - sturm_count(d, e2, N, 0.0, pivmin);
+    if (tid == nt - 1) s_npos = N - sturm_count(d, e2, N, 0.0, pivmin);
     __syncthreads();
-    const int per = max(1, nt / max(mk, 1));  // threads per eigenvalue
+    const int per = max(1, nt / max(mk, 1));
     const int j_me = tid / per, s_me = tid % per;
-    int* cnts = (int*)cnt_buf;
-    for (int round = 0; round < 40; ++round) {
-      // all intervals narrow enough?
-      // the shifts only need to be close enough for inverse iteration; the
-      // values themselves come from Rayleigh quotients afterwards
+    for (int round = 0; round < 48; ++round) {
+      // the shifts only need to be close for inverse iteration; the values
+      // come from Rayleigh quotients afterwards
       bool done = true;
       for (int j = 0; j < mk; ++j) {
         double w = s_hi[j] - s_lo[j];
-        double tolj = 1e-12 * tnorm + 4.0 * 2.2e-16 * fmax(fabs(s_lo[j]), fabs(s_hi[j])) + 4.0 * pivmin;
+        double tolj = 1e-12 * tnorm + 8.8e-16 * fmax(fabs(s_lo[j]), fabs(s_hi[j])) + 4.0 * pivmin;
         if (w > tolj) { done = false; break; }
       }
       if (done) break;
@@ -207,12 +332,10 @@ __global__ __launch_bounds__(kTriThreads) void k_rr_tri(RRArgs a) {
         const int target = N - 1 - j;  // ascending index of the j-th largest
         double lo = s_lo[j], hi = s_hi[j];
         double nlo = lo, nhi = hi;
-        // points x_s (s = 0..per-1); count(x) = #eigenvalues < x
         for (int s2 = 0; s2 < per; ++s2) {
           double x = lo + (hi - lo) * (double)(s2 + 1) / (double)(per + 1);
-          int c = cnts[j * per + s2];
-          if (c <= target) nlo = x;                 // eigenvalue >= x
-          else { nhi = x; break; }                  // eigenvalue < x
+          if (cnts[j * per + s2] <= target) nlo = x;
+          else { nhi = x; break; }
         }
         s_lo[j] = nlo;
         s_hi[j] = nhi;
@@ -220,158 +343,109 @@ __global__ __launch_bounds__(kTriThreads) void k_rr_tri(RRArgs a) {
       __syncthreads();
     }
   }
-
   if (tid == 0) st->t_phase[2] = wall_clock64();
-  // ---- 3. inverse iteration on T, one thread per eigenvector: Gaussian
-  // elimination with partial pivoting of the tridiagonal T - sigma I (row
-  // interchanges add a second super-diagonal), zero pivots replaced by
-  // eps ||T||.  Factors live in global scratch, interleaved by eigenvector.
-  double* fdl = a.scratch;                        // N x mk each: element i of j at i*mk + j
-  double* fdd = fdl + (size_t)N * mk;
-  double* fdu = fdd + (size_t)N * mk;
-  double* fdu2 = fdu + (size_t)N * mk;
-  double* fpiv = fdu2 + (size_t)N * mk;
-  const double pfloor = fmax(2.2e-16 * tnorm, 1e-300);
-  if (tid < mk) {
-    const int j = tid;
-    const double sigma = 0.5 * (s_lo[j] + s_hi[j]);
-#define F(arr, i) arr[(size_t)(i) * mk + j]
-    for (int i = 0; i < N; ++i) {
-      F(fdd, i) = d[i] - sigma;
-      F(fdl, i) = (i + 1 < N) ? e[i] : 0.0;
-      F(fdu, i) = (i + 1 < N) ? e[i] : 0.0;
-      F(fdu2, i) = 0.0;
-    }
-    for (int i = 0; i + 1 < N; ++i) {
-      double di = F(fdd, i), li = F(fdl, i);
-      if (fabs(di) >= fabs(li)) {
-        if (di == 0.0) { di = pfloor; F(fdd, i) = di; }
-        double fact = li / di;
-        F(fdl, i) = fact;
-        F(fdd, i + 1) -= fact * F(fdu, i);
-        F(fpiv, i) = 0.0;
-      } else {
-        double fact = di / li;
-        F(fdd, i) = li;
-        F(fdl, i) = fact;
-        double tmp = F(fdu, i);
-        F(fdu, i) = F(fdd, i + 1);
-        F(fdd, i + 1) = tmp - fact * F(fdd, i + 1);
-        if (i + 2 < N) {
-          F(fdu2, i) = F(fdu, i + 1);
-          F(fdu, i + 1) = -fact * F(fdu, i + 1);
-        }
-        F(fpiv, i) = 1.0;
-      }
-    }
-    if (F(fdd, N - 1) == 0.0) F(fdd, N - 1) = pfloor;
-    for (int i = 0; i < N; ++i) {
-      if (fabs(F(fdd, i)) < pfloor) F(fdd, i) = copysign(pfloor, F(fdd, i));
-      Y[i + (size_t)j * N] = start_entry(i, j);
-    }
-#undef F
-  }
-  __syncthreads();
-  const double ortol = 1e-3 * tnorm;
-  for (int itn = 0; itn < 2; ++itn) {
-    if (tid < mk) {
-      const int j = tid;
-      double* y = Y + (size_t)j * N;
-#define F(arr, i) arr[(size_t)(i) * mk + j]
-      // forward: apply the row interchanges and multipliers
-      for (int i = 0; i + 1 < N; ++i) {
-        if (F(fpiv, i) != 0.0) {
-          double t0 = y[i];
-          y[i] = y[i + 1];
-          y[i + 1] = t0 - F(fdl, i) * y[i];
-        } else {
-          y[i + 1] -= F(fdl, i) * y[i];
-        }
-      }
-      // backward with the three diagonals of U
-      y[N - 1] /= F(fdd, N - 1);
-      if (N >= 2) y[N - 2] = (y[N - 2] - F(fdu, N - 2) * y[N - 1]) / F(fdd, N - 2);
-      for (int i = N - 3; i >= 0; --i)
-        y[i] = (y[i] - F(fdu, i) * y[i + 1] - F(fdu2, i) * y[i + 2]) / F(fdd, i);
-#undef F
-      double nn = 0.0, mx = 0.0;
-      for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(y[i]));
-      double sc = mx > 0.0 ? 1.0 / mx : 1.0;
-      for (int i = 0; i < N; ++i) { y[i] *= sc; nn += y[i] * y[i]; }
-      double inv = 1.0 / sqrt(nn);
-      for (int i = 0; i < N; ++i) y[i] *= inv;
-    }
-    __syncthreads();
-    // modified Gram-Schmidt inside clusters of close eigenvalues
-    for (int j = 1; j < mk; ++j) {
-      double mid_j = 0.5 * (s_lo[j] + s_hi[j]);
-      double mid_p = 0.5 * (s_lo[j - 1] + s_hi[j - 1]);
-      if (mid_p - mid_j > ortol) continue;   // uniform: not in a cluster with j-1
-      int c0 = j - 1;
-      while (c0 > 0 && 0.5 * (s_lo[c0 - 1] + s_hi[c0 - 1]) - 0.5 * (s_lo[c0] + s_hi[c0]) <= ortol) --c0;
-      double* yj = Y + (size_t)j * N;
-      for (int i0 = c0; i0 < j; ++i0) {
-        const double* yi = Y + (size_t)i0 * N;
-        double dp = 0.0;
-        for (int r = tid; r < N; r += nt) dp += yi[r] * yj[r];
-        dp = wg_sum(dp, red);
-        for (int r = tid; r < N; r += nt) yj[r] -= dp * yi[r];
-        __syncthreads();
-      }
-      double nn = 0.0;
-      for (int r = tid; r < N; r += nt) nn += yj[r] * yj[r];
-      nn = wg_sum(nn, red);
-      double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-      for (int r = tid; r < N; r += nt) yj[r] *= inv;
-      __syncthreads();
-    }
-  }
-  if (tid == 0) st->t_phase[3] = wall_clock64();
-  // Rayleigh quotients y^T T y (eigenvalues of H to second order)
-  double* theta = cnt_buf;  // mk doubles (the counts are no longer needed)
-  if (tid < mk) {
-    const double* y = Y + (size_t)tid * N;
-    double rq = 0.0;
-    for (int i = 0; i < N; ++i) {
-      double ty = d[i] * y[i];
-      if (i > 0) ty += e[i - 1] * y[i - 1];
-      if (i + 1 < N) ty += e[i] * y[i + 1];
-      rq += y[i] * ty;
-    }
-    theta[tid] = rq;
-  }
-  __syncthreads();
 
-  // ---- 4. back-transformation Z = H_0 H_1 ... H_{N-3} Y
-  for (int k = N - 3; k >= 0; --k) {
-    const double t = tau[k];
-    if (t == 0.0) continue;  // uniform
-    const int m = N - k - 1;
-    // w_j = v^T Y[k+1:, j], rows split into 8 segments
-    const int seg = (m + 7) / 8;
-    for (int x = tid; x < 8 * mk; x += nt) {
-      int j = x % mk, sgi = x / mk;
-      int r0 = k + 1 + sgi * seg, r1 = min(N, r0 + seg);
-      double s = 0.0;
-      for (int r = r0; r < r1; ++r) s += Hp[pl(r, k)] * Y[r + (size_t)j * N];
-      part[sgi * mk + j] = s;
+  // ---- 3. inverse iteration (one lane per vector; mk <= 64 so all lanes
+  // are in wave 0), Gram-Schmidt inside clusters by the same wave
+  const double pfloor = fmax(2.2e-16 * tnorm, 1e-300);
+  const double ortol = 1e-3 * tnorm;
+  if (wv == 0) {
+    for (int j = lane; j < mk; j += 64)
+      for (int i = 0; i < N; ++i) Y[i + (size_t)j * ldy] = start_entry(i, j);
+    __threadfence_block();
+    for (int itn = 0; itn < 2; ++itn) {
+      for (int j = lane; j < mk; j += 64) {
+        const double sigma = 0.5 * (s_lo[j] + s_hi[j]);
+        double* y = Y + (size_t)j * ldy;
+        double *U0, *U1, *U2;
+        size_t us;
+        if (fac_lds) {
+          U0 = ufac + (size_t)j * 3 * N; U1 = U0 + N; U2 = U1 + N; us = 1;
+        } else {
+          U0 = a.scratch + j; U1 = U0 + (size_t)N * mk; U2 = U1 + (size_t)N * mk; us = mk;
+        }
+        tri_solve(d, e, N, sigma, pfloor, y, U0, U1, U2, us);
+        double mx = 0.0;
+        for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(y[i]));
+        const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+        double nn = 0.0;
+        for (int i = 0; i < N; ++i) { y[i] *= sc; nn += y[i] * y[i]; }
+        const double inv = 1.0 / sqrt(nn);
+        for (int i = 0; i < N; ++i) y[i] *= inv;
+      }
+      __threadfence_block();
+      for (int j = 1; j < mk; ++j) {
+        const double mid_j = 0.5 * (s_lo[j] + s_hi[j]);
+        const double mid_p = 0.5 * (s_lo[j - 1] + s_hi[j - 1]);
+        if (mid_p - mid_j > ortol) continue;
+        int c0 = j - 1;
+        while (c0 > 0 && 0.5 * (s_lo[c0 - 1] + s_hi[c0 - 1]) - 0.5 * (s_lo[c0] + s_hi[c0]) <= ortol)
+          --c0;
+        double* yj = Y + (size_t)j * ldy;
+        for (int i0 = c0; i0 < j; ++i0) {
+          const double* yi = Y + (size_t)i0 * ldy;
+          double dp = 0.0;
+          for (int r = lane; r < N; r += 64) dp += yi[r] * yj[r];
+          dp = wave_sum(dp);
+          for (int r = lane; r < N; r += 64) yj[r] -= dp * yi[r];
+          __threadfence_block();
+        }
+        double nn = 0.0;
+        for (int r = lane; r < N; r += 64) nn += yj[r] * yj[r];
+        nn = wave_sum(nn);
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int r = lane; r < N; r += 64) yj[r] *= inv;
+        __threadfence_block();
+      }
     }
-    __syncthreads();
-    for (int x = tid; x < m * mk; x += nt) {
-      int r = k + 1 + x % m, j = x / m;
-      double wj = part[j] + part[mk + j] + part[2 * mk + j] + part[3 * mk + j] +
-                  part[4 * mk + j] + part[5 * mk + j] + part[6 * mk + j] + part[7 * mk + j];
-      Y[r + (size_t)j * N] -= t * Hp[pl(r, k)] * wj;
+    // Rayleigh quotients y^T T y
+    for (int j = lane; j < mk; j += 64) {
+      const double* y = Y + (size_t)j * ldy;
+      double rq = 0.0;
+      for (int i = 0; i < N; ++i) {
+        double ty = d[i] * y[i];
+        if (i > 0) ty += e[i - 1] * y[i - 1];
+        if (i + 1 < N) ty += e[i] * y[i + 1];
+        rq += y[i] * ty;
+      }
+      pv[j] = rq;
     }
-    __syncthreads();
   }
+  __syncthreads();
+  if (tid == 0) st->t_phase[3] = wall_clock64();
+
+  // ---- 4. back-transformation Z = H_0 ... H_{N-3} Y.  Columns are
+  // independent: each column is owned by a group of 8 lanes of one wave
+  // (row segments), reflectors applied in order with a 3-step shuffle sum.
+  {
+    const int g = lane >> 3, sl = lane & 7;  // 8 groups of 8 lanes per wave
+    const int ncg = (nt / 64) * 8;           // column groups in the workgroup
+    for (int j = wv * 8 + g; j - g < mk; j += ncg) {
+      const bool act = j < mk;
+      double* __restrict__ y = Y + (size_t)(act ? j : 0) * ldy;
+      for (int k = N - 3; k >= 0; --k) {
+        const double t = tau[k];
+        if (t == 0.0) continue;
+        double dp = 0.0;
+        if (act)
+          for (int r = k + 1 + sl; r < N; r += 8) dp += H.low(r, k) * y[r];
+        dp += __shfl_xor(dp, 1, 64);
+        dp += __shfl_xor(dp, 2, 64);
+        dp += __shfl_xor(dp, 4, 64);
+        dp *= t;
+        if (act)
+          for (int r = k + 1 + sl; r < N; r += 8) y[r] -= dp * H.low(r, k);
+      }
+    }
+  }
+  __syncthreads();
   if (tid == 0) st->t_phase[4] = wall_clock64();
   // ---- outputs: C = Z (N x mk), Ritz values descending
   for (int x = tid; x < N * mk; x += nt) {
-    int i = x % N, j = x / N;
-    a.C[i + (size_t)j * a.ldc] = Y[x];
+    const int i = x % N, j = x / N;
+    a.C[i + (size_t)j * a.ldc] = Y[i + (size_t)j * ldy];
   }
-  for (int j = tid; j < mk; j += nt) st->theta[j] = theta[j];
+  for (int j = tid; j < mk; j += nt) st->theta[j] = pv[j];
   if (tid == 0) {
     st->npos_rr = s_npos;
     st->mk = mk;
@@ -383,12 +457,21 @@ __global__ __launch_bounds__(kTriThreads) void k_rr_tri(RRArgs a) {
 
 static int g_tri_lds_limit = 56 * 1024;
 
-hipError_t launch_rr_tri(const RRArgs& a, int Np_host, int mk_host, hipStream_t st) {
-  size_t N = Np_host, mk = std::min(mk_host, Np_host);
-  size_t need = N * (N + 1) / 2 + 13 * N + N * mk + kTriThreads / 2 + 16;
-  size_t bytes = sizeof(double) * need;
-  if (bytes > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_rr_tri, dim3(1), dim3(kTriThreads), bytes, st, a);
+hipError_t launch_rr_tri(const RRArgs& a_in, int Np_host, int mk_host, hipStream_t st) {
+  RRArgs a = a_in;
+  const size_t N = Np_host, mk = std::min(mk_host, Np_host);
+  const bool full = Np_host <= kFullMaxN;
+  const size_t hsz = full ? N * N : N * (N + 1) / 2;
+  const size_t base = hsz + 14 * N + (N + 1) * mk + (kTriThreads + 2) / 2 + 2;
+  const size_t cap = (size_t)g_tri_lds_limit / 8;
+  if (base > cap) return hipErrorInvalidValue;
+  const size_t want = base + 3 * N * mk;  // U factors in LDS as well
+  const size_t doubles = want <= cap ? want : base;
+  a.lds_cap = doubles;
+  if (full)
+    hipLaunchKernelGGL(k_rr_tri<true>, dim3(1), dim3(kTriThreads), doubles * 8, st, a);
+  else
+    hipLaunchKernelGGL(k_rr_tri<false>, dim3(1), dim3(kTriThreads), doubles * 8, st, a);
   return hipGetLastError();
 }
 
@@ -397,11 +480,13 @@ hipError_t rr_tri_init() {
   if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     lim = 64 * 1024;
-  int dyn = lim - 2 * 1024;  // static LDS of k_rr_tri is below 2 KB
+  const int dyn = lim - 2 * 1024;  // static LDS of k_rr_tri is below 2 KB
   if (dyn > 0) {
     g_tri_lds_limit = dyn;
-    (void)hipFuncSetAttribute((const void*)k_rr_tri, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr_tri<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr_tri<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
   }
   (void)hipGetLastError();
   return hipSuccess;

@@ -173,6 +173,35 @@ __global__ __launch_bounds__(kSmallThreads) void k_decide_chol(DecideArgs a) {
     __syncthreads();
   }
   const int N = s_N;
+  if (a.mode == -1) {
+    // Second pass: S1 is orthonormal to first order, G = I + E.  When
+    // max|E| <= 1e-6 the Cholesky factor is I + F + O(E^2) with F the strict
+    // lower part of E plus half its diagonal, so T = L^-T = I - F^T up to
+    // O(E^2) <= 1e-12: no sequential factorization is needed.
+    double em = 0.0;
+    for (int x = tid; x < N * N; x += blockDim.x) {
+      int i = x % N, j = x / N;
+      em = fmax(em, fabs(a.G[i + (size_t)j * a.ldg] - (i == j ? 1.0 : 0.0)));
+    }
+    em = block_max(em, red);
+    if (em <= 1e-6) {
+      for (int x = tid; x < N * N; x += blockDim.x) {
+        int t = x % N, c = x / N;
+        double v = 0.0;
+        if (c == t) v = 1.0 - 0.5 * (a.G[t + (size_t)t * a.ldg] - 1.0);
+        else if (c > t) v = -a.G[c + (size_t)t * a.ldg];
+        a.T[t + (size_t)c * a.ldt] = v;
+      }
+      for (int t = tid; t < N; t += blockDim.x) {
+        a.colptr[t] = a.bases[4] + (size_t)t * a.ld;
+        st->keep_col[t] = t;
+      }
+      if (tid == 0) {
+        st->Np1 = N;  // Np and nx unchanged
+      }
+      return;
+    }
+  }
   double* Lp = lds;                      // N(N+1)/2
   double* dsc = Lp + N * (N + 1) / 2;    // N scales
   double* row = dsc + N;                 // scratch: inverse blocks + 16 x N
