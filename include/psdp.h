@@ -179,6 +179,16 @@ psdp_status psdp_project_batched(psdp_handle h, int count, const int *n,
 psdp_status psdp_full_eig_project(psdp_handle h, int n, const double *X, int ldx,
                                   double *lambda_all, double *Pi, int ldpi);
 
+/* The block product of one LOBPCG iteration on its own (paper §5.1: the
+ * O(n^2 m) term): Y = sym(X) S with sym(X) the symmetric matrix whose lower
+ * triangle is that of X, rounded to `prec` (psdp_prec), on the matrix cores
+ * (MFMA FP64, FP32, or BF16 with FP32 accumulation).  S is n x k (lds),
+ * Y is n x k (ldy), FP64 device pointers, 1 <= k <= 144.  Synchronises the
+ * handle's stream. */
+psdp_status psdp_block_product(psdp_handle h, int n, const double *X, int ldx,
+                               const double *S, int lds, int k, int prec,
+                               double *Y, int ldy);
+
 /* Static string for a status code. */
 const char *psdp_status_str(psdp_status s);
 

@@ -235,6 +235,23 @@ class Projector:
                               infos[i].status))
         return out
 
+    def block_product(self, X, S, prec="fp64", Y_out=None):
+        """Y = sym(X) S with the product kernel alone (psdp_block_product)."""
+        torch = _torch()
+        Xf = self._check_matrix(X)
+        n = Xf.shape[0]
+        Sf = fortran(S)
+        k = Sf.shape[1]
+        self._sync_stream()
+        Y = Y_out if Y_out is not None else _empty_f(n, k, Xf.device)
+        rc = self.lib.psdp_block_product(self._h, n, ctypes.c_void_p(Xf.data_ptr()), Xf.stride(1),
+                                         ctypes.c_void_p(Sf.data_ptr()), Sf.stride(1), k,
+                                         PREC[prec] if isinstance(prec, str) else int(prec),
+                                         ctypes.c_void_p(Y.data_ptr()), Y.stride(1))
+        if rc < 0:
+            raise PsdpError(rc, "psdp_block_product")
+        return Y
+
     # ------------------------------------------------------------ profiling
     def profile_enable(self, on: bool = True):
         self.lib.psdp_profile_enable(self._h, 1 if on else 0)

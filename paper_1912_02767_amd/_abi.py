@@ -24,7 +24,7 @@ EXPORTED = [
     "psdp_default_options", "psdp_create", "psdp_destroy", "psdp_set_stream",
     "psdp_workspace_bytes", "psdp_project", "psdp_project_batched",
     "psdp_full_eig_project", "psdp_status_str", "psdp_profile_enable",
-    "psdp_profile_get", "psdp_version",
+    "psdp_profile_get", "psdp_version", "psdp_block_product",
 ]
 
 
@@ -113,6 +113,9 @@ def load():
     lib.psdp_full_eig_project.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp,
                                           ctypes.c_int]
     lib.psdp_full_eig_project.restype = ctypes.c_int
+    lib.psdp_block_product.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, vp, ctypes.c_int]
+    lib.psdp_block_product.restype = ctypes.c_int
     lib.psdp_status_str.argtypes = [ctypes.c_int]
     lib.psdp_status_str.restype = ctypes.c_char_p
     lib.psdp_profile_enable.argtypes = [vp, ctypes.c_int]

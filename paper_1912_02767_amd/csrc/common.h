@@ -220,8 +220,9 @@ struct ProductArgs {
   const int* cols_dev;  // device pointer to the column count (or nullptr)
   int cols_max;         // grid bound on columns
   void* scratch;        // low-precision copy of S (bf16/fp32), size lds*cols_max*4 bytes
-  float* partial;       // split-K partial sums (fp32/fp64 scratch)
+  void* partial;        // split-K partial sums (FP64 for FP64 products, else FP32)
   size_t partial_bytes;
+  int max_slices;       // split-K slices the partial buffer holds
   const int* stop;      // device stop flag: the launch is a no-op when set
 };
 

@@ -56,6 +56,7 @@ using namespace psdp;
 namespace {
 
 constexpr int kMaxSweeps = 40;
+constexpr int kProductSlices = 8;
 
 struct ProfEntry {
   long launches = 0;
@@ -77,6 +78,8 @@ struct Workspace {
   double *X = nullptr, *R = nullptr, *P = nullptr, *AX = nullptr, *Z = nullptr;
   double *S1 = nullptr, *S2 = nullptr, *AS = nullptr;
   double *Gpart = nullptr, *G = nullptr, *T = nullptr, *C = nullptr, *rrs = nullptr;
+  void* ppart = nullptr;  // split-K partial products
+  size_t ppart_bytes = 0;
   double* log = nullptr;
   size_t log_cap = 0;
   const double** colptr = nullptr;
@@ -208,6 +211,8 @@ psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
   size_t oT = take(sizeof(double) * (size_t)NC * NC);
   size_t oC = take(sizeof(double) * (size_t)NC * NC);
   size_t oRrs = take(sizeof(double) * 5 * (size_t)NC * MC);
+  const size_t ppart_bytes = sizeof(double) * kProductSlices * (size_t)L * NC;
+  size_t oPP = take(ppart_bytes);
   size_t oLog = take(sizeof(double) * log_cap);
   size_t oPtr = take(sizeof(double*) * (size_t)NC);
   size_t oFro = take(sizeof(double) * (size_t)fro_nblk);
@@ -242,6 +247,8 @@ psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
   w.T = (double*)(base + oT);
   w.C = (double*)(base + oC);
   w.rrs = (double*)(base + oRrs);
+  w.ppart = (void*)(base + oPP);
+  w.ppart_bytes = ppart_bytes;
   w.log = (double*)(base + oLog);
   w.log_cap = log_cap;
   w.colptr = (const double**)(base + oPtr);
@@ -393,6 +400,7 @@ struct Solver {
       pa.A = amat(pprec); pa.lda = L; pa.n = n; pa.prec = pprec;
       pa.S = w.S2; pa.lds = L; pa.Y = w.AS; pa.ldy = L;
       pa.cols_dev = &w.st->Np; pa.cols_max = Nmax; pa.stop = stop;
+      pa.partial = w.ppart; pa.partial_bytes = w.ppart_bytes; pa.max_slices = kProductSlices;
       HIP_TRY(launch_product(pa, s));
     }
     // ---- projected matrix K = S2^T A S2
@@ -529,6 +537,7 @@ psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t* bytes) {
   size_t nblk = (L + kGramRows - 1) / kGramRows;
   size_t T32 = (L + 31) / 32;
   size_t b = 8 * L * L + 4 * L * L + 5 * 8 * L * MC + 3 * 8 * L * NC + 8 * nblk * NC * NC +
+             8 * 8 * L * NC +
              3 * 8 * NC * NC + 5 * 8 * NC * MC + 8 * (size_t)kMaxSweeps * (NC + 1) * (NC + 2) + 8 * NC +
              8 * T32 * (T32 + 1) / 2 + sizeof(State) + 4096;
   *bytes = b;
@@ -682,6 +691,37 @@ extern "C" psdp_status psdp_full_eig_project(psdp_handle h, int n, const double*
   if (!h || n < 1 || !X || !Pi || ldx < n || ldpi < n) return PSDP_ERR_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
   return full_eig_core(h, n, X, ldx, lambda_all, Pi, ldpi, nullptr, 0, 0, nullptr, nullptr, nullptr);
+}
+
+// --------------------------------------------------------- block product ---
+extern "C" psdp_status psdp_block_product(psdp_handle h, int n, const double* X, int ldx,
+                                          const double* S, int lds, int k, int prec, double* Y,
+                                          int ldy) {
+  if (!h || n < 1 || k < 1 || k > kMaxN || !X || !S || !Y || ldx < n || lds < n || ldy < n ||
+      prec < 0 || prec > 2)
+    return PSDP_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
+  psdp_status ps = ensure_workspace(h, n, (k + 2) / 3, prec);
+  if (ps != PSDP_OK) return ps;
+  Workspace& w = h->ws;
+  if (k > w.NC) return PSDP_ERR_CAPACITY;
+  hipStream_t s = h->stream;
+  int nb = 0;
+  HIP_TRY(launch_ingest(X, ldx, n, 1.0, w.A64, w.L, w.L, w.Alp, prec, w.fro_part, w.nonfinite, s, &nb));
+  HIP_TRY(launch_copy_cols(S, lds, w.S2, w.L, n, k, s));
+  ProductArgs pa{};
+  pa.A = prec == 0 ? (const void*)w.A64 : w.Alp; pa.lda = w.L; pa.n = n; pa.prec = prec;
+  pa.S = w.S2; pa.lds = w.L; pa.Y = w.AS; pa.ldy = w.L;
+  pa.cols_dev = nullptr; pa.cols_max = k; pa.stop = nullptr;
+  pa.partial = w.ppart; pa.partial_bytes = w.ppart_bytes; pa.max_slices = kProductSlices;
+  {
+    ProfScope pscope(h, "product", (double)product_elem_bytes(prec) * n * (double)n + 16.0 * n * k,
+                     2.0 * n * (double)n * k);
+    HIP_TRY(launch_product(pa, s));
+  }
+  HIP_TRY(launch_copy_cols(w.AS, w.L, Y, ldy, n, k, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PSDP_OK;
 }
 
 // ---------------------------------------------------------- single cone ---
