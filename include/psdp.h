@@ -92,6 +92,11 @@ typedef struct {
                             /* block outgrows m_cap, use the full eig instead     */
     int block_guard;        /* cold start block = hint + max(block_guard,         */
                             /* ceil(0.2 hint)); default 4                         */
+    int batch_variant;      /* psdp_project_batched launch shape: -1 = autotuned  */
+                            /* (default), 0..3 = a fixed variant                  */
+    int batch_graph;        /* psdp_project_batched: 1 = replay the launch        */
+                            /* sequence from a captured hipGraph (default),       */
+                            /* 0 = plain launches                                 */
 } psdp_options;
 
 typedef struct {
@@ -158,13 +163,27 @@ psdp_status psdp_project(psdp_handle h, int n, const double *X, int ldx,
 /* Project `count` independent cones of uneven size in one persistent
  * launch (paper §6.1: block-diagonal SDPs split into many smaller PSD
  * variables).  Every array argument is a HOST array of length count whose
- * elements are device pointers / sizes; cone i has order n[i] in [1, 256],
- * leading dimension n[i] for X[i], V[i] and Pi[i], and m_cap[i] <= 96.
- * m_inout[i] (host) is the warm-start width on entry and m_out on exit.
- * Cones are solved with FP32 block products and FP64 Rayleigh-Ritz
- * (opt->prec FP64 selects FP64 products).  info is a host array[count].
- * A cone whose block outgrows m_cap[i] or that does not converge is
- * reported in its info (status), the call returns the worst status. */
+ * elements are device pointers or sizes:
+ *   n[i]        order of cone i, 1 <= n[i] <= 256
+ *   X[i]        n[i] x n[i], leading dimension n[i], lower triangle read
+ *   V[i]        n[i] x m_cap[i] (leading dimension n[i]): warm start on entry
+ *               (first m_inout[i] columns), Ritz block on exit
+ *   m_cap[i]    >= 1; the block of cone i is limited to min(m_cap[i], 32, n[i])
+ *   m_inout[i]  (host) warm-start width on entry, m_out on exit; 0 = cold
+ *               start from min(m_cap[i], 32, n[i]) seeded N(0,1) columns
+ *   lambda[i]   m_cap[i] doubles: Ritz values, descending
+ *   Pi[i]       n[i] x n[i] output, both triangles, may not alias X[i]
+ * One workgroup solves one cone at a time from a queue ordered by
+ * decreasing n^2 m.  opt->side POS or AUTO approximates the positive part
+ * of every cone, NEG the positive part of -X (Moreau); FULL is rejected.
+ * opt->prec FP64 selects FP64 products, FP32 and BF16 select FP32 products;
+ * orthogonalization, Rayleigh-Ritz, the final sweeps and the bound are FP64.
+ * tol <= 0 picks 1e-8 ||X_i||_F / sqrt(2 m) per cone.  Results do not
+ * depend on the queue order or the launch shape beyond rounding of the
+ * product sums.  info is a HOST array[count]; a cone that does not converge
+ * reports PSDP_NOT_CONVERGED with its bound, a non-finite cone
+ * PSDP_ERR_NUMERICAL (its outputs untouched).  Returns the most severe
+ * status (errors first).  Synchronises the handle's stream. */
 psdp_status psdp_project_batched(psdp_handle h, int count, const int *n,
                                  const double *const *X, double *const *V,
                                  const int *m_cap, int *m_inout,

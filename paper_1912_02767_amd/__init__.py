@@ -189,12 +189,13 @@ class Projector:
         return Pi, lam
 
     def project_batched(self, Xs: Sequence, m_caps=None, Vs=None, prec="fp32", tol: float = 0.0,
-                        max_iter: int = 300, seed=None, pos_hints=None, V_bufs=None,
-                        Pi_outs=None) -> List[Result]:
-        """Many uneven cones in one persistent launch (psdp_project_batched)."""
+                        max_iter: int = 300, seed=None, side="pos", variant: int = -1,
+                        graph: bool = True, V_bufs=None, Pi_outs=None,
+                        expand_cols: int = 0) -> List[Result]:
+        """Many uneven cones (n <= 256) in one persistent launch
+        (psdp_project_batched).  m_caps[i] bounds cone i's block (at most 32)
+        and is its cold-start width; Vs[i] (n x k, or None) warm-starts it."""
         torch = _torch()
-        if not hasattr(self.lib, "psdp_project_batched"):
-            raise PsdpError(PSDP_ERR_INVALID_ARG, "psdp_project_batched not in this build")
         count = len(Xs)
         Xf = [self._check_matrix(x) for x in Xs]
         ns = [x.shape[0] for x in Xf]
@@ -202,14 +203,15 @@ class Projector:
             if x.stride(1) != x.shape[0]:
                 raise ValueError("batched cones need leading dimension n")
         self._sync_stream()
-        caps = list(m_caps) if m_caps is not None else [min(96, max(8, n // 3)) for n in ns]
+        caps = list(m_caps) if m_caps is not None else [min(32, max(1, n)) for n in ns]
         if V_bufs is None:
             V_bufs = [_empty_f(n, c, x.device) for n, c, x in zip(ns, caps, Xf)]
         m_in = [0] * count
         if Vs is not None:
             for i, v in enumerate(Vs):
                 if v is not None and v.shape[1] > 0:
-                    V_bufs[i][:, :v.shape[1]].copy_(v)
+                    if V_bufs[i].data_ptr() != v.data_ptr():
+                        V_bufs[i][:, :v.shape[1]].copy_(v)
                     m_in[i] = v.shape[1]
         lams = [torch.empty(c, dtype=torch.float64, device=x.device) for c, x in zip(caps, Xf)]
         Pis = Pi_outs if Pi_outs is not None else [_empty_f(n, n, x.device) for n, x in zip(ns, Xf)]
@@ -222,11 +224,13 @@ class Projector:
         V_arr = PA(*[v.data_ptr() for v in V_bufs])
         L_arr = PA(*[l.data_ptr() for l in lams])
         P_arr = PA(*[p.data_ptr() for p in Pis])
-        opt = _opts(self.lib, "pos", prec, tol, max_iter, True, True, seed)
-        infos = (_abi.Info * count)()
+        opt = _opts(self.lib, side, prec, tol, max_iter, True, True, seed, expand_cols=expand_cols)
+        opt.batch_variant = int(variant)
+        opt.batch_graph = 1 if graph else 0
+        infos = (_abi.Info * max(count, 1))()
         rc = self.lib.psdp_project_batched(self._h, count, n_arr, X_arr, V_arr, cap_arr, mio,
                                            L_arr, P_arr, ctypes.byref(opt), infos)
-        if rc < 0:
+        if rc < 0 and rc != PSDP_ERR_NUMERICAL:
             raise PsdpError(rc, "psdp_project_batched")
         out = []
         for i in range(count):

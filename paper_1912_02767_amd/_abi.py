@@ -43,6 +43,8 @@ class Options(ctypes.Structure):
         ("pos_hint", ctypes.c_int),
         ("fallback_full", ctypes.c_int),
         ("block_guard", ctypes.c_int),
+        ("batch_variant", ctypes.c_int),
+        ("batch_graph", ctypes.c_int),
     ]
 
 

@@ -200,6 +200,26 @@ struct RRArgs {
   State* st;
 };
 
+struct RRShared {
+  double* lo;
+  double* hi;
+  int* npos;
+  double* tnorm;
+  double* pivmin;
+};
+struct CholShared {
+  int* list;
+  int* kind;
+  int* col;
+  int* keep;
+  int* N;
+  int* Np;
+  int* nx;
+  int* stop;
+  int* drop;
+  double* piv;
+  double* red;  // blockDim.x / 64 doubles
+};
 hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st);
 hipError_t launch_rr(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
 hipError_t launch_rr_tri(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);

@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "../../include/psdp.h"
+#include "batched.h"
 #include "common.h"
 
 namespace psdp {
@@ -49,6 +50,16 @@ hipError_t launch_update(const double* S, const double* AS, int lds, const doubl
 hipError_t launch_rebuild(const double* V, int ldv, const double* lt, int mt, int n,
                           const double* base, int ldb, double base_sign, double* Pi, int ldpi,
                           hipStream_t st);
+// batched engine (batched_host.cpp)
+struct BatchEngine;
+BatchEngine* batch_engine_new(int device);
+void batch_engine_free(BatchEngine* e);
+double batch_engine_last_ms(const BatchEngine* e);
+int batch_engine_last_variant(const BatchEngine* e);
+psdp_status batch_engine_run(BatchEngine* e, hipStream_t s, int count, const int* n,
+                             const double* const* X, double* const* V, const int* m_cap,
+                             int* m_inout, double* const* lambda, double* const* Pi,
+                             const psdp_options& opt, psdp_info* info);
 }  // namespace psdp
 
 using namespace psdp;
@@ -111,6 +122,7 @@ struct psdp_handle_s {
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> event_pool;
+  psdp::BatchEngine* batch = nullptr;
 };
 
 namespace {
@@ -528,6 +540,8 @@ void psdp_default_options(psdp_options* o) {
   o->pos_hint = -1;
   o->fallback_full = 0;
   o->block_guard = 4;
+  o->batch_variant = -1;
+  o->batch_graph = 1;
 }
 
 psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t* bytes) {
@@ -579,6 +593,7 @@ psdp_status psdp_destroy(psdp_handle h) {
   if (h->h_state) hipHostFree(h->h_state);
   if (h->h_pin) hipHostFree(h->h_pin);
   if (h->rb) rocblas_destroy_handle(h->rb);
+  batch_engine_free(h->batch);
   delete h;
   return PSDP_OK;
 }
@@ -733,6 +748,52 @@ static void fill_info_defaults(psdp_info* info) {
   info->pi_fro = NAN;
   info->theta_guard = NAN;
   info->n_pos_full = -1;
+}
+
+extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int* n,
+                                            const double* const* X, double* const* V,
+                                            const int* m_cap, int* m_inout,
+                                            double* const* lambda, double* const* Pi,
+                                            const psdp_options* opt_in, psdp_info* info) {
+  psdp_options opt;
+  if (opt_in) opt = *opt_in; else psdp_default_options(&opt);
+  // ---- validation (no launch before this point)
+  if (!h || count < 0) return PSDP_ERR_INVALID_ARG;
+  if (count == 0) return PSDP_OK;
+  if (!n || !X || !V || !m_cap || !m_inout || !lambda || !Pi || !info) return PSDP_ERR_INVALID_ARG;
+  if (opt.side < 0 || opt.side > 2 || opt.prec < 0 || opt.prec > 2) return PSDP_ERR_INVALID_ARG;
+  if (opt.max_iter < 1 || opt.certify != 0 || opt.expand_cols < 0 || opt.batch_variant < -1)
+    return PSDP_ERR_INVALID_ARG;
+  if (opt.prec == PSDP_PREC_BF16) opt.prec = PSDP_PREC_FP32;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > kBatchMaxN || m_cap[i] < 1) return PSDP_ERR_INVALID_ARG;
+    if (m_inout[i] < 0 || m_inout[i] > m_cap[i]) return PSDP_ERR_INVALID_ARG;
+    if (!X[i] || !V[i] || !lambda[i] || !Pi[i]) return PSDP_ERR_INVALID_ARG;
+    if ((const void*)Pi[i] == (const void*)X[i]) return PSDP_ERR_INVALID_ARG;
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
+  if (!h->batch) h->batch = batch_engine_new(h->device);
+  if (!h->batch) return PSDP_ERR_OUT_OF_MEMORY;
+  h->calls += 1;
+  psdp_status rc;
+  size_t first = h->pending.size();
+  {
+    ProfScope pscope(h, "batched");
+    rc = batch_engine_run(h->batch, h->stream, count, n, X, V, m_cap, m_inout, lambda, Pi, opt, info);
+  }
+  if (h->prof && h->pending.size() > first) {
+    // algorithmic traffic: X read, Pi written, V read and written; flops of
+    // the iterations: product 2 n^2 (3m) + Gram/orthogonalization ~ 10 n (3m)^2
+    double bytes = 0.0, flops = 0.0;
+    for (int i = 0; i < count; ++i) {
+      const double nn = n[i], mm = std::min(std::min(m_cap[i], kBatchMaxM), n[i]);
+      bytes += 16.0 * nn * nn + 16.0 * nn * mm;
+      flops += (double)std::max(info[i].iters, 0) * (6.0 * nn * nn * mm + 90.0 * nn * mm * mm);
+    }
+    h->pending.back().bytes = bytes;
+    h->pending.back().flops = flops;
+  }
+  return rc;
 }
 
 extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int ldx, double* V,
