@@ -2,18 +2,31 @@
 """Benchmark: warm-started PSD projections/s on one MI355X, against the on-GPU
 full eigendecomposition path at relative Frobenius error <= 1e-6.
 
-Default workload (one step = one warm-started projection of the next matrix):
-  n1000_warm_seq  n = 1000, X_0 = Q diag(lam) Q^T with 20 eigenvalues in
-                  [0.5, 5] and 980 in [-5, -0.01], X_{k+1} = X_k + E_k with
+Workloads (one step = one pass of the whole projection path):
+  n1000_warm_seq  (default) n = 1000, X_0 = Q diag(lam) Q^T with 20 eigenvalues
+                  in [0.5, 5] and 980 in [-5, -0.01], X_{k+1} = X_k + E_k with
                   ||E_k||_F = 1e-3 * 0.98^k * ||X_k||_F, 200 matrices, block 24,
-                  tolerance 1e-8, FP64 products.
-  --workload n4000_mixed: n = 4000, Householder basis, 40 positive
-                  eigenvalues, 50 warm-started steps at 1e-4 ||X||_F,
-                  FP32 (or --prec bf16) products, FP64 ortho/RR/refinement.
+                  tolerance 1e-8, FP64 products; a step is one warm-started
+                  projection of the next matrix.
+  n4000_mixed     n = 4000, Householder basis, 40 positive eigenvalues, 50
+                  warm-started steps X_{k+1} = X_k + E_k, ||E_k||_F = 1e-4 ||X_k||_F,
+                  FP32 (or --prec bf16) products, FP64 orthogonalization /
+                  Rayleigh-Ritz / refinement.  The random walk moves hundreds of
+                  eigenvalues of the -1e-3 cluster across zero within a few steps;
+                  once the positive count outgrows the 48-column block the side
+                  rule sends the step to the exact full eigendecomposition.
+  n4000_mixed_iid the same cone with X_k = X_0 + E_k (independent perturbations
+                  of size 1e-4 ||X_0||_F): the positive count stays 40.
+  batched512      512 cones, n_i uniform in [16, 256], 10% positive spectrum;
+                  a step is one persistent launch projecting all 512 (FP32
+                  products, FP64 Rayleigh-Ritz).
 
-Prints ONE JSON line (rank 0).  Inputs are generated on the host (seeded) and
-uploaded before the timed region.  The cpu_baseline leg times the FP64 Jacobi
-oracle on a bounded sample of the same matrices.
+Prints ONE JSON line.  Inputs are generated on the host (seeded) and
+uploaded before the timed region.  The cpu_baseline leg times the FP64
+Jacobi oracle on a bounded sample of the same matrices.
+
+--copy-probe B runs only a plain device copy of B MiB (ten times) and
+exits: the reference kernel for scaling the HBM byte counters of a profile.
 """
 from __future__ import annotations
 
@@ -32,84 +45,99 @@ import numpy as np  # noqa: E402
 PEAKS = {  # MI355X published dense peaks
     "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
 }
+FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rebuild", "ingest", "batched"]
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_inputs(workload, steps_total):
+def roofline(fams, prec):
+    """Dominant kernel family: algorithmic bytes or flops per launch divided
+    by its average launch time (hipEvents on the launching stream)."""
+    dom = max(fams, key=lambda f: fams[f]["ms"])
+    fd = fams[dom]
+    avg_ms = fd["ms"] / max(1, fd["launches"])
+    flops_l = fd["flops"] / max(1, fd["launches"])
+    bytes_l = fd["bytes"] / max(1, fd["launches"])
+    if dom == "product":
+        pk = PEAKS[prec]
+        ai = flops_l / max(bytes_l, 1.0)
+        if ai >= pk / PEAKS["hbm"]:
+            roof = {"bound": "mfma", "achieved": flops_l / (avg_ms * 1e-3) / 1e12,
+                    "peak": pk / 1e12, "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": bytes_l / (avg_ms * 1e-3) / 1e9,
+                    "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s"}
+    elif dom in ("gram", "tsmm", "rebuild", "ingest"):
+        roof = {"bound": "hbm", "achieved": bytes_l / (avg_ms * 1e-3) / 1e9,
+                "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s"}
+    else:  # one-workgroup FP64 kernels and the batched engine: vector ALU
+        roof = {"bound": "alu", "achieved": flops_l / (avg_ms * 1e-3) / 1e12,
+                "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = avg_ms
+    return roof
+
+
+def kernels_table(fams):
+    return {f: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                "gflop": round(v["flops"] / 1e9, 3), "gbyte": round(v["bytes"] / 1e9, 3)}
+            for f, v in fams.items() if v["launches"]}
+
+
+# ----------------------------------------------------------- sequences ---
+def make_sequence(workload, steps_total):
     from workloads import large_cone_sequence, warm_sequence
     if workload == "n1000_warm_seq":
         seq = warm_sequence(n=1000, n_pos=20, steps=steps_total)
         c0 = next(seq)
-        return 1000, 20, [c0.X] + list(seq), {"Pi0": c0.sandwich(np.maximum(c0.lam, 0))}
-    seq = large_cone_sequence(n=4000, n_pos=40, steps=steps_total)
+        return 1000, 20, [c0.X] + list(seq), c0.lam
+    seq = large_cone_sequence(n=4000, n_pos=40, steps=steps_total,
+                              cumulative=(workload == "n4000_mixed"))
     X0, lam, basis = next(seq)
-    mats = [X0]
-    for X in seq:
-        mats.append(X)
-    return 4000, 40, mats, {"Pi0": basis.sandwich(np.maximum(lam, 0))}
+    return 4000, 40, [X0] + list(seq), lam
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="n1000_warm_seq",
-                    choices=["n1000_warm_seq", "n4000_mixed"])
-    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--full-eig-samples", type=int, default=None)
-    ap.add_argument("--oracle-samples", type=int, default=None)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (the projection of one cone "
-              "runs on one device); --gpus must be 1", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_1912_02767_amd as psdp
-
+def run_sequence(args, torch, psdp):
     wl = args.workload
-    big = wl == "n4000_mixed"
+    big = wl.startswith("n4000")
     total = 50 if big else 200
     warm = max(0, args.warmup)
     steps = args.steps if args.steps is not None else total - warm
     steps = max(1, min(steps, total - warm))
     prec = args.prec or ("fp32" if big else "fp64")
     t_gen = time.time()
-    n, p, mats, extra = make_inputs(wl, warm + steps)
+    n, p, mats, lam0 = make_sequence(wl, warm + steps)
     log(f"generated {len(mats)} matrices n={n} in {time.time() - t_gen:.1f}s")
     dev = torch.device("cuda", 0)
     Xs = [torch.from_numpy(np.asfortranarray(X)).to(dev) for X in mats]
     torch.cuda.synchronize()
-    nrm_pi0 = float(np.linalg.norm(extra["Pi0"]))
     if big:
-        tol = 1e-7 * nrm_pi0 / math.sqrt(2 * p)   # sqrt(2 m~) tol <= 1e-7 ||Pi||
-        m_cap, block = 56, 48
+        # sqrt(2 m~) tol <= 1e-7 ||Pi||; ||Pi_0||_F from the construction
+        nrm_pi0 = float(np.linalg.norm(np.maximum(lam0, 0)))
+        tol = 1e-7 * nrm_pi0 / math.sqrt(2 * p)
+        m_cap, block = 48, 48
     else:
         tol, m_cap, block = 1e-8, 24, 24
 
     proj = psdp.Projector(0)
-    sess = psdp.Session(proj, n, m_cap=m_cap, tol=tol, side="pos", pos_hint=p, prec=prec,
-                        block_guard=block - p)
+    # AUTO side with the block cost rule; a block that outgrows the cap falls
+    # back to the exact path and the next step starts from its inertia
+    sess = psdp.Session(proj, n, m_cap=m_cap, tol=tol, side="auto", pos_hint=p, prec=prec,
+                        block_guard=block - p, fallback_full=True)
     Pis = [psdp._empty_f(n, n, dev) for _ in range(2)]
-
-    # ---- warmup (untimed): the first matrices of the sequence
-    for k in range(warm):
+    for k in range(warm):  # untimed: the first matrices of the sequence
         sess.project(Xs[k], Pi_out=Pis[k % 2])
     torch.cuda.synchronize()
 
-    # ---- timed region: K warm-started projections
     proj.profile_enable(True)
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
-    infos = []
-    keep = {}
+    infos, keep = [], {}
     sample_at = {warm, warm + steps // 2, warm + steps - 1}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -123,20 +151,17 @@ def main():
             keep[k] = res.Pi.clone()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lat = np.array([a.elapsed_time(b) for a, b in ev])  # ms
-    fams = {f: proj.profile_get(f) for f in
-            ["product", "gram", "tsmm", "chol", "rr", "rebuild", "ingest"]}
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    fams = {f: proj.profile_get(f) for f in FAMILIES}
     proj.profile_enable(False)
     value = steps / wall
-    iters = np.array([inf["iters"] for inf in infos])
-    statuses = [inf["status"] for inf in infos]
 
-    # ---- on-GPU full eigendecomposition on the same matrices
+    # on-GPU full eigendecomposition of the same matrices
     n_fe = args.full_eig_samples if args.full_eig_samples is not None else (3 if big else 10)
     fe_idx = [warm + int(i * max(1, steps - 1) / max(1, n_fe - 1)) for i in range(n_fe)] if n_fe else []
     fe_idx = sorted(set(min(k, warm + steps - 1) for k in fe_idx) | set(keep))
     fe_Pi = {}
-    proj.full_eig(Xs[fe_idx[0]])  # warm the solver
+    proj.full_eig(Xs[fe_idx[0]])
     torch.cuda.synchronize()
     t_fe = 0.0
     for k in fe_idx:
@@ -151,42 +176,13 @@ def main():
     rel_vs_fe = {k: float(torch.linalg.norm(keep[k] - fe_Pi[k]) / torch.linalg.norm(fe_Pi[k]))
                  for k in keep}
 
-    # ---- dominant kernel roofline (algorithmic bytes/flops / measured time)
-    dom = max(fams, key=lambda f: fams[f]["ms"])
-    fd = fams[dom]
-    avg_ms = fd["ms"] / max(1, fd["launches"])
-    flops_l = fd["flops"] / max(1, fd["launches"])
-    bytes_l = fd["bytes"] / max(1, fd["launches"])
-    if dom == "product":
-        pk = PEAKS[prec]
-        ridge = pk / PEAKS["hbm"]
-        ai = flops_l / max(bytes_l, 1.0)
-        if ai >= ridge:
-            roof = {"bound": "mfma", "achieved": flops_l / (avg_ms * 1e-3) / 1e12, "peak": pk / 1e12,
-                    "unit": "TFLOP/s"}
-        else:
-            roof = {"bound": "hbm", "achieved": bytes_l / (avg_ms * 1e-3) / 1e9,
-                    "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s"}
-    elif dom in ("gram", "tsmm", "rebuild", "ingest"):
-        roof = {"bound": "hbm", "achieved": bytes_l / (avg_ms * 1e-3) / 1e9,
-                "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s"}
-    else:  # one-workgroup FP64 small-matrix kernels: plain vector ALU
-        roof = {"bound": "alu", "achieved": flops_l / (avg_ms * 1e-3) / 1e12,
-                "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = avg_ms
-
-    # ---- CPU oracle on a bounded sample of the same matrices
-    cpu = None
-    rel_oracle = {}
+    cpu, rel_oracle = None, {}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        n_or = args.oracle_samples if args.oracle_samples is not None else (0 if big else 3)
-        ks = sorted(keep)[:n_or] if n_or else []
-        if ks:
+        if not big:
+            n_or = args.oracle_samples if args.oracle_samples is not None else 3
+            ks = sorted(keep)[:n_or]
             t = time.perf_counter()
             for k in ks:
                 Pi_ref, _ = oracle.project(mats[k])
@@ -196,53 +192,187 @@ def main():
                    "kind": "oracle",
                    "sample": f"{len(ks)} of the timed matrices (steps {ks}), FP64 cyclic Jacobi + clip"}
         else:
-            # n = 4000: one Jacobi sweep on X_0 scaled by the sweep count the
-            # same family needs at n = 1000 is not an oracle run; time the
-            # oracle on the step-0 matrix's leading 1000 x 1000 block instead
             sub = np.asfortranarray(mats[0][:1000, :1000])
             t = time.perf_counter()
             oracle.project(sub)
             dt = time.perf_counter() - t
             scale = (n / 1000.0) ** 3
-            cpu = {"value": 1.0 / (dt * scale), "unit": "projections/s", "cores": oracle.num_threads(),
-                   "kind": "oracle",
+            cpu = {"value": 1.0 / (dt * scale), "unit": "projections/s",
+                   "cores": oracle.num_threads(), "kind": "oracle",
                    "sample": "oracle on the leading 1000x1000 block of X_0, time scaled by (4000/1000)^3"}
-    # step 0 exact (construction closed form) when the timed region covers it
+    iters = np.array([inf["iters"] for inf in infos])
     out = {
-        "metric": "warm-started PSD projections/s vs full-eig at rel err <=1e-6; p50/p99 latency",
-        "value": value,
-        "unit": "projections/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": warm,
-        "ms_per_step": 1e3 * wall / steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "value": value, "steps": steps, "warmup": warm, "ms_per_step": 1e3 * wall / steps,
         "dtype": prec,
-        "data": "synthetic (seeded prescribed-spectrum matrices; SDPLIB is not available)",
         "config": {"workload": wl, "n": n, "n_pos": p, "block": block, "tol": tol,
-                   "matrices": len(mats), "products": prec,
-                   "ortho_rr_refine": "fp64"},
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "iters_mean": float(iters.mean()),
-        "iters_max": int(iters.max()),
-        "status_ok": int(sum(1 for s_ in statuses if s_ == 0)),
+                   "matrices": len(mats), "products": prec, "ortho_rr_refine": "fp64"},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+        "status_ok": int(sum(1 for inf in infos if inf["status"] == 0)),
+        "steps_full_eig": int(sum(1 for inf in infos if inf["side_used"] == 3)),
+        "n_pos_last": int(infos[-1]["n_pos_full"] if infos[-1]["side_used"] == 3
+                          else infos[-1]["n_pos"]),
         "full_eig": {"value": fe_rate, "unit": "projections/s", "method": "rocsolver_dsyevd",
                      "samples": len(fe_idx)},
         "speedup_vs_full_eig": value / fe_rate,
         "rel_err_vs_full_eig_max": max(rel_vs_fe.values()) if rel_vs_fe else None,
         "rel_err_vs_oracle_max": max(rel_oracle.values()) if rel_oracle else None,
-        "err_bound_rel_max": max(inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in infos),
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "kernels": {f: {"launches": v["launches"], "ms": round(v["ms"], 3),
-                        "gflop": round(v["flops"] / 1e9, 3), "gbyte": round(v["bytes"] / 1e9, 3)}
-                    for f, v in fams.items()},
+        "err_bound_rel_max": max(inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in infos
+                                 if inf["side_used"] != 3) if any(inf["side_used"] != 3 for inf in infos) else 0.0,
+        "roofline": roofline(fams, prec), "cpu_baseline": cpu, "kernels": kernels_table(fams),
     }
-    print(json.dumps(out), flush=True)
     proj.close()
+    return out
+
+
+# -------------------------------------------------------------- batched ---
+def batch_caps(cones):
+    out = []
+    for c in cones:
+        p = int((c.lam > 0).sum())
+        out.append(min(32, c.X.shape[0], p + max(4, math.ceil(0.2 * p))))
+    return out
+
+
+def run_batched(args, torch, psdp):
+    from workloads import batched_cones
+    warm = max(1, args.warmup)
+    steps = args.steps if args.steps is not None else 10
+    prec = args.prec or "fp32"
+    t_gen = time.time()
+    cones = batched_cones(count=512)
+    caps = batch_caps(cones)
+    log(f"generated 512 cones in {time.time() - t_gen:.1f}s")
+    dev = torch.device("cuda", 0)
+    Xs = [torch.from_numpy(np.asfortranarray(c.X)).to(dev) for c in cones]
+    ns = [c.X.shape[0] for c in cones]
+    Vb = [psdp._empty_f(n, c, dev) for n, c in zip(ns, caps)]
+    Pb = [psdp._empty_f(n, n, dev) for n in ns]
+    proj = psdp.Projector(0)
+    for _ in range(warm):  # first call autotunes the launch shape
+        res = proj.project_batched(Xs, m_caps=caps, prec=prec, V_bufs=Vb, Pi_outs=Pb)
+    torch.cuda.synchronize()
+    proj.profile_enable(True)
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t = time.perf_counter()
+        res = proj.project_batched(Xs, m_caps=caps, prec=prec, V_bufs=Vb, Pi_outs=Pb)
+        lat.append(1e3 * (time.perf_counter() - t))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fams = {f: proj.profile_get(f) for f in FAMILIES}
+    proj.profile_enable(False)
+    value = 512 * steps / wall
+    infos = [r.info for r in res]
+    variant, kernel_ms = proj.batched_tuning()
+
+    # full eigendecomposition, one cone after another (the plain path)
+    n_fe = args.full_eig_samples if args.full_eig_samples is not None else 128
+    idx = list(range(0, 512, max(1, 512 // n_fe)))[:n_fe]
+    proj.full_eig(Xs[idx[0]])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fe = {}
+    for i in idx:
+        fe[i], _ = proj.full_eig(Xs[i])
+    torch.cuda.synchronize()
+    fe_rate = len(idx) / (time.perf_counter() - t)
+    rel_fe = max(float(torch.linalg.norm(res[i].Pi - fe[i]) / max(torch.linalg.norm(fe[i]), 1e-300))
+                 for i in idx)
+
+    cpu, rel_oracle = None, []
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        n_or = args.oracle_samples if args.oracle_samples is not None else 64
+        sidx = list(range(0, 512, max(1, 512 // n_or)))[:n_or]
+        t = time.perf_counter()
+        for i in sidx:
+            Pi_ref, _ = oracle.project(cones[i].X)
+            rel_oracle.append(oracle.rel_error(res[i].Pi.cpu().numpy(), Pi_ref))
+        dt = time.perf_counter() - t
+        cpu = {"value": len(sidx) / dt, "unit": "projections/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{len(sidx)} of the 512 cones (every {512 // n_or}th), FP64 cyclic Jacobi + clip"}
+    iters = np.array([inf["iters"] for inf in infos])
+    out = {
+        "value": value, "steps": steps, "warmup": warm, "ms_per_step": 1e3 * wall / steps,
+        "dtype": prec,
+        "config": {"workload": "batched512", "cones": 512, "n_range": [16, 256],
+                   "sum_n2": int(sum(n * n for n in ns)), "products": prec, "rr": "fp64",
+                   "launch_variant": variant, "kernel_ms_last": kernel_ms},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+        "status_ok": int(sum(1 for inf in infos if inf["status"] == 0)),
+        "full_eig": {"value": fe_rate, "unit": "projections/s",
+                     "method": "rocsolver_dsyevd one cone at a time", "samples": len(idx)},
+        "speedup_vs_full_eig": value / fe_rate,
+        "rel_err_vs_full_eig_max": rel_fe,
+        "rel_err_vs_oracle_max": max(rel_oracle) if rel_oracle else None,
+        "err_bound_rel_max": max(inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in infos),
+        "roofline": roofline(fams, prec), "cpu_baseline": cpu, "kernels": kernels_table(fams),
+    }
+    proj.close()
+    return out
+
+
+def copy_probe(mib, torch):
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "launches": 10}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="n1000_warm_seq",
+                    choices=["n1000_warm_seq", "n4000_mixed", "n4000_mixed_iid", "batched512"])
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--full-eig-samples", type=int, default=None)
+    ap.add_argument("--oracle-samples", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (each projection runs on one "
+              "device); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.copy_probe:
+        copy_probe(args.copy_probe, torch)
+        return
+    import paper_1912_02767_amd as psdp
+
+    if args.workload == "batched512":
+        body = run_batched(args, torch, psdp)
+    else:
+        body = run_sequence(args, torch, psdp)
+    out = {
+        "metric": "warm-started PSD projections/s vs full-eig at rel err <=1e-6; p50/p99 latency",
+        "value": body.pop("value"),
+        "unit": "projections/s",
+        "n_gpus": 1,
+        "steps": body.pop("steps"),
+        "warmup": body.pop("warmup"),
+        "ms_per_step": body.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": body.pop("dtype"),
+        "data": "synthetic (seeded prescribed-spectrum matrices; SDPLIB is not available)",
+        "config": body.pop("config"),
+    }
+    out.update(body)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

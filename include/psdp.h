@@ -190,6 +190,11 @@ psdp_status psdp_project_batched(psdp_handle h, int count, const int *n,
                                  double *const *lambda, double *const *Pi,
                                  const psdp_options *opt, psdp_info *info);
 
+/* Launch shape (0..3) the last psdp_project_batched call used and the
+ * device time of its launch in milliseconds (hipEvents on the handle's
+ * stream); -1 and 0 before the first call. */
+psdp_status psdp_batched_tuning(psdp_handle h, int *variant, double *last_ms);
+
 /* Exact projection through a full FP64 eigendecomposition (rocSOLVER
  * syevd), clip and rebuild: the exact fallback and the baseline path
  * (paper §1: full eigendecomposition with syevr in COSMO).

@@ -15,6 +15,7 @@ warm starting; §6: the side is chosen from the previous iterate's inertia).
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -260,12 +261,38 @@ class Projector:
     def profile_enable(self, on: bool = True):
         self.lib.psdp_profile_enable(self._h, 1 if on else 0)
 
+    def batched_tuning(self):
+        """(launch shape, kernel ms) of the last project_batched call."""
+        v = ctypes.c_int(-1)
+        ms = ctypes.c_double(0.0)
+        self.lib.psdp_batched_tuning(self._h, ctypes.byref(v), ctypes.byref(ms))
+        return v.value, ms.value
+
     def profile_get(self, family: str):
         n = ctypes.c_long()
         ms, by, fl = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self.lib.psdp_profile_get(self._h, family.encode(), ctypes.byref(n), ctypes.byref(ms),
                                   ctypes.byref(by), ctypes.byref(fl))
         return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
+
+
+def auto_side(n: int, pos_hint: int, m_cap: int, block_guard: int = 4,
+              threshold: float = 1.0 / 3.0, max_block: int = 48) -> str:
+    """The AUTO side rule of psdp_project (paper §6 plus the block cost rule):
+    the side with fewer than threshold * n eigenvalues, if the block it needs
+    fits min(m_cap, 48) columns and 6 * block < n; else the full eig."""
+    if pos_hint < 0:
+        return "full"
+    if pos_hint < threshold * n:
+        side, est = "pos", pos_hint
+    elif n - pos_hint < threshold * n:
+        side, est = "neg", n - pos_hint
+    else:
+        return "full"
+    need = est + max(block_guard, math.ceil(0.2 * est))
+    if need > min(m_cap, max_block) or 6 * need >= n:
+        return "full"
+    return side
 
 
 class Session:
@@ -294,24 +321,20 @@ class Session:
         side = self.side_mode
         hint = self.pos_hint
         if side == "auto":
-            # resolve here so that a side switch drops the (other side's) block
-            if hint < 0:
-                side = "full"
-            elif hint < self.n / 3.0:
-                side = "pos"
-            elif self.n - hint < self.n / 3.0:
-                side = "neg"
-            else:
-                side = "full"
+            # resolve here (same rule as the library's AUTO side) so that a
+            # side switch drops the other side's block
+            side = auto_side(self.n, hint, self.m_cap, self.kw.get("block_guard", 4))
         warm = self.m if (self.last_side == side and side != "full") else 0
         res = self.p.project(X, V=warm, side=side, prec=self.prec, tol=self.tol,
                              pos_hint=hint, V_buf=self.V_buf, lam_buf=self.lam_buf,
                              Pi_out=Pi_out, **self.kw)
         info = res.info
         if info["side_used"] == SIDE_FULL:
+            # the full path returns the positive eigenpairs (up to m_cap):
+            # they warm-start a later positive-side call
             self.pos_hint = info["n_pos_full"]
-            self.m = 0
-            self.last_side = "full"
+            self.m = info["m_out"]
+            self.last_side = "pos"
         else:
             self.m = info["m_out"]
             self.last_side = "pos" if info["side_used"] == SIDE_POS else "neg"

@@ -24,7 +24,7 @@ EXPORTED = [
     "psdp_default_options", "psdp_create", "psdp_destroy", "psdp_set_stream",
     "psdp_workspace_bytes", "psdp_project", "psdp_project_batched",
     "psdp_full_eig_project", "psdp_status_str", "psdp_profile_enable",
-    "psdp_profile_get", "psdp_version", "psdp_block_product",
+    "psdp_profile_get", "psdp_version", "psdp_block_product", "psdp_batched_tuning",
 ]
 
 
@@ -122,6 +122,8 @@ def load():
     lib.psdp_status_str.restype = ctypes.c_char_p
     lib.psdp_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.psdp_profile_enable.restype = ctypes.c_int
+    lib.psdp_batched_tuning.argtypes = [vp, ip, dp]
+    lib.psdp_batched_tuning.restype = ctypes.c_int
     lib.psdp_profile_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp, dp, dp]
     lib.psdp_profile_get.restype = ctypes.c_int
     lib.psdp_version.argtypes = []

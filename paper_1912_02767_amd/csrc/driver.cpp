@@ -796,6 +796,13 @@ extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int*
   return rc;
 }
 
+extern "C" psdp_status psdp_batched_tuning(psdp_handle h, int* variant, double* last_ms) {
+  if (!h || !variant || !last_ms) return PSDP_ERR_INVALID_ARG;
+  *variant = batch_engine_last_variant(h->batch);
+  *last_ms = batch_engine_last_ms(h->batch);
+  return PSDP_OK;
+}
+
 extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int ldx, double* V,
                                     int ldv, int m_cap, int* m_inout, double* lambda, double* Pi,
                                     int ldpi, const psdp_options* opt_in, psdp_info* info) {
@@ -823,6 +830,14 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     else if (opt.pos_hint < opt.side_threshold * n) side = PSDP_SIDE_POS;
     else if (n - opt.pos_hint < opt.side_threshold * n) side = PSDP_SIDE_NEG;
     else side = PSDP_SIDE_FULL;
+    if (side != PSDP_SIDE_FULL) {
+      // cost rule: the block the estimate needs must fit the capacity, and a
+      // trial basis of 3m columns must stay well below n (paper §5.1: the
+      // O(n^2 m) iteration only pays off for m << n)
+      const int est = (side == PSDP_SIDE_POS) ? opt.pos_hint : n - opt.pos_hint;
+      const int need = est + std::max(opt.block_guard, (int)std::ceil(0.2 * est));
+      if (need > std::min(m_cap, kMaxM) || 6 * need >= n) side = PSDP_SIDE_FULL;
+    }
   }
   const int mcap = std::min(std::min(m_cap, kMaxM), n);
   if (side == PSDP_SIDE_FULL) {

@@ -164,14 +164,21 @@ def large_cone(n: int = 4000, n_pos: int = 40, n_reflectors: int = 64,
 
 def large_cone_sequence(n: int = 4000, n_pos: int = 40, steps: int = 50,
                         rel: float = 1e-4, n_reflectors: int = 64,
-                        stream: int = 0) -> Iterator[np.ndarray]:
-    """Warm-start sequence on the large cone: X_{k+1} = X_k + E_k with
-    ||E_k||_F = rel * ||X_k||_F.  First item: (X_0, lam, basis)."""
-    X, lam, basis = large_cone(n, n_pos, n_reflectors, stream)
-    yield (X, lam, basis)
+                        stream: int = 0, cumulative: bool = True) -> Iterator[np.ndarray]:
+    """Warm-start sequence on the large cone.  cumulative: X_{k+1} = X_k + E_k
+    with ||E_k||_F = rel * ||X_k||_F (a random walk); otherwise
+    X_k = X_0 + E_k with ||E_k||_F = rel * ||X_0||_F (independent
+    perturbations of the same matrix).  First item: (X_0, lam, basis)."""
+    X0, lam, basis = large_cone(n, n_pos, n_reflectors, stream)
+    yield (X0, lam, basis)
     rng = rng_for(3, 1000 + stream)
+    X = X0
+    nrm0 = np.linalg.norm(X0)
     for _ in range(1, steps):
-        X = np.asfortranarray(X + sym_perturbation(n, rel * np.linalg.norm(X), rng))
+        if cumulative:
+            X = np.asfortranarray(X + sym_perturbation(n, rel * np.linalg.norm(X), rng))
+        else:
+            X = np.asfortranarray(X0 + sym_perturbation(n, rel * nrm0, rng))
         yield X
 
 
