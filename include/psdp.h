@@ -43,6 +43,7 @@ typedef enum {
     PSDP_NOT_CONVERGED = 1,      /* max_iter reached; Pi valid with its (larger)  */
                                  /* bound in info->err_bound                      */
     PSDP_FELL_BACK_FULL_EIG = 2, /* exact full eigendecomposition was used       */
+    PSDP_PENDING = 3,            /* server request not finished yet (wait/poll)  */
     PSDP_ERR_INVALID_ARG = -1,   /* bad size, pointer, stride or option          */
     PSDP_ERR_HIP = -2,           /* a HIP/ROCm call failed (e.g. no device)      */
     PSDP_ERR_OUT_OF_MEMORY = -3, /* workspace allocation failed                  */
@@ -153,8 +154,9 @@ psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t *bytes);
  *            alias X
  * Returns PSDP_OK, PSDP_NOT_CONVERGED (Pi still valid, bound larger),
  * PSDP_FELL_BACK_FULL_EIG, or an error.  info (host) is filled on return.
- * On the full-eig side, V/lambda return the eigenpairs with positive
- * eigenvalues (up to m_cap) and m_out their count. */
+ * On the full-eig side, V/lambda return the leading eigenpairs, largest
+ * first: the p positive ones and max(4, ceil(0.2 p)) more as guard columns,
+ * at most m_cap; m_out is their count and info->n_pos_full = p. */
 psdp_status psdp_project(psdp_handle h, int n, const double *X, int ldx,
                          double *V, int ldv, int m_cap, int *m_inout,
                          double *lambda, double *Pi, int ldpi,
@@ -178,7 +180,10 @@ psdp_status psdp_project(psdp_handle h, int n, const double *X, int ldx,
  * of every cone, NEG the positive part of -X (Moreau); FULL is rejected.
  * opt->prec FP64 selects FP64 products, FP32 and BF16 select FP32 products;
  * orthogonalization, Rayleigh-Ritz, the final sweeps and the bound are FP64.
- * tol <= 0 picks 1e-8 ||X_i||_F / sqrt(2 m) per cone.  Results do not
+ * tol <= 0 picks 1e-8 ||X_i||_F / sqrt(2 m) per cone.  With
+ * opt->fallback_full, cones that do not converge are projected exactly by
+ * psdp_full_eig_project_batched in the same call (status
+ * PSDP_FELL_BACK_FULL_EIG).  Results do not
  * depend on the queue order or the launch shape beyond rounding of the
  * product sums.  info is a HOST array[count]; a cone that does not converge
  * reports PSDP_NOT_CONVERGED with its bound, a non-finite cone
@@ -189,6 +194,19 @@ psdp_status psdp_project_batched(psdp_handle h, int count, const int *n,
                                  const int *m_cap, int *m_inout,
                                  double *const *lambda, double *const *Pi,
                                  const psdp_options *opt, psdp_info *info);
+
+/* Exact projection of `count` cones (n[i] <= 256) through full FP64
+ * eigendecompositions (paper §1), batched: cones are zero-padded to buckets
+ * of order round_up(n, 32) and each bucket is one batched rocSOLVER syevd.
+ * Arrays as in psdp_project_batched; V may be NULL (then m_cap, m_inout and
+ * lambda are ignored), else V[i]/lambda[i] receive the leading eigenpairs
+ * (positive ones plus max(4, ceil(0.2 p)) guard columns, at most m_cap[i])
+ * and m_inout[i] their count.  info[i].n_pos = n_pos_full = p. */
+psdp_status psdp_full_eig_project_batched(psdp_handle h, int count, const int *n,
+                                          const double *const *X, double *const *V,
+                                          const int *m_cap, int *m_inout,
+                                          double *const *lambda, double *const *Pi,
+                                          psdp_info *info);
 
 /* Launch shape (0..3) the last psdp_project_batched call used and the
  * device time of its launch in milliseconds (hipEvents on the handle's
@@ -212,6 +230,99 @@ psdp_status psdp_full_eig_project(psdp_handle h, int n, const double *X, int ldx
 psdp_status psdp_block_product(psdp_handle h, int n, const double *X, int ldx,
                                const double *S, int lds, int k, int prec,
                                double *Y, int ldy);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop for many concurrent ADMM solves (paper §6: every
+ * PSD variable is projected once per ADMM iteration, warm-started from its
+ * previous Ritz block).  A session is one such variable; its warm-start
+ * block stays in device memory owned by the server.  Requests are admitted
+ * while device-memory estimates stay within hbm_budget, run concurrently on
+ * `slots` worker streams (single-cone path) and on one batching lane that
+ * gathers every waiting small request (n <= small_n, positive side, block
+ * <= 32) into one persistent batched launch; a request the lane does not
+ * converge is redone on a worker through the full eigendecomposition.  Requests of one session run
+ * in submission order; requests of different sessions overlap on the GPU.
+ * The server owns its worker threads, handles and streams; the caller owns
+ * X and Pi of each request until psdp_server_wait reports it done.
+ * ------------------------------------------------------------------------ */
+typedef struct psdp_server_s *psdp_server;
+
+typedef struct {
+    int slots;              /* concurrent single-cone workers, default 4         */
+    size_t hbm_budget;      /* device bytes for workspaces; 0 = 16 GiB           */
+    int batch_lane;         /* 1 (default): small requests share batched launches */
+    int small_n;            /* largest order for the batching lane (<= 256)      */
+    int max_batch;          /* most requests per batched launch, default 512     */
+    psdp_options opt;       /* options of every request; side AUTO resolves per  */
+                            /* session from its last inertia; fallback_full is   */
+                            /* forced on so that every request returns Pi         */
+} psdp_server_config;
+
+typedef struct {
+    psdp_info info;         /* the projection's info                             */
+    long long ticket;
+    int session;
+    int lane;               /* 0 = single-cone worker, 1 = batching lane         */
+    int batch_size;         /* requests in its launch (1 on a worker)            */
+    double queue_ms;        /* submit -> start on the device                     */
+    double latency_ms;      /* submit -> result complete                         */
+} psdp_result;
+
+typedef struct {
+    long long submitted, completed, rejected;
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* latency of completed requests     */
+    double throughput;      /* completed / (last completion - first submission) */
+    size_t hbm_held;        /* current workspace estimate                        */
+    size_t hbm_peak;        /* its maximum                                       */
+    int active, queued;     /* requests on the device / waiting now             */
+    int max_active;         /* most requests on the device at once              */
+    long long batched_launches, batched_requests;
+    long long lane_fallbacks; /* lane results not converged, redone exactly     */
+} psdp_server_stats;
+
+/* Defaults documented above (opt from psdp_default_options). */
+void psdp_server_default_config(psdp_server_config *cfg);
+
+/* Start the worker threads on HIP device `device`. */
+psdp_status psdp_server_create(psdp_server *srv, int device, const psdp_server_config *cfg);
+
+/* Wait for every submitted request, stop the workers, free everything. */
+psdp_status psdp_server_destroy(psdp_server srv);
+
+/* Open a session of order n (1 <= n) with block capacity m_cap (<= 48) and an
+ * estimate of its positive eigenvalue count (-1: unknown, first request uses
+ * the full eig).  Allocates its device block (n x m_cap) now. */
+psdp_status psdp_server_open_session(psdp_server srv, int n, int m_cap, int pos_hint,
+                                     int *session);
+
+/* Close a session after its requests completed (PSDP_PENDING otherwise). */
+psdp_status psdp_server_close_session(psdp_server srv, int session);
+
+/* Submit Pi(X) for a session: X and Pi are n x n device matrices with
+ * leading dimension n (lower triangle of X read, both triangles of Pi
+ * written).  producer_stream (hipStream_t or NULL) is the stream that wrote
+ * X: the request waits for it.  Returns at once with *ticket. */
+psdp_status psdp_server_submit(psdp_server srv, int session, const double *X, double *Pi,
+                               void *producer_stream, long long *ticket);
+
+/* Wait up to timeout_ms (< 0: no limit) for a request; PSDP_OK fills *out
+ * (the projection's status is out->info.status), PSDP_PENDING on timeout.
+ * A ticket can be waited for until the next psdp_server_wait on it returns
+ * PSDP_OK; afterwards it is forgotten. */
+psdp_status psdp_server_wait(psdp_server srv, long long ticket, double timeout_ms,
+                             psdp_result *out);
+
+/* Wait until every submitted request has completed. */
+psdp_status psdp_server_drain(psdp_server srv);
+
+/* Copy a session's warm-start block (device, n x m, leading dim ldv) and
+ * its Ritz values (device, m) out; *m = its width.  NULL V/lambda: width only. */
+psdp_status psdp_server_session_block(psdp_server srv, int session, double *V, int ldv,
+                                      double *lambda, int *m);
+
+/* Counters and latency percentiles since creation (or the last reset). */
+psdp_status psdp_server_stats_get(psdp_server srv, psdp_server_stats *st);
+psdp_status psdp_server_stats_reset(psdp_server srv);
 
 /* Static string for a status code. */
 const char *psdp_status_str(psdp_status s);

@@ -22,12 +22,12 @@ from typing import List, Optional, Sequence
 from . import _abi
 from ._abi import (PREC_BF16, PREC_FP32, PREC_FP64, PSDP_ERR_CAPACITY,
                    PSDP_ERR_HIP, PSDP_ERR_INVALID_ARG, PSDP_ERR_NUMERICAL,
-                   PSDP_ERR_OUT_OF_MEMORY, PSDP_FELL_BACK_FULL_EIG,
+                   PSDP_ERR_OUT_OF_MEMORY, PSDP_FELL_BACK_FULL_EIG, PSDP_PENDING,
                    PSDP_NOT_CONVERGED, PSDP_OK, SIDE_AUTO, SIDE_FULL, SIDE_NEG,
                    SIDE_POS, LibraryMissing, load, status_str)
 
-__all__ = ["Projector", "Session", "Result", "PsdpError", "load", "status_str",
-           "fortran", "PREC", "SIDE", "LibraryMissing"]
+__all__ = ["Projector", "Session", "Server", "Result", "ServedResult", "PsdpError", "load",
+           "status_str", "fortran", "auto_side", "PREC", "SIDE", "LibraryMissing"]
 
 PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 SIDE = {"auto": SIDE_AUTO, "pos": SIDE_POS, "neg": SIDE_NEG, "full": SIDE_FULL}
@@ -192,7 +192,7 @@ class Projector:
     def project_batched(self, Xs: Sequence, m_caps=None, Vs=None, prec="fp32", tol: float = 0.0,
                         max_iter: int = 300, seed=None, side="pos", variant: int = -1,
                         graph: bool = True, V_bufs=None, Pi_outs=None,
-                        expand_cols: int = 0) -> List[Result]:
+                        expand_cols: int = 0, fallback_full: bool = False) -> List[Result]:
         """Many uneven cones (n <= 256) in one persistent launch
         (psdp_project_batched).  m_caps[i] bounds cone i's block (at most 32)
         and is its cold-start width; Vs[i] (n x k, or None) warm-starts it."""
@@ -225,7 +225,8 @@ class Projector:
         V_arr = PA(*[v.data_ptr() for v in V_bufs])
         L_arr = PA(*[l.data_ptr() for l in lams])
         P_arr = PA(*[p.data_ptr() for p in Pis])
-        opt = _opts(self.lib, side, prec, tol, max_iter, True, True, seed, expand_cols=expand_cols)
+        opt = _opts(self.lib, side, prec, tol, max_iter, True, True, seed, expand_cols=expand_cols,
+                    fallback_full=fallback_full)
         opt.batch_variant = int(variant)
         opt.batch_graph = 1 if graph else 0
         infos = (_abi.Info * max(count, 1))()
@@ -260,6 +261,47 @@ class Projector:
     # ------------------------------------------------------------ profiling
     def profile_enable(self, on: bool = True):
         self.lib.psdp_profile_enable(self._h, 1 if on else 0)
+
+    def full_eig_batched(self, Xs: Sequence, m_caps=None, V_bufs=None, Pi_outs=None):
+        """Exact projections of many small cones (n <= 256) in zero-padded
+        buckets (psdp_full_eig_project_batched).  With m_caps, also the
+        leading eigenpairs (positive + guard columns) per cone."""
+        torch = _torch()
+        count = len(Xs)
+        Xf = [self._check_matrix(x) for x in Xs]
+        ns = [x.shape[0] for x in Xf]
+        for x in Xf:
+            if x.stride(1) != x.shape[0]:
+                raise ValueError("batched cones need leading dimension n")
+        self._sync_stream()
+        Pis = Pi_outs if Pi_outs is not None else [_empty_f(n, n, x.device) for n, x in zip(ns, Xf)]
+        IA = ctypes.c_int * max(count, 1)
+        PA = ctypes.c_void_p * max(count, 1)
+        infos = (_abi.Info * max(count, 1))()
+        lams = None
+        if m_caps is not None:
+            if V_bufs is None:
+                V_bufs = [_empty_f(n, c, x.device) for n, c, x in zip(ns, m_caps, Xf)]
+            lams = [torch.empty(c, dtype=torch.float64, device=x.device) for c, x in zip(m_caps, Xf)]
+            mio = IA(*([0] * count))
+            rc = self.lib.psdp_full_eig_project_batched(
+                self._h, count, IA(*ns), PA(*[x.data_ptr() for x in Xf]),
+                PA(*[v.data_ptr() for v in V_bufs]), IA(*m_caps), mio,
+                PA(*[l.data_ptr() for l in lams]), PA(*[p.data_ptr() for p in Pis]), infos)
+        else:
+            mio = IA(*([0] * count))
+            rc = self.lib.psdp_full_eig_project_batched(
+                self._h, count, IA(*ns), PA(*[x.data_ptr() for x in Xf]), None, None, None, None,
+                PA(*[p.data_ptr() for p in Pis]), infos)
+        if rc < 0 and rc != PSDP_ERR_NUMERICAL:
+            raise PsdpError(rc, "psdp_full_eig_project_batched")
+        out = []
+        for i in range(count):
+            mo = mio[i] if m_caps is not None else 0
+            V = V_bufs[i][:, :mo] if m_caps is not None else None
+            lam = lams[i][:mo] if lams is not None else None
+            out.append(Result(Pis[i], V, lam, infos[i].as_dict(), infos[i].status))
+        return out
 
     def batched_tuning(self):
         """(launch shape, kernel ms) of the last project_batched call."""
@@ -342,3 +384,125 @@ class Session:
             self.pos_hint = np_side if self.last_side == "pos" else self.n - np_side
         self.calls += 1
         return res
+
+
+@dataclass
+class ServedResult:
+    Pi: object          # (n, n) float64 projection written by the server
+    info: dict
+    status: int
+    session: int
+    lane: int           # 0 single-cone worker, 1 batching lane
+    batch_size: int
+    queue_ms: float
+    latency_ms: float
+
+
+class Server:
+    """Request loop over many sessions (psdp_server_*): device-resident
+    warm-start blocks, admission by device-memory footprint, worker streams
+    and a batching lane for small requests (continuous batching)."""
+
+    def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0,
+                 batch_lane: bool = True, small_n: int = 256, max_batch: int = 512,
+                 prec="fp32", tol: float = 0.0, max_iter: int = 300, seed=None,
+                 block_guard: int = 4):
+        self.lib = load()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise PsdpError(PSDP_ERR_HIP, "Server: no GPU visible")
+        self.device = int(device)
+        cfg = _abi.ServerConfig()
+        self.lib.psdp_server_default_config(ctypes.byref(cfg))
+        cfg.slots = int(slots)
+        cfg.hbm_budget = int(hbm_budget)
+        cfg.batch_lane = 1 if batch_lane else 0
+        cfg.small_n = int(small_n)
+        cfg.max_batch = int(max_batch)
+        cfg.opt = _opts(self.lib, "auto", prec, tol, max_iter, True, True, seed,
+                        block_guard=block_guard)
+        self._s = ctypes.c_void_p()
+        rc = self.lib.psdp_server_create(ctypes.byref(self._s), self.device, ctypes.byref(cfg))
+        if rc != 0:
+            raise PsdpError(rc, "psdp_server_create")
+        self._live = {}     # ticket -> (X, Pi) kept alive until the result is read
+        self._n = {}
+
+    def open_session(self, n: int, m_cap: int = 48, pos_hint: int = -1) -> int:
+        sid = ctypes.c_int()
+        rc = self.lib.psdp_server_open_session(self._s, int(n), int(m_cap), int(pos_hint),
+                                               ctypes.byref(sid))
+        if rc != 0:
+            raise PsdpError(rc, "psdp_server_open_session")
+        self._n[sid.value] = int(n)
+        return sid.value
+
+    def close_session(self, sid: int) -> int:
+        return self.lib.psdp_server_close_session(self._s, int(sid))
+
+    def submit(self, sid: int, X, Pi_out=None) -> int:
+        torch = _torch()
+        n = self._n[sid]
+        Xf = fortran(X)
+        if Xf.shape != (n, n) or Xf.dtype != torch.float64 or Xf.stride(1) != n:
+            raise ValueError("X must be a float64 (n, n) matrix with leading dimension n")
+        Pi = Pi_out if Pi_out is not None else _empty_f(n, n, Xf.device)
+        t = ctypes.c_longlong()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        rc = self.lib.psdp_server_submit(self._s, int(sid), ctypes.c_void_p(Xf.data_ptr()),
+                                         ctypes.c_void_p(Pi.data_ptr()), ctypes.c_void_p(stream),
+                                         ctypes.byref(t))
+        if rc != 0:
+            raise PsdpError(rc, "psdp_server_submit")
+        self._live[t.value] = (Xf, Pi)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> Optional[ServedResult]:
+        r = _abi.ServerResult()
+        rc = self.lib.psdp_server_wait(self._s, int(ticket), float(timeout_ms), ctypes.byref(r))
+        if rc == PSDP_PENDING:
+            return None
+        if rc != 0:
+            raise PsdpError(rc, "psdp_server_wait")
+        _, Pi = self._live.pop(ticket)
+        return ServedResult(Pi, r.info.as_dict(), r.info.status, r.session, r.lane, r.batch_size,
+                            r.queue_ms, r.latency_ms)
+
+    def drain(self):
+        self.lib.psdp_server_drain(self._s)
+
+    def session_block(self, sid: int):
+        """(V, lam) copies of a session's warm-start block."""
+        torch = _torch()
+        n = self._n[sid]
+        m = ctypes.c_int()
+        rc = self.lib.psdp_server_session_block(self._s, int(sid), None, n, None, ctypes.byref(m))
+        if rc != 0:
+            raise PsdpError(rc, "psdp_server_session_block")
+        V = _empty_f(n, max(m.value, 1), torch.device("cuda", self.device))
+        lam = torch.empty(max(m.value, 1), dtype=torch.float64, device=V.device)
+        rc = self.lib.psdp_server_session_block(self._s, int(sid), ctypes.c_void_p(V.data_ptr()), n,
+                                                ctypes.c_void_p(lam.data_ptr()), ctypes.byref(m))
+        if rc != 0:
+            raise PsdpError(rc, "psdp_server_session_block")
+        return V[:, :m.value], lam[:m.value]
+
+    def stats(self) -> dict:
+        st = _abi.ServerStats()
+        self.lib.psdp_server_stats_get(self._s, ctypes.byref(st))
+        return st.as_dict()
+
+    def stats_reset(self):
+        self.lib.psdp_server_stats_reset(self._s)
+
+    def close(self):
+        if self._s:
+            self.lib.psdp_server_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

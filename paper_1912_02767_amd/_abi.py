@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libpsdp.so")
 PSDP_OK = 0
 PSDP_NOT_CONVERGED = 1
 PSDP_FELL_BACK_FULL_EIG = 2
+PSDP_PENDING = 3
 PSDP_ERR_INVALID_ARG = -1
 PSDP_ERR_HIP = -2
 PSDP_ERR_OUT_OF_MEMORY = -3
@@ -25,6 +26,10 @@ EXPORTED = [
     "psdp_workspace_bytes", "psdp_project", "psdp_project_batched",
     "psdp_full_eig_project", "psdp_status_str", "psdp_profile_enable",
     "psdp_profile_get", "psdp_version", "psdp_block_product", "psdp_batched_tuning",
+    "psdp_server_default_config", "psdp_server_create", "psdp_server_destroy",
+    "psdp_server_open_session", "psdp_server_close_session", "psdp_server_submit",
+    "psdp_server_wait", "psdp_server_drain", "psdp_server_session_block",
+    "psdp_server_stats_get", "psdp_server_stats_reset", "psdp_full_eig_project_batched",
 ]
 
 
@@ -71,6 +76,53 @@ class Info(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("slots", ctypes.c_int),
+        ("hbm_budget", ctypes.c_size_t),
+        ("batch_lane", ctypes.c_int),
+        ("small_n", ctypes.c_int),
+        ("max_batch", ctypes.c_int),
+        ("opt", Options),
+    ]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [
+        ("info", Info),
+        ("ticket", ctypes.c_longlong),
+        ("session", ctypes.c_int),
+        ("lane", ctypes.c_int),
+        ("batch_size", ctypes.c_int),
+        ("queue_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_longlong),
+        ("completed", ctypes.c_longlong),
+        ("rejected", ctypes.c_longlong),
+        ("p50_ms", ctypes.c_double),
+        ("p99_ms", ctypes.c_double),
+        ("mean_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double),
+        ("throughput", ctypes.c_double),
+        ("hbm_held", ctypes.c_size_t),
+        ("hbm_peak", ctypes.c_size_t),
+        ("active", ctypes.c_int),
+        ("queued", ctypes.c_int),
+        ("max_active", ctypes.c_int),
+        ("batched_launches", ctypes.c_longlong),
+        ("batched_requests", ctypes.c_longlong),
+        ("lane_fallbacks", ctypes.c_longlong),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -106,12 +158,14 @@ def load():
                                  ctypes.c_int, ip, vp, vp, ctypes.c_int,
                                  ctypes.POINTER(Options), ctypes.POINTER(Info)]
     lib.psdp_project.restype = ctypes.c_int
-    if hasattr(lib, "psdp_project_batched"):
-        lib.psdp_project_batched.argtypes = [vp, ctypes.c_int, ip, ctypes.POINTER(vp),
-                                             ctypes.POINTER(vp), ip, ip, ctypes.POINTER(vp),
-                                             ctypes.POINTER(vp), ctypes.POINTER(Options),
-                                             ctypes.POINTER(Info)]
-        lib.psdp_project_batched.restype = ctypes.c_int
+    lib.psdp_project_batched.argtypes = [vp, ctypes.c_int, ip, ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ip, ip, ctypes.POINTER(vp),
+                                         ctypes.POINTER(vp), ctypes.POINTER(Options),
+                                         ctypes.POINTER(Info)]
+    lib.psdp_project_batched.restype = ctypes.c_int
+    lib.psdp_full_eig_project_batched.argtypes = [vp, ctypes.c_int, ip, ctypes.POINTER(vp),
+                                                  ctypes.POINTER(vp), ip, ip, ctypes.POINTER(vp),
+                                                  ctypes.POINTER(vp), ctypes.POINTER(Info)]
     lib.psdp_full_eig_project.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, vp,
                                           ctypes.c_int]
     lib.psdp_full_eig_project.restype = ctypes.c_int
@@ -126,6 +180,31 @@ def load():
     lib.psdp_batched_tuning.restype = ctypes.c_int
     lib.psdp_profile_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp, dp, dp]
     lib.psdp_profile_get.restype = ctypes.c_int
+    llp = ctypes.POINTER(ctypes.c_longlong)
+    lib.psdp_full_eig_project_batched.restype = ctypes.c_int
+    lib.psdp_server_default_config.argtypes = [ctypes.POINTER(ServerConfig)]
+    lib.psdp_server_default_config.restype = None
+    lib.psdp_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ServerConfig)]
+    lib.psdp_server_create.restype = ctypes.c_int
+    lib.psdp_server_destroy.argtypes = [vp]
+    lib.psdp_server_destroy.restype = ctypes.c_int
+    lib.psdp_server_open_session.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip]
+    lib.psdp_server_open_session.restype = ctypes.c_int
+    lib.psdp_server_close_session.argtypes = [vp, ctypes.c_int]
+    lib.psdp_server_close_session.restype = ctypes.c_int
+    lib.psdp_server_submit.argtypes = [vp, ctypes.c_int, vp, vp, vp, llp]
+    lib.psdp_server_submit.restype = ctypes.c_int
+    lib.psdp_server_wait.argtypes = [vp, ctypes.c_longlong, ctypes.c_double,
+                                     ctypes.POINTER(ServerResult)]
+    lib.psdp_server_wait.restype = ctypes.c_int
+    lib.psdp_server_drain.argtypes = [vp]
+    lib.psdp_server_drain.restype = ctypes.c_int
+    lib.psdp_server_session_block.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ip]
+    lib.psdp_server_session_block.restype = ctypes.c_int
+    lib.psdp_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.psdp_server_stats_get.restype = ctypes.c_int
+    lib.psdp_server_stats_reset.argtypes = [vp]
+    lib.psdp_server_stats_reset.restype = ctypes.c_int
     lib.psdp_version.argtypes = []
     lib.psdp_version.restype = ctypes.c_char_p
     _lib = lib

@@ -48,6 +48,21 @@ struct BatchArgs {
   int kc;                  // k-chunk of the workgroup GEMM
 };
 
+// One cone of the batched exact path (zero-padded full eigendecomposition).
+struct EigCone {
+  const double* X;  // n x n, lower triangle read
+  double* Pi;       // n x n output
+  double* V;        // n x m_cap leading eigenvectors, or nullptr
+  double* lam;      // m_cap leading eigenvalues, or nullptr
+  int n, m_cap;
+};
+hipError_t launch_eig_pad(const EigCone* cones, int count, double* A, int nb, int* bad,
+                          hipStream_t st);
+hipError_t launch_eig_rebuild(const EigCone* cones, int count, const double* A, const double* D,
+                              int nb, hipStream_t st);
+hipError_t launch_eig_leading(const EigCone* cones, int count, const double* A, const double* D,
+                              int nb, int* out, hipStream_t st);
+
 size_t batched_scratch_bytes(int nmax, int mmax);
 size_t batched_static_lds_bytes();
 hipError_t launch_batched(const BatchArgs& a, bool rr_full, int grid, hipStream_t st);

@@ -30,6 +30,7 @@
 #include "../../include/psdp.h"
 #include "batched.h"
 #include "common.h"
+#include "internal.h"
 
 namespace psdp {
 // launchers defined in the kernel files
@@ -123,6 +124,8 @@ struct psdp_handle_s {
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> event_pool;
   psdp::BatchEngine* batch = nullptr;
+  char* beig = nullptr;  // batched exact path scratch
+  size_t beig_bytes = 0;
 };
 
 namespace {
@@ -514,6 +517,7 @@ const char* psdp_status_str(psdp_status s) {
   switch (s) {
     case PSDP_OK: return "PSDP_OK";
     case PSDP_NOT_CONVERGED: return "PSDP_NOT_CONVERGED";
+    case PSDP_PENDING: return "PSDP_PENDING";
     case PSDP_FELL_BACK_FULL_EIG: return "PSDP_FELL_BACK_FULL_EIG";
     case PSDP_ERR_INVALID_ARG: return "PSDP_ERR_INVALID_ARG";
     case PSDP_ERR_HIP: return "PSDP_ERR_HIP";
@@ -594,6 +598,7 @@ psdp_status psdp_destroy(psdp_handle h) {
   if (h->h_pin) hipHostFree(h->h_pin);
   if (h->rb) rocblas_destroy_handle(h->rb);
   batch_engine_free(h->batch);
+  if (h->beig) hipFree(h->beig);
   delete h;
   return PSDP_OK;
 }
@@ -645,15 +650,17 @@ static psdp_status full_eig_core(psdp_handle h, int n, const double* X, int ldx,
     if (h->eig_A) hipFree(h->eig_A);
     h->eig_A = nullptr;
     // the ingest writes the zero padding too: the copy is lda x lda
-    size_t b = sizeof(double) * ((size_t)lda * lda + 2 * (size_t)n + 8 + fro_n + 8) + 64;
+    // d and e are sized for any order up to lda (later calls reuse the buffer)
+    size_t b = sizeof(double) * ((size_t)lda * lda + 2 * (size_t)lda + 8 + fro_n + 8) + 64;
     if (hipMalloc(&h->eig_A, b) != hipSuccess) { h->eig_cap = 0; return PSDP_ERR_OUT_OF_MEMORY; }
     h->eig_cap = lda;
   }
+  const int cap = h->eig_cap;
   double* A = h->eig_A;
-  double* d = A + (size_t)lda * lda;
-  double* e = d + n;
-  rocblas_int* info = (rocblas_int*)(e + n);
-  double* fro_part = e + n + 8;
+  double* d = A + (size_t)cap * cap;
+  double* e = d + cap;
+  rocblas_int* info = (rocblas_int*)(e + cap);
+  double* fro_part = e + cap + 8;
   int* nonfin = (int*)(fro_part + fro_n);
   // symmetric copy (lower triangle of X) via the ingest kernel, FP64 only
   int nb = 0;
@@ -687,8 +694,9 @@ static psdp_status full_eig_core(psdp_handle h, int n, const double* X, int ldx,
                            0.0, Pi, ldpi, s));
   }
   if (V && m_out) {
-    int k = std::min(npos, m_cap);
-    // largest first
+    // the positive pairs plus the next ones as guard columns (a warm start
+    // for a later block solve), largest first
+    int k = std::min(std::min(m_cap, n), npos + std::max(4, (int)std::ceil(0.2 * npos)));
     for (int j = 0; j < k; ++j) {
       HIP_TRY(hipMemcpyAsync(V + (size_t)j * ldv, A + (size_t)(n - 1 - j) * lda, sizeof(double) * n,
                              hipMemcpyDeviceToDevice, s));
@@ -750,6 +758,134 @@ static void fill_info_defaults(psdp_info* info) {
   info->n_pos_full = -1;
 }
 
+// Exact projection of many cones (n <= 256) through zero-padded buckets of
+// order round_up(n, 32) and one batched rocSOLVER eigendecomposition per
+// bucket.  Outputs per cone i (caller's order): n_pos[i], m_out[i] (leading
+// columns written to V[i], 0 when V is null), bad[i] (non-finite input or
+// solver failure).
+static psdp_status full_eig_batched(psdp_handle h, int count, const int* n,
+                                    const double* const* X, double* const* Pi,
+                                    double* const* V, const int* m_cap, double* const* lambda,
+                                    int* m_out, int* n_pos, int* bad) {
+  hipStream_t s = h->stream;
+  if (!h->rb && rocblas_create_handle(&h->rb) != rocblas_status_success) return PSDP_ERR_HIP;
+  rocblas_set_stream(h->rb, s);
+  std::map<int, std::vector<int>> buckets;
+  for (int i = 0; i < count; ++i) buckets[round_up(n[i], 32)].push_back(i);
+  size_t maxA = 0, maxD = 0;
+  for (auto& b : buckets) {
+    maxA = std::max(maxA, (size_t)b.first * b.first * b.second.size());
+    maxD = std::max(maxD, (size_t)b.first * b.second.size());
+  }
+  const size_t oA = 0, oD = align_up(oA + 8 * maxA, 256), oE = align_up(oD + 8 * maxD, 256);
+  const size_t oC = align_up(oE + 8 * maxD, 256);
+  const size_t oI = align_up(oC + sizeof(EigCone) * count, 256);
+  const size_t oO = align_up(oI + sizeof(int) * count, 256);
+  const size_t oB = align_up(oO + 2 * sizeof(int) * count, 256);
+  const size_t total = align_up(oB + sizeof(int) * count, 256);
+  if (total > h->beig_bytes) {
+    (void)hipStreamSynchronize(s);
+    if (h->beig) hipFree(h->beig);
+    h->beig = nullptr;
+    h->beig_bytes = 0;
+    if (hipMalloc(&h->beig, total) != hipSuccess) return PSDP_ERR_OUT_OF_MEMORY;
+    h->beig_bytes = total;
+  }
+  const size_t pin = sizeof(EigCone) * count + 4 * sizeof(int) * count + 64;
+  psdp_status pp = ensure_pinned(h, pin);
+  if (pp != PSDP_OK) return pp;
+  char* base = h->beig;
+  double* A = (double*)(base + oA);
+  double* D = (double*)(base + oD);
+  double* E = (double*)(base + oE);
+  EigCone* dc = (EigCone*)(base + oC);
+  rocblas_int* dinfo = (rocblas_int*)(base + oI);
+  int* dout = (int*)(base + oO);
+  int* dbad = (int*)(base + oB);
+  EigCone* hc = (EigCone*)h->h_pin;
+  int* hint = (int*)(hc + count);  // out (2 count), bad (count), info (count)
+  std::vector<int> order;
+  order.reserve(count);
+  int q = 0;
+  for (auto& b : buckets) {
+    const int nb = b.first, cnt = (int)b.second.size();
+    for (int t = 0; t < cnt; ++t) {
+      const int i = b.second[t];
+      order.push_back(i);
+      EigCone c{};
+      c.X = X[i];
+      c.Pi = Pi[i];
+      c.V = V ? V[i] : nullptr;
+      c.lam = lambda ? lambda[i] : nullptr;
+      c.n = n[i];
+      c.m_cap = m_cap ? m_cap[i] : 0;
+      hc[q + t] = c;
+    }
+    HIP_TRY(hipMemcpyAsync(dc + q, hc + q, sizeof(EigCone) * cnt, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_eig_pad(dc + q, cnt, A, nb, dbad + q, s));
+    if (rocsolver_dsyevd_strided_batched(h->rb, rocblas_evect_original, rocblas_fill_lower, nb, A, nb,
+                                         (rocblas_stride)nb * nb, D, nb, E, nb, dinfo + q,
+                                         cnt) != rocblas_status_success)
+      return PSDP_ERR_HIP;
+    HIP_TRY(launch_eig_rebuild(dc + q, cnt, A, D, nb, s));
+    HIP_TRY(launch_eig_leading(dc + q, cnt, A, D, nb, dout + 2 * q, s));
+    q += cnt;
+  }
+  HIP_TRY(hipMemcpyAsync(hint, dout, 2 * sizeof(int) * count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hint + 2 * count, dbad, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(hint + 3 * count, dinfo, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int t = 0; t < count; ++t) {
+    const int i = order[t];
+    n_pos[i] = hint[2 * t];
+    m_out[i] = hint[2 * t + 1];
+    bad[i] = hint[2 * count + t] != 0 || hint[3 * count + t] != 0;
+  }
+  return PSDP_OK;
+}
+
+static void fill_full_info(psdp_info* f, int npos, int mo, int bad) {
+  std::memset(f, 0, sizeof(*f));
+  f->side_used = PSDP_SIDE_FULL;
+  f->n_pos = npos;
+  f->n_pos_full = npos;
+  f->m_out = mo;
+  f->status = bad ? PSDP_ERR_NUMERICAL : PSDP_OK;
+}
+
+extern "C" psdp_status psdp_full_eig_project_batched(psdp_handle h, int count, const int* n,
+                                                     const double* const* X, double* const* V,
+                                                     const int* m_cap, int* m_inout,
+                                                     double* const* lambda, double* const* Pi,
+                                                     psdp_info* info) {
+  if (!h || count < 0) return PSDP_ERR_INVALID_ARG;
+  if (count == 0) return PSDP_OK;
+  if (!n || !X || !Pi || !info) return PSDP_ERR_INVALID_ARG;
+  const bool want_v = V != nullptr;
+  if (want_v && (!m_cap || !m_inout || !lambda)) return PSDP_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > kBatchMaxN || !X[i] || !Pi[i]) return PSDP_ERR_INVALID_ARG;
+    if ((const void*)Pi[i] == (const void*)X[i]) return PSDP_ERR_INVALID_ARG;
+    if (want_v && (!V[i] || !lambda[i] || m_cap[i] < 1)) return PSDP_ERR_INVALID_ARG;
+  }
+  if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
+  std::vector<int> mo(count, 0), np(count, 0), bad(count, 0);
+  psdp_status rc;
+  {
+    ProfScope pscope(h, "fulleig");
+    rc = full_eig_batched(h, count, n, X, Pi, want_v ? V : nullptr, want_v ? m_cap : nullptr,
+                          want_v ? lambda : nullptr, mo.data(), np.data(), bad.data());
+  }
+  if (rc != PSDP_OK) return rc;
+  psdp_status worst = PSDP_OK;
+  for (int i = 0; i < count; ++i) {
+    fill_full_info(&info[i], np[i], mo[i], bad[i]);
+    if (want_v && !bad[i]) m_inout[i] = mo[i];
+    if (bad[i]) worst = PSDP_ERR_NUMERICAL;
+  }
+  return worst;
+}
+
 extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int* n,
                                             const double* const* X, double* const* V,
                                             const int* m_cap, int* m_inout,
@@ -781,6 +917,44 @@ extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int*
     ProfScope pscope(h, "batched");
     rc = batch_engine_run(h->batch, h->stream, count, n, X, V, m_cap, m_inout, lambda, Pi, opt, info);
   }
+  if (rc == PSDP_NOT_CONVERGED && opt.fallback_full) {
+    // exact path for the cones the block solver did not converge
+    std::vector<int> idx;
+    for (int i = 0; i < count; ++i)
+      if (info[i].status == PSDP_NOT_CONVERGED) idx.push_back(i);
+    const int c = (int)idx.size();
+    std::vector<int> fn(c), fcap(c), mo(c), np(c), bad(c);
+    std::vector<const double*> fX(c);
+    std::vector<double*> fV(c), fL(c), fP(c);
+    for (int t = 0; t < c; ++t) {
+      const int i = idx[t];
+      fn[t] = n[i]; fcap[t] = m_cap[i]; fX[t] = X[i]; fV[t] = V[i]; fL[t] = lambda[i]; fP[t] = Pi[i];
+    }
+    psdp_status r2;
+    {
+      ProfScope pscope(h, "fulleig");
+      r2 = full_eig_batched(h, c, fn.data(), fX.data(), fP.data(), fV.data(), fcap.data(), fL.data(),
+                            mo.data(), np.data(), bad.data());
+    }
+    if (r2 != PSDP_OK) return r2;
+    rc = PSDP_OK;
+    for (int t = 0; t < c; ++t) {
+      const int i = idx[t];
+      const int iters = info[i].iters, exps = info[i].expansions;
+      fill_full_info(&info[i], np[t], mo[t], bad[t]);
+      info[i].iters = iters;
+      info[i].expansions = exps;
+      if (bad[t]) { rc = PSDP_ERR_NUMERICAL; continue; }
+      info[i].status = PSDP_FELL_BACK_FULL_EIG;
+      m_inout[i] = mo[t];
+    }
+    if (rc == PSDP_OK) {
+      for (int i = 0; i < count; ++i) {
+        if (info[i].status < 0) { rc = (psdp_status)std::min((int)rc, info[i].status); }
+        else if (rc >= 0) rc = (psdp_status)std::max((int)rc, info[i].status);
+      }
+    }
+  }
   if (h->prof && h->pending.size() > first) {
     // algorithmic traffic: X read, Pi written, V read and written; flops of
     // the iterations: product 2 n^2 (3m) + Gram/orthogonalization ~ 10 n (3m)^2
@@ -795,6 +969,28 @@ extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int*
   }
   return rc;
 }
+
+namespace psdp {
+int block_need(int est, const psdp_options& opt) {
+  return est + std::max(opt.block_guard, (int)std::ceil(0.2 * est));
+}
+
+int auto_side(int n, int pos_hint, int m_cap, const psdp_options& opt) {
+  // paper §6: project through the side with fewer than threshold * n
+  // eigenvalues; with no estimate, the full eig
+  int side;
+  if (pos_hint < 0) return PSDP_SIDE_FULL;
+  if (pos_hint < opt.side_threshold * n) side = PSDP_SIDE_POS;
+  else if (n - pos_hint < opt.side_threshold * n) side = PSDP_SIDE_NEG;
+  else return PSDP_SIDE_FULL;
+  // cost rule: the block the estimate needs must fit the capacity, and a
+  // trial basis of 3m columns must stay well below n (paper §5.1: the
+  // O(n^2 m) iteration only pays off for m << n)
+  const int need = block_need(side == PSDP_SIDE_POS ? pos_hint : n - pos_hint, opt);
+  if (need > std::min(m_cap, kMaxM) || 6 * need >= n) return PSDP_SIDE_FULL;
+  return side;
+}
+}  // namespace psdp
 
 extern "C" psdp_status psdp_batched_tuning(psdp_handle h, int* variant, double* last_ms) {
   if (!h || !variant || !last_ms) return PSDP_ERR_INVALID_ARG;
@@ -825,20 +1021,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
 
   // ---- side (paper §6): fewer than threshold*n positive -> positive side
   int side = opt.side;
-  if (side == PSDP_SIDE_AUTO) {
-    if (opt.pos_hint < 0) side = PSDP_SIDE_FULL;
-    else if (opt.pos_hint < opt.side_threshold * n) side = PSDP_SIDE_POS;
-    else if (n - opt.pos_hint < opt.side_threshold * n) side = PSDP_SIDE_NEG;
-    else side = PSDP_SIDE_FULL;
-    if (side != PSDP_SIDE_FULL) {
-      // cost rule: the block the estimate needs must fit the capacity, and a
-      // trial basis of 3m columns must stay well below n (paper §5.1: the
-      // O(n^2 m) iteration only pays off for m << n)
-      const int est = (side == PSDP_SIDE_POS) ? opt.pos_hint : n - opt.pos_hint;
-      const int need = est + std::max(opt.block_guard, (int)std::ceil(0.2 * est));
-      if (need > std::min(m_cap, kMaxM) || 6 * need >= n) side = PSDP_SIDE_FULL;
-    }
-  }
+  if (side == PSDP_SIDE_AUTO) side = auto_side(n, opt.pos_hint, m_cap, opt);
   const int mcap = std::min(std::min(m_cap, kMaxM), n);
   if (side == PSDP_SIDE_FULL) {
     int mo = 0, npos = 0;

@@ -1,0 +1,16 @@
+// Host-side functions shared between the driver, the batched engine and
+// the server (not part of the C-ABI).
+#pragma once
+#include <stddef.h>
+
+#include "../../include/psdp.h"
+
+namespace psdp {
+
+// AUTO side rule of psdp_project (paper §6 plus the block cost rule):
+// returns PSDP_SIDE_POS, _NEG or _FULL.
+int auto_side(int n, int pos_hint, int m_cap, const psdp_options& opt);
+// block an estimate of `est` eigenvalues needs: est + max(guard, ceil(0.2 est))
+int block_need(int est, const psdp_options& opt);
+
+}  // namespace psdp

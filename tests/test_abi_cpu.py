@@ -61,7 +61,10 @@ int main(void) {{ printf("size %zu\\n", sizeof({struct})); {body} return 0; }}
     return {k: int(v) for k, v in (ln.split() for ln in out.strip().splitlines())}
 
 
-@pytest.mark.parametrize("name,cls", [("psdp_options", "Options"), ("psdp_info", "Info")])
+@pytest.mark.parametrize("name,cls", [("psdp_options", "Options"), ("psdp_info", "Info"),
+                                      ("psdp_server_config", "ServerConfig"),
+                                      ("psdp_result", "ServerResult"),
+                                      ("psdp_server_stats", "ServerStats")])
 def test_struct_layout_matches_header(tmp_path, name, cls):
     sys.path.insert(0, ROOT)
     from paper_1912_02767_amd import _abi

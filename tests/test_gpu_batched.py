@@ -195,3 +195,50 @@ def test_full_size_batch_sampled(proj):
     sample = list(order[:4]) + list(order[-6:]) + list(order[250:254])
     for i in sample:
         _check_cone(res[i], cones[i].X)
+
+
+def test_full_eig_batched_matches_oracle(proj):
+    """Exact batched path: zero-padded buckets of order round_up(n, 32)."""
+    from gpu_util import to_dev, to_host
+    ns = [1, 5, 31, 32, 33, 64, 100, 200, 255, 256]
+    cones = [random_spectrum_matrix(n, max(1, n // 7), rng_for(43, n)) for n in ns]
+    caps = [min(48, n) for n in ns]
+    res = proj.full_eig_batched([to_dev(c.X) for c in cones], m_caps=caps)
+    for c, r, cap in zip(cones, res, caps):
+        Pi_ref, lam_ref = oracle.project(c.X)
+        assert r.status == 0
+        assert oracle.rel_error(to_host(r.Pi), Pi_ref, c.X) <= 1e-12
+        p = int((lam_ref > 0).sum())
+        assert r.info["n_pos"] == p
+        k = r.info["m_out"]
+        assert k == min(cap, c.X.shape[0], p + max(4, math.ceil(0.2 * p)))
+        # leading eigenpairs, largest first, in the cone's own coordinates
+        lam = to_host(r.lam)
+        assert np.allclose(lam, np.sort(lam_ref)[::-1][:k], atol=1e-10 * np.abs(lam_ref).max())
+        V = to_host(r.V)
+        assert np.abs(V.T @ V - np.eye(k)).max() <= 1e-10
+    # projection only
+    res2 = proj.full_eig_batched([to_dev(c.X) for c in cones])
+    for a, b in zip(res, res2):
+        assert np.array_equal(to_host(a.Pi), to_host(b.Pi))
+
+
+def test_fallback_to_exact_path(proj):
+    """A cone whose positive eigenvalues crowd against zero does not converge
+    within a few iterations; with fallback_full the call returns it exact."""
+    from gpu_util import to_dev, to_host
+    rng = rng_for(44, 0)
+    from workloads import from_spectrum, haar_orthogonal
+    n = 120
+    lam = np.concatenate([10.0 ** rng.uniform(-3, 2, 12), -(10.0 ** rng.uniform(-3, 2, n - 12))])
+    lam[:3] = [1e-5, 2e-5, 3e-5]
+    X = from_spectrum(haar_orthogonal(n, rng), lam)
+    good = batched_cones(count=3, stream=8)
+    Xs = [X] + [c.X for c in good]
+    caps = [20] + _caps(good)
+    res = proj.project_batched([to_dev(x) for x in Xs], m_caps=caps, prec="fp32", max_iter=15,
+                               fallback_full=True)
+    assert res[0].status == 2 and res[0].info["side_used"] == 3
+    for x, r in zip(Xs, res):
+        Pi_ref, _ = oracle.project(x)
+        assert oracle.rel_error(to_host(r.Pi), Pi_ref, x) <= REL, r.info

@@ -23,6 +23,7 @@ __all__ = [
     "cold_block", "Cone", "HouseholderBasis",
     "single_cone", "warm_sequence", "large_cone", "large_cone_sequence",
     "batched_cones", "serving_sessions", "poisson_arrivals", "SessionSpec",
+    "session_sequence",
     "random_spectrum_matrix",
 ]
 
@@ -242,3 +243,15 @@ def poisson_arrivals(rate: float, duration: float, n_sessions: int,
     t = t[t < duration]
     sid = rng.integers(0, n_sessions, size=t.size)
     return t, sid
+
+
+def session_sequence(spec: SessionSpec, steps: int, rel: float = 1e-3,
+                     stream: int = 0) -> Iterator[np.ndarray]:
+    """The matrices one serving session submits: X_0 = its cone, then
+    X_{k+1} = X_k + E_k with ||E_k||_F = rel * ||X_k||_F."""
+    rng = rng_for(5, 20_000 + 1000 * stream + spec.sid)
+    X = spec.cone.X
+    yield X
+    for _ in range(1, steps):
+        X = np.asfortranarray(X + sym_perturbation(spec.n, rel * np.linalg.norm(X), rng))
+        yield X
