@@ -20,6 +20,11 @@ Workloads (one step = one pass of the whole projection path):
   batched512      512 cones, n_i uniform in [16, 256], 10% positive spectrum;
                   a step is one persistent launch projecting all 512 (FP32
                   products, FP64 Rayleigh-Ritz).
+  serving_mix     Poisson arrivals at 2000 requests/s for --serve-seconds from
+                  64 sessions (n log-uniform in [32, 2048], 1-20% positive,
+                  magnitudes 10^U[-3,2], warm-start sequences at 1e-3 ||X||_F)
+                  through the serving loop; value = served requests/s, beside
+                  the plain path (one projection at a time, same arrivals).
 
 Prints ONE JSON line.  Inputs are generated on the host (seeded) and
 uploaded before the timed region.  The cpu_baseline leg times the FP64
@@ -317,6 +322,107 @@ def run_batched(args, torch, psdp):
     return out
 
 
+# -------------------------------------------------------------- serving ---
+def run_serving(args, torch, psdp):
+    """Poisson stream of requests from 64 sessions through the server, then
+    the same stream through the plain path (one projection at a time)."""
+    from workloads import poisson_arrivals, serving_sessions, session_sequence
+    rate = 2000.0
+    duration = args.serve_seconds
+    prec = args.prec or "fp32"
+    t_gen = time.time()
+    specs = serving_sessions(count=64)
+    t_arr, sid = poisson_arrivals(rate, duration, len(specs))
+    gens = [session_sequence(sp, 10 ** 6) for sp in specs]
+    mats = [np.asfortranarray(next(gens[s_])) for s_ in sid]
+    log(f"generated {len(specs)} sessions, {len(mats)} requests in {time.time() - t_gen:.1f}s")
+    dev = torch.device("cuda", 0)
+    Xd = [torch.from_numpy(X).to(dev) for X in mats]
+    Pd = [psdp._empty_f(X.shape[0], X.shape[0], dev) for X in mats]
+    torch.cuda.synchronize()
+
+    def serve(slots, lane):
+        srv = psdp.Server(0, slots=slots, batch_lane=lane, prec=prec)
+        ids = [srv.open_session(sp.n, m_cap=48, pos_hint=-1) for sp in specs]
+        torch.cuda.synchronize()
+        tickets = []
+        t0 = time.perf_counter()
+        for k in range(len(mats)):
+            while time.perf_counter() - t0 < t_arr[k]:
+                pass
+            tickets.append(srv.submit(ids[sid[k]], Xd[k], Pi_out=Pd[k]))
+        res = [srv.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return res, st, wall
+
+    # untimed warm-up pass of the server (library init, solver handles)
+    serve(4, True)
+    res, st, wall = serve(4, True)
+    lat = np.array([r.latency_ms for r in res])
+    n_lane = sum(1 for r in res if r.lane == 1)
+    n_full = sum(1 for r in res if r.info["side_used"] == 3)
+    keep = {k: Pd[k].clone() for k in range(0, len(mats), max(1, len(mats) // 24))}
+
+    # plain path: one Projector, one Session per session, FIFO in arrival order
+    proj = psdp.Projector(0)
+    sess = [psdp.Session(proj, sp.n, m_cap=48, prec=prec, side="auto", pos_hint=-1,
+                         fallback_full=True) for sp in specs]
+    proj.profile_enable(True)
+    plain_lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(len(mats)):
+        now = time.perf_counter() - t0
+        if now < t_arr[k]:
+            time.sleep(t_arr[k] - now)
+        sess[sid[k]].project(Xd[k], Pi_out=Pd[k])
+        torch.cuda.synchronize()
+        plain_lat.append(1e3 * (time.perf_counter() - t0 - t_arr[k]))
+    plain_wall = time.perf_counter() - t0
+    fams = {f: proj.profile_get(f) for f in FAMILIES}
+    proj.profile_enable(False)
+    plain_lat = np.array(plain_lat)
+    rel_fe = max(float(torch.linalg.norm(keep[k] - Pd[k]) / max(torch.linalg.norm(Pd[k]), 1e-300))
+                 for k in keep)
+
+    cpu, rel_oracle = None, []
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        small = [k for k in keep if mats[k].shape[0] <= 700][:8]
+        t = time.perf_counter()
+        for k in small:
+            Pi_ref, _ = oracle.project(mats[k])
+            rel_oracle.append(oracle.rel_error(keep[k].cpu().numpy(), Pi_ref))
+        dt = time.perf_counter() - t
+        cpu = {"value": len(small) / max(dt, 1e-9), "unit": "projections/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{len(small)} served requests with n <= 700, FP64 cyclic Jacobi + clip"}
+    value = st["throughput"]
+    out = {
+        "value": value, "steps": len(mats), "warmup": 1, "ms_per_step": 1e3 * wall / len(mats),
+        "dtype": prec,
+        "config": {"workload": "serving_mix", "sessions": 64, "rate_per_s": rate,
+                   "duration_s": duration, "requests": len(mats), "n_range": [32, 2048],
+                   "slots": 4, "batch_lane": True, "products": prec, "refine": "fp64"},
+        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+        "served_in_lane": n_lane, "served_full_eig": n_full,
+        "batched_launches": st["batched_launches"], "max_active": st["max_active"],
+        "hbm_peak_bytes": st["hbm_peak"],
+        "plain_path": {"value": len(mats) / plain_wall, "unit": "projections/s",
+                       "p50_ms": float(np.percentile(plain_lat, 50)),
+                       "p99_ms": float(np.percentile(plain_lat, 99))},
+        "speedup_vs_plain_path": value / (len(mats) / plain_wall),
+        "rel_err_served_vs_plain_max": rel_fe,
+        "rel_err_vs_oracle_max": max(rel_oracle) if rel_oracle else None,
+        "roofline": roofline(fams, prec), "cpu_baseline": cpu, "kernels": kernels_table(fams),
+    }
+    proj.close()
+    return out
+
+
 def copy_probe(mib, torch):
     n = mib * 1024 * 1024 // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -333,7 +439,10 @@ def main():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n1000_warm_seq",
-                    choices=["n1000_warm_seq", "n4000_mixed", "n4000_mixed_iid", "batched512"])
+                    choices=["n1000_warm_seq", "n4000_mixed", "n4000_mixed_iid", "batched512",
+                             "serving_mix"])
+    ap.add_argument("--serve-seconds", type=float, default=0.25,
+                    help="length of the Poisson arrival window (serving_mix)")
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--full-eig-samples", type=int, default=None)
     ap.add_argument("--oracle-samples", type=int, default=None)
@@ -354,6 +463,8 @@ def main():
 
     if args.workload == "batched512":
         body = run_batched(args, torch, psdp)
+    elif args.workload == "serving_mix":
+        body = run_serving(args, torch, psdp)
     else:
         body = run_sequence(args, torch, psdp)
     out = {
