@@ -50,14 +50,41 @@ import numpy as np  # noqa: E402
 PEAKS = {  # MI355X published dense peaks
     "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
 }
-FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rebuild", "ingest", "batched"]
+FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rebuild", "ingest", "batched", "fulleig"]
+
+# HBM bytes per launch measured with rocprofv3 PMC counters (FETCH_SIZE x 2.0
+# + WRITE_SIZE x 1.0, factors from a plain 256 MiB copy), keyed by workload
+# and kernel family, with the hash of the kernel sources at measurement time:
+# when the sources have changed since, the figure no longer describes the
+# kernel and is reported as null.
+TRAFFIC = {
+    ("n1000_warm_seq", "rr"): {
+        "bytes": 68.0e3,
+        "files": ["paper_1912_02767_amd/csrc/rr_body.h", "paper_1912_02767_amd/csrc/k_rr_tri.hip",
+                  "paper_1912_02767_amd/csrc/common.h"],
+        "sha256": "8510b3652702efc8a0cc92154c30103558df3feb9a38d0e014f313769e505061",
+        "profile": "profiles/hbm_traffic_n1000_warm_seq.txt",
+    },
+}
+
+
+def measured_traffic(workload, family):
+    import hashlib
+    t = TRAFFIC.get((workload, family))
+    if t is None:
+        return None
+    h = hashlib.sha256()
+    for f in t["files"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return t["bytes"] if h.hexdigest() == t["sha256"] else None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def roofline(fams, prec):
+def roofline(fams, prec, workload=None):
     """Dominant kernel family: algorithmic bytes or flops per launch divided
     by its average launch time (hipEvents on the launching stream)."""
     dom = max(fams, key=lambda f: fams[f]["ms"])
@@ -81,7 +108,8 @@ def roofline(fams, prec):
         roof = {"bound": "alu", "achieved": flops_l / (avg_ms * 1e-3) / 1e12,
                 "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(workload, dom)
+    roof["algorithmic_bytes"] = bytes_l
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
     return roof
@@ -224,7 +252,7 @@ def run_sequence(args, torch, psdp):
         "rel_err_vs_oracle_max": max(rel_oracle.values()) if rel_oracle else None,
         "err_bound_rel_max": max(inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in infos
                                  if inf["side_used"] != 3) if any(inf["side_used"] != 3 for inf in infos) else 0.0,
-        "roofline": roofline(fams, prec), "cpu_baseline": cpu, "kernels": kernels_table(fams),
+        "roofline": roofline(fams, prec, wl), "cpu_baseline": cpu, "kernels": kernels_table(fams),
     }
     proj.close()
     return out
@@ -316,7 +344,7 @@ def run_batched(args, torch, psdp):
         "rel_err_vs_full_eig_max": rel_fe,
         "rel_err_vs_oracle_max": max(rel_oracle) if rel_oracle else None,
         "err_bound_rel_max": max(inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in infos),
-        "roofline": roofline(fams, prec), "cpu_baseline": cpu, "kernels": kernels_table(fams),
+        "roofline": roofline(fams, prec, "batched512"), "cpu_baseline": cpu, "kernels": kernels_table(fams),
     }
     proj.close()
     return out
@@ -417,7 +445,8 @@ def run_serving(args, torch, psdp):
         "speedup_vs_plain_path": value / (len(mats) / plain_wall),
         "rel_err_served_vs_plain_max": rel_fe,
         "rel_err_vs_oracle_max": max(rel_oracle) if rel_oracle else None,
-        "roofline": roofline(fams, prec), "cpu_baseline": cpu, "kernels": kernels_table(fams),
+        "roofline": roofline(fams, prec, "serving_mix"), "cpu_baseline": cpu,
+        "kernels": kernels_table(fams),
     }
     proj.close()
     return out
