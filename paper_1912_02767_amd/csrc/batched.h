@@ -69,12 +69,19 @@ hipError_t launch_batched(const BatchArgs& a, bool rr_full, int grid, hipStream_
 hipError_t batched_init(int lds_bytes);
 
 // Dynamic LDS doubles the batched kernel needs for blocks of width <= mmax
-// with the given Rayleigh-Ritz storage and GEMM k-chunk.
-inline size_t batched_lds_doubles(int mmax, bool rr_full, int kc) {
-  const size_t N = 3 * (size_t)mmax, mk = mmax;
-  const size_t hsz = rr_full ? N * N : N * (N + 1) / 2;
-  const size_t rr = hsz + 14 * N + (N + 1) * mk + (kBThreads + 2) / 2 + 2;
-  const size_t chol = N * (N + 1) / 2 + N + (N * 16 > 1024 ? N * 16 : 1024) + 8;
+// with the given GEMM k-chunk (the Rayleigh-Ritz body, the Cholesky body
+// and the GEMM staging share the same space).
+inline size_t batched_lds_doubles(int mmax, bool /*one_per_cu*/, int kc) {
+  const size_t N = 3 * (size_t)mmax;
+  const size_t n2 = N * (N + 1) / 2;
+  const size_t ldy = (N & 1) ? N : N + 1;
+  const size_t wy = 16 * 16 + 16 * (size_t)mmax;
+  const size_t lp = 96;  // 16 row groups x 6 = 16 column groups x 6
+  size_t ysp = ldy * mmax;
+  if (ysp < 5 * lp) ysp = 5 * lp;
+  if (ysp < (size_t)kBThreads) ysp = kBThreads;
+  const size_t rr = n2 + 5 * N + ysp + (wy > 3 * N ? wy : 3 * N) + kBThreads / 64 + 4;
+  const size_t chol = n2 + N + (N * 16 > 1024 ? N * 16 : 1024) + 8;
   const size_t gemm = 2 * (size_t)kc * 65;
   size_t m = rr > chol ? rr : chol;
   return m > gemm ? m : gemm;

@@ -223,6 +223,7 @@ struct CholShared {
 hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st);
 hipError_t launch_rr(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
 hipError_t launch_rr_tri(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
+hipError_t launch_rr_fast(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
 hipError_t rr_tri_init();
 hipError_t small_kernels_init();
 

@@ -118,7 +118,9 @@ struct psdp_handle_s {
   double* h_pin = nullptr;  // pinned scratch for small readbacks
   size_t h_pin_cap = 0;
   unsigned long long calls = 0;
-  int rr_method = 0;  // 0: tridiagonal + bisection + inverse iteration, 1: Jacobi
+  int rr_method = 0;  // 0: column-parallel tridiagonal + twisted vectors + WY back-transform,
+                      // 1: Jacobi, 2: first tridiagonal design (inverse iteration)
+  bool trace = false; // PSDP_TRACE=1: one line per iteration on stderr
   bool prof = false;
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<PendingEvent> pending;
@@ -438,6 +440,8 @@ struct Solver {
     {
       ProfScope ps(h, "rr");
       if (h->rr_method == 0) {
+        HIP_TRY(launch_rr_fast(ra, Nmax, std::min(mtarget, Nmax), s));
+      } else if (h->rr_method == 2) {
         HIP_TRY(launch_rr_tri(ra, Nmax, std::min(mtarget, Nmax), s));
       } else {
         HIP_TRY(launch_rr(ra, Nmax, std::min(mtarget, Nmax), s));
@@ -452,6 +456,15 @@ struct Solver {
     }
     psdp_status rs = read_state();
     if (rs != PSDP_OK) return rs;
+    if (h->trace) {
+      double ph[4];
+      for (int q = 0; q < 4; ++q) ph[q] = (hs->t_phase[q + 1] - hs->t_phase[q]) * 1e-2;  // us
+      std::fprintf(stderr,
+                   "psdp: iter %d mode %d prec %d N %d Np %d mk %d npos %d/%d stop %d rmax %.3e "
+                   "rguard %.3e tol %.3e rr_us %.0f %.0f %.0f %.0f\n",
+                   hs->iter, mode, pprec, hs->N, hs->Np, hs->mk, hs->npos_blk, hs->npos_rr,
+                   hs->stop, hs->res_max_pos, hs->guard_res, hs->tol, ph[0], ph[1], ph[2], ph[3]);
+    }
     if (h->prof && hs->stop == kRunning) {
       auto& e = h->prof_tab["rr_stats"];  // launches: RR calls, bytes: sum Np, flops: sum rounds
       e.launches += 1;
@@ -577,7 +590,11 @@ psdp_status psdp_create(psdp_handle* out, int device, void* stream) {
     delete h;
     return PSDP_ERR_HIP;
   }
-  if (const char* m = std::getenv("PSDP_RR_METHOD")) h->rr_method = std::atoi(m) == 1 ? 1 : 0;
+  if (const char* m = std::getenv("PSDP_RR_METHOD")) {
+    const int v = std::atoi(m);
+    h->rr_method = (v == 1 || v == 2) ? v : 0;
+  }
+  if (const char* t = std::getenv("PSDP_TRACE")) h->trace = std::atoi(t) != 0;
   if (hipHostMalloc((void**)&h->h_state, sizeof(State), hipHostMallocDefault) != hipSuccess) {
     delete h;
     return PSDP_ERR_OUT_OF_MEMORY;

@@ -12,7 +12,7 @@
 // bound statistics and the rebuild.
 #include "batched.h"
 #include "chol_body.h"
-#include "rr_body.h"
+#include "rr_fast.h"
 
 namespace psdp {
 
@@ -229,7 +229,7 @@ struct ConeSolver {
       ra.lds_cap = ba.lds_doubles;
       ra.scratch = w.rrs;
       ra.st = st;
-      rr_tri_body<RRFULL>(ra, lds, sh.rr);
+      rr_fast_body<6, 6, kBThreads>(ra, lds, sh.rr);  // 16 x 16 thread grid, N <= 96
       __syncthreads();
     }
     // X = S2 C, AX = AS C, P = S2[:, nx:] C[nx:, :], R = AX - X diag(theta)
@@ -462,8 +462,8 @@ struct ConeSolver {
   }
 };
 
-// RRFULL: Rayleigh-Ritz matrix stored square (one workgroup per CU) or as a
-// packed triangle, with registers limited so two workgroups share a CU.
+// RRFULL: one workgroup per CU, or (false) registers limited so that two
+// workgroups share a CU.
 template <bool RRFULL>
 __global__ __launch_bounds__(kBThreads, RRFULL ? 1 : 2) void k_batched(BatchArgs ba) {
   extern __shared__ double lds[];

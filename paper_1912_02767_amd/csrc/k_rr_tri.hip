@@ -1,5 +1,7 @@
-// Rayleigh-Ritz kernel for the single-cone pipeline (body in rr_body.h).
+// Rayleigh-Ritz kernels for the single-cone pipeline (bodies in rr_body.h
+// and rr_fast.h).
 #include "rr_body.h"
+#include "rr_fast.h"
 
 namespace psdp {
 
@@ -14,7 +16,30 @@ __global__ __launch_bounds__(kTriThreads) void k_rr_tri(RRArgs a) {
   rr_tri_body<FULL>(a, lds, sh);
 }
 
+constexpr int kFastThreads = 512;
+
+__global__ __launch_bounds__(kFastThreads) void k_rr_fast(RRArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double s_lo[kMaxM], s_hi[kMaxM];
+  __shared__ int s_npos;
+  __shared__ double s_tnorm, s_pivmin;
+  if (a.st->stop) return;
+  RRShared sh{s_lo, s_hi, &s_npos, &s_tnorm, &s_pivmin};
+  rr_fast_body<5, 9, kFastThreads>(a, lds, sh);  // 32 x 16 thread grid, N <= 144
+}
+
 static int g_tri_lds_limit = 56 * 1024;
+
+hipError_t launch_rr_fast(const RRArgs& a_in, int Np_host, int mk_host, hipStream_t st) {
+  RRArgs a = a_in;
+  if (Np_host > 144) return hipErrorInvalidValue;
+  const size_t doubles =
+      rr_fast_lds_doubles(Np_host, std::min(mk_host, Np_host), kFastThreads, 5, 9);
+  if (doubles * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
+  a.lds_cap = doubles;
+  hipLaunchKernelGGL(k_rr_fast, dim3(1), dim3(kFastThreads), doubles * 8, st, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_rr_tri(const RRArgs& a_in, int Np_host, int mk_host, hipStream_t st) {
   RRArgs a = a_in;
@@ -46,6 +71,8 @@ hipError_t rr_tri_init() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void*)k_rr_tri<false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              dyn);
   }
   (void)hipGetLastError();
   return hipSuccess;

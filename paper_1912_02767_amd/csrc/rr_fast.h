@@ -1,0 +1,663 @@
+// Device body of the one-workgroup Rayleigh-Ritz step, second design:
+//   1. Householder tridiagonalization of the N x N projected matrix held as
+//      a packed lower triangle in column-major order (column j starts at
+//      cb(j) + j with cb(j) = j N - j (j + 1) / 2; element (i, j), i >= j, at
+//      cb(j) + i), one thread per column: thread j forms its entry of the
+//      symmetric product p = A v from its column (rows at and below j) and
+//      its row (columns left of j, read along those columns), updates its
+//      own column in the rank-2 step, and the owner of the next pivot column
+//      forms the next reflector's norm while it updates that column.  Two
+//      barriers per step; reflectors are scaled in place once at the end.
+//   2. multisection with Sturm counts for the mk largest eigenvalues,
+//      bracketed to a few ulps of ||T||;
+//   3. eigenvectors by the twisted factorization of T - sigma I (top-down
+//      and bottom-up pivots, twist at the smallest |gamma|), one thread per
+//      vector; modified Gram-Schmidt inside clusters (with inverse iteration
+//      from a fixed start vector when a vector collapses onto its
+//      predecessors, as for exactly repeated eigenvalues); Rayleigh quotients;
+//   4. back-transformation by blocks of 16 reflectors in compact WY form,
+//      Y <- (I - V T V^T) Y, last block first, spread over the workgroup.
+// Included by the single-cone kernel and the batched persistent kernel;
+// needs blockDim.x >= N.
+#pragma once
+#include "rr_body.h"
+
+namespace psdp {
+
+constexpr int kWYBlock = 16;
+
+__host__ __device__ inline int pk_cb(int j, int N) { return j * N - (j * (j + 1)) / 2; }
+
+// dynamic LDS doubles of rr_fast_body for order N and mk vectors
+// Tb + Wb region: the block reflector factor and V^T Y, or the three
+// factor diagonals of one inverse-iteration solve
+__host__ __device__ inline size_t rr_fast_tbw(int N, int mk) {
+  const size_t wy = (size_t)kWYBlock * kWYBlock + (size_t)kWYBlock * mk;
+  return wy > 3 * (size_t)N ? wy : 3 * (size_t)N;
+}
+
+// The Y region also hosts the reflector buffers and per-wave partial
+// products of phase 1 and the Sturm counts of phase 2.
+// LP: padded length of the phase-1 vectors (rows covered by the thread grid)
+__host__ __device__ inline size_t rr_fast_lp(int nthreads, int nbr, int nbc) {
+  const size_t a = (size_t)(nthreads / 16) * nbr, b = 16 * (size_t)nbc;
+  return a > b ? a : b;
+}
+
+__host__ __device__ inline size_t rr_fast_yspace(int N, int mk, int nthreads, size_t lp) {
+  const size_t n = N;
+  const size_t ldy = (N & 1) ? n : n + 1;
+  size_t y = ldy * (size_t)mk;
+  if (y < 5 * lp) y = 5 * lp;
+  if (y < (size_t)nthreads) y = nthreads;
+  return y;
+}
+
+__host__ __device__ inline size_t rr_fast_lds_doubles(int N, int mk, int nthreads, int nbr,
+                                                      int nbc) {
+  const size_t n = N, nw = nthreads / 64;
+  return n * (n + 1) / 2 + 5 * n + rr_fast_yspace(N, mk, nthreads, rr_fast_lp(nthreads, nbr, nbc)) +
+         rr_fast_tbw(N, mk) + nw + 4;
+}
+
+// Twisted-factorization eigenvector of the tridiagonal T (d, e, e2 = e^2)
+// for the shift sigma, written to y (length N, stride 1, not normalized);
+// pivots of magnitude below pfloor are replaced by -pfloor.  The loops load
+// four entries ahead of the pivot recurrences.
+__device__ inline double tw_piv(double dd, double ee2, double prev, double pfloor) {
+  double q = dd - fast_div(ee2, prev);
+  return (fabs(q) < pfloor) ? -pfloor : q;
+}
+
+__device__ inline void twisted_vector(const double* d, const double* e, const double* e2, int N,
+                                      double sigma, double pfloor, double* y) {
+  if (N == 1) { y[0] = 1.0; return; }
+  // top-down pivots D+ into y
+  double dp = d[0] - sigma;
+  if (fabs(dp) < pfloor) dp = -pfloor;
+  y[0] = dp;
+  int i = 1;
+  for (; i + 3 < N; i += 4) {
+    const double d0 = d[i] - sigma, d1 = d[i + 1] - sigma, d2 = d[i + 2] - sigma, d3 = d[i + 3] - sigma;
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+    dp = tw_piv(d0, f0, dp, pfloor); y[i] = dp;
+    dp = tw_piv(d1, f1, dp, pfloor); y[i + 1] = dp;
+    dp = tw_piv(d2, f2, dp, pfloor); y[i + 2] = dp;
+    dp = tw_piv(d3, f3, dp, pfloor); y[i + 3] = dp;
+  }
+  for (; i < N; ++i) { dp = tw_piv(d[i] - sigma, e2[i - 1], dp, pfloor); y[i] = dp; }
+  // bottom-up pivots D-, twist index at the smallest |gamma_i|,
+  // gamma_i = D+_i + D-_i - (d_i - sigma)
+  double dm = d[N - 1] - sigma;
+  if (fabs(dm) < pfloor) dm = -pfloor;
+  int r = N - 1;
+  double gbest = fabs(y[N - 1]);
+  i = N - 2;
+  for (; i - 3 >= 0; i -= 4) {
+    const double d0 = d[i] - sigma, d1 = d[i - 1] - sigma, d2 = d[i - 2] - sigma, d3 = d[i - 3] - sigma;
+    const double f0 = e2[i], f1 = e2[i - 1], f2 = e2[i - 2], f3 = e2[i - 3];
+    const double y0 = y[i], y1 = y[i - 1], y2 = y[i - 2], y3 = y[i - 3];
+    double g;
+    dm = tw_piv(d0, f0, dm, pfloor); g = fabs(y0 + dm - d0); if (g < gbest) { gbest = g; r = i; }
+    dm = tw_piv(d1, f1, dm, pfloor); g = fabs(y1 + dm - d1); if (g < gbest) { gbest = g; r = i - 1; }
+    dm = tw_piv(d2, f2, dm, pfloor); g = fabs(y2 + dm - d2); if (g < gbest) { gbest = g; r = i - 2; }
+    dm = tw_piv(d3, f3, dm, pfloor); g = fabs(y3 + dm - d3); if (g < gbest) { gbest = g; r = i - 3; }
+  }
+  for (; i >= 0; --i) {
+    const double di = d[i] - sigma;
+    dm = tw_piv(di, e2[i], dm, pfloor);
+    const double g = fabs(y[i] + dm - di);
+    if (g < gbest) { gbest = g; r = i; }
+  }
+  // D- again below the twist (y[i], i > r, is no longer needed as D+)
+  dm = d[N - 1] - sigma;
+  if (fabs(dm) < pfloor) dm = -pfloor;
+  if (r < N - 1) y[N - 1] = dm;
+  for (i = N - 2; i > r; --i) {
+    dm = tw_piv(d[i] - sigma, e2[i], dm, pfloor);
+    y[i] = dm;
+  }
+  // the vector: z_r = 1, upward through L (D+), downward through U (D-)
+  double z = 1.0;
+  for (i = r - 1; i >= 0; --i) {
+    z = -fast_div(e[i], y[i]) * z;
+    y[i] = z;
+  }
+  z = 1.0;
+  for (i = r + 1; i < N; ++i) {
+    z = -fast_div(e[i - 1], y[i]) * z;
+    y[i] = z;
+  }
+  y[r] = 1.0;
+}
+
+// Reflector scalars of a column with leading entry alpha and squared norm
+// xn of the entries below it (LAPACK dlarfg convention, beta = -sign(alpha) |x|).
+__device__ inline void reflector(double alpha, double xn, double& t, double& beta, double& scale) {
+  t = 0.0;
+  beta = alpha;
+  scale = 0.0;
+  if (xn > 0.0) {
+    beta = -copysign(sqrt(alpha * alpha + xn), alpha);
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+}
+
+// Sum over each row of 16 lanes (every lane of the row gets the sum).
+__device__ inline double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);   // lane ^ 1
+  v += dpp_d<0x4E>(v);   // lane ^ 2
+  v += dpp_d<0x141>(v);  // other quad of each 8
+  v += dpp_d<0x140>(v);  // other 8 of each 16
+  return v;
+}
+
+// lane ^ 16 (within 32) and lane ^ 32 partners' values added
+__device__ inline double add_x16_x32(double v) {
+  int2 x = __builtin_bit_cast(int2, v);
+  x.x = __builtin_amdgcn_ds_swizzle(x.x, 0x401F);
+  x.y = __builtin_amdgcn_ds_swizzle(x.y, 0x401F);
+  v += __builtin_bit_cast(double, x);
+  return v + __shfl_xor(v, 32, 64);
+}
+
+template <int NB>
+__device__ inline double sel(const double (&row)[NB], int q) {
+  double v = row[0];
+#pragma unroll
+  for (int t = 1; t < NB; ++t) v = (t == q) ? row[t] : v;
+  return v;
+}
+
+// Householder tridiagonalization with the matrix in registers.  The NT
+// threads form an RG x 16 grid (RG = NT / 16 row groups, 16 column groups):
+// thread (r, c) = (tid >> 4, tid & 15) holds A(r + RG li, c + 16 lj) for
+// li < NBR, lj < NBC (both triangles), so the 16 threads of one row group
+// are 16 lanes of one wave.  Per step k:
+//   (a) with x the raw column k below the diagonal (LDS column buffer),
+//       every thread forms its partial rows of A x, summed over the 16
+//       lanes of the row group (DPP), its part of x^T A x, and every wave
+//       the norm of x; the owners of column k + 1 publish that column;
+//   (b) every thread forms the reflector scalars; with v = scale x +
+//       g e_{k+1} (g = 1 - scale x_{k+1}), A v and v^T A v follow from A x,
+//       x^T A x and column k + 1; one thread per trailing row forms
+//       w = t A v - (t^2 / 2)(v^T A v) v, keeps the reflector in P, and forms
+//       column k + 1 after the update (the next column buffer) and its
+//       diagonal entry;
+//   (c) every thread applies A -= v w^T + w v^T to its block.
+// Two barriers per step.  Vectors in LDS are zero-padded to LP entries so
+// that threads read them without bounds tests.  On return: d, e (N - 1
+// entries), tau, and the reflectors (unit entry at row k + 1 included) in
+// the packed column-major lower triangle P.
+template <int NBR, int NBC, int NT>
+__device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d, double* e,
+                                   double* tau, double* buf, double* red) {
+  constexpr int RG = NT / 16, nw = NT / 64;
+  constexpr int LP = (RG * NBR > 16 * NBC) ? RG * NBR : 16 * NBC;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int r = tid >> 4, c = tid & 15;
+  // LDS vectors (LP each): column buffers (2), w, the published column, t A v
+  double* colb[2] = {buf, buf + LP};
+  double* wb = buf + 2 * LP;
+  double* cpre = buf + 3 * LP;
+  double* pf = buf + 4 * LP;
+  double A[NBR][NBC];
+#pragma unroll
+  for (int li = 0; li < NBR; ++li)
+#pragma unroll
+    for (int lj = 0; lj < NBC; ++lj) {
+      const int i = r + RG * li, j = c + 16 * lj;
+      A[li][lj] = (i < N && j < N) ? 0.5 * (a.K[i + (size_t)j * a.ldk] + a.K[j + (size_t)i * a.ldk])
+                                   : 0.0;
+    }
+  // column 0 below the diagonal, and d[0]
+  for (int i = tid; i < LP; i += NT) {
+    colb[0][i] = (i >= 1 && i < N) ? 0.5 * (a.K[i] + a.K[(size_t)i * a.ldk]) : 0.0;
+    colb[1][i] = 0.0;  // rows at or beyond N stay zero in every buffer
+    wb[i] = 0.0;
+    cpre[i] = 0.0;
+    pf[i] = 0.0;
+  }
+  if (tid == 0) d[0] = a.K[0];
+  __syncthreads();
+  for (int k = 0; k + 2 < N; ++k) {
+    const double* col = colb[k & 1];
+    double* coln = colb[(k + 1) & 1];
+    // ---- (a) products with the raw column x (x_i = A(i, k) for i > k, 0
+    // otherwise); the reflector is v = scale x + g e_{k+1}, g = 1 - scale x_{k+1}
+    double xs = 0.0;
+    for (int i = k + 2 + lane; i < N; i += 64) xs = fma(col[i], col[i], xs);
+    double xr[NBR], xc[NBC];
+#pragma unroll
+    for (int q = 0; q < NBR; ++q) {
+      const int i = r + RG * q;
+      xr[q] = (i > k) ? col[i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NBC; ++q) {
+      const int j = c + 16 * q;
+      xc[q] = (j > k) ? col[j] : 0.0;
+    }
+    // the owners of column k + 1 publish it (before this step's update)
+    if (c == ((k + 1) & 15)) {
+      const int lj1 = (k + 1) >> 4;
+#pragma unroll
+      for (int li = 0; li < NBR; ++li) {
+        double x = A[li][0];
+#pragma unroll
+        for (int q = 1; q < NBC; ++q) x = (q == lj1) ? A[li][q] : x;
+        cpre[r + RG * li] = x;
+      }
+    }
+    double xax = 0.0;
+#pragma unroll
+    for (int li = 0; li < NBR; ++li) {
+      double s0 = 0.0;
+      if (RG * li + RG - 1 > k) {
+#pragma unroll
+        for (int lj = 0; lj < NBC; ++lj) s0 = fma(A[li][lj], xc[lj], s0);
+      }
+      s0 = row16_sum(s0);  // (A x) for row r + RG li
+      if (c == 0) {
+        xax = fma(xr[li], s0, xax);
+        pf[r + RG * li] = s0;
+      }
+    }
+    xs = wave_sum(xs);  // same value in every wave
+    xax = wave_sum(xax);
+    if (lane == 0) red[wv] = xax;
+    __syncthreads();
+    // ---- (b) reflector scalars (every thread), w, the reflector kept in P,
+    // the next column
+    const double alpha = col[k + 1];
+    double t, beta, scale;
+    reflector(alpha, xs, t, beta, scale);
+    const double g = 1.0 - scale * alpha;
+    double xaxs = 0.0;
+#pragma unroll
+    for (int q = 0; q < nw; ++q) xaxs += red[q];
+    const double ax1 = pf[k + 1], a11 = cpre[k + 1];
+    // v^T A v = scale^2 x^T A x + 2 scale g (A x)_{k+1} + g^2 A(k+1, k+1)
+    const double vav = scale * scale * xaxs + 2.0 * scale * g * ax1 + g * g * a11;
+    const double alf = -0.5 * t * t * vav;
+    // (A v)_i = scale (A x)_i + g A(i, k+1)
+    const double w1 = (t != 0.0) ? t * (scale * ax1 + g * a11) + alf : 0.0;  // v_{k+1} = 1
+    if (tid == 0) {
+      tau[k] = t;
+      e[k] = beta;
+    }
+    const int ck = pk_cb(k, N);
+    for (int i = k + 1 + tid; i < N; i += NT) {
+      const double x = col[i];
+      const double vi = (i == k + 1) ? 1.0 : x * scale;
+      const double ci = cpre[i];
+      const double wi = (t != 0.0) ? t * (scale * pf[i] + g * ci) + alf * vi : 0.0;
+      wb[i] = wi;
+      // reflector kept below the diagonal of column k (identity if t = 0)
+      P[ck + i] = (t != 0.0) ? vi : ((i == k + 1) ? 1.0 : 0.0);
+      // column k + 1 after the update: A(i, k+1) - v_i w_{k+1} - w_i v_{k+1}
+      const double upd = (t != 0.0) ? vi * w1 + wi : 0.0;
+      if (i == k + 1) d[k + 1] = ci - ((t != 0.0) ? 2.0 * w1 : 0.0);
+      coln[i] = (i >= k + 2) ? ci - upd : 0.0;
+    }
+    __syncthreads();
+    // ---- (c) rank-2 update of this thread's block
+    if (t != 0.0) {
+      double vr[NBR], vc[NBC], wr[NBR], wc[NBC];
+#pragma unroll
+      for (int q = 0; q < NBR; ++q) {
+        const int i = r + RG * q;
+        vr[q] = (i == k + 1) ? 1.0 : xr[q] * scale;
+        wr[q] = (i > k) ? wb[i] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < NBC; ++q) {
+        const int j = c + 16 * q;
+        vc[q] = (j == k + 1) ? 1.0 : xc[q] * scale;
+        wc[q] = (j > k) ? wb[j] : 0.0;
+      }
+#pragma unroll
+      for (int li = 0; li < NBR; ++li)
+        if (RG * li + RG - 1 > k) {
+#pragma unroll
+          for (int lj = 0; lj < NBC; ++lj)
+            A[li][lj] = fma(-vr[li], wc[lj], fma(-wr[li], vc[lj], A[li][lj]));
+        }
+    }
+  }
+  // last diagonal entry and last off-diagonal from the registers
+#pragma unroll
+  for (int li = 0; li < NBR; ++li)
+#pragma unroll
+    for (int lj = 0; lj < NBC; ++lj) {
+      const int i = r + RG * li, j = c + 16 * lj;
+      if (N >= 2 && i == N - 1 && j == N - 1) d[N - 1] = A[li][lj];
+      if (N >= 2 && i == N - 1 && j == N - 2) e[N - 2] = A[li][lj];
+    }
+  if (tid == 0) {
+    tau[max(N - 2, 0)] = 0.0;
+    if (N == 1) d[0] = a.K[0];
+  }
+  __syncthreads();
+}
+
+template <int NBR, int NBC, int NT>
+__device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared& sh) {
+  double* s_lo = sh.lo;
+  double* s_hi = sh.hi;
+  int& s_npos = *sh.npos;
+  double& s_tnorm = *sh.tnorm;
+  double& s_pivmin = *sh.pivmin;
+  State* st = a.st;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int N = st->Np;
+  const int mk = min(a.mtarget, N);
+  // ---- LDS layout
+  const int ldy = (N & 1) ? N : N + 1;  // odd: threads over columns hit distinct banks
+  double* P = lds;                                   // N(N+1)/2 packed lower, column-major
+  double* d = P + (size_t)N * (N + 1) / 2;           // N
+  double* e = d + N;                                 // N
+  double* e2 = e + N;                                // N
+  double* tau = e2 + N;                              // N
+  double* pv = tau + N;                              // N: Ritz values
+  double* Y = pv + N;                                // ldy x mk (phase 3, 4)
+  double* tbuf = Y;                                  // phase-1 vectors and partial products
+  int* cnts = (int*)Y;                               // nt Sturm counts (phase 2)
+  double* Tb = Y + rr_fast_yspace(N, mk, nt, rr_fast_lp(nt, NBR, NBC));  // 16 x 16 WY factor
+  double* Wb = Tb + kWYBlock * kWYBlock;             // 16 x mk
+  double* red = Tb + rr_fast_tbw(N, mk);             // nw
+  if (tid == 0) st->t_phase[0] = wall_clock64();
+
+  // ---- 1. tridiagonalization (matrix in registers)
+  tridiag_reg<NBR, NBC, NT>(a, N, P, d, e, tau, tbuf, red);
+  for (int i = tid; i + 1 < N; i += nt) e2[i] = e[i] * e[i];
+  __syncthreads();
+  if (tid == 0) {
+    double tn = 0.0, emax2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double rr = fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
+      tn = fmax(tn, rr);
+      if (i + 1 < N) emax2 = fmax(emax2, e2[i]);
+    }
+    s_tnorm = tn;
+    s_pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+  }
+  __syncthreads();
+  const double tnorm = s_tnorm, pivmin = s_pivmin;
+  if (tid == 0) st->t_phase[1] = wall_clock64();
+
+  // ---- 2. multisection for the top mk eigenvalues (+ count of positives)
+  {
+    double gl = 0.0, gu = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double rr = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
+      gl = (i == 0) ? d[i] - rr : fmin(gl, d[i] - rr);
+      gu = (i == 0) ? d[i] + rr : fmax(gu, d[i] + rr);
+    }
+    const double pad = 2.2e-16 * tnorm * 4.0 * N + 2.0 * pivmin;
+    gl -= pad;
+    gu += pad;
+    for (int j = tid; j < mk; j += nt) { s_lo[j] = gl; s_hi[j] = gu; }
+    if (tid == nt - 1) s_npos = N - sturm_count(d, e2, N, 0.0, pivmin);
+    __syncthreads();
+    const int per = max(1, nt / max(mk, 1));  // shifts per eigenvalue per round
+    const int j_me = tid / per, s_me = tid % per;
+    for (int round = 0; round < 64; ++round) {
+      bool done = true;
+      for (int j = 0; j < mk; ++j) {
+        const double w = s_hi[j] - s_lo[j];
+        const double tolj = 4.4e-16 * (tnorm + fmax(fabs(s_lo[j]), fabs(s_hi[j]))) + 4.0 * pivmin;
+        if (w > tolj) { done = false; break; }
+      }
+      if (done) break;
+      if (j_me < mk) {
+        const double lo = s_lo[j_me], hi = s_hi[j_me];
+        const double x = lo + (hi - lo) * (double)(s_me + 1) / (double)(per + 1);
+        cnts[tid] = sturm_count(d, e2, N, x, pivmin);
+      }
+      __syncthreads();
+      if (tid < mk) {
+        const int j = tid;
+        const int target = N - 1 - j;  // ascending index of the j-th largest
+        const double lo = s_lo[j], hi = s_hi[j];
+        double nlo = lo, nhi = hi;
+        for (int s2 = 0; s2 < per; ++s2) {
+          const double x = lo + (hi - lo) * (double)(s2 + 1) / (double)(per + 1);
+          if (cnts[j * per + s2] <= target) nlo = x;
+          else { nhi = x; break; }
+        }
+        s_lo[j] = nlo;
+        s_hi[j] = nhi;
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) st->t_phase[2] = wall_clock64();
+
+  // ---- 3. eigenvectors: twisted factorization, one thread per vector
+  const double pfloor = fmax(2.2e-16 * tnorm, 1e-300);
+  const double ortol = 1e-3 * tnorm;
+  for (int j = tid; j < mk; j += nt) {
+    double* y = Y + (size_t)j * ldy;
+    twisted_vector(d, e, e2, N, 0.5 * (s_lo[j] + s_hi[j]), pfloor, y);
+    double mx = 0.0;
+    for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(y[i]));
+    const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+    double nn = 0.0;
+    for (int i = 0; i < N; ++i) { const double v = y[i] * sc; y[i] = v; nn += v * v; }
+    const double inv = 1.0 / sqrt(nn);
+    for (int i = 0; i < N; ++i) y[i] *= inv;
+  }
+  __syncthreads();
+  // modified Gram-Schmidt inside clusters (wave 0)
+  if (wv == 0) {
+    for (int j = 1; j < mk; ++j) {
+      const double mid_j = 0.5 * (s_lo[j] + s_hi[j]);
+      const double mid_p = 0.5 * (s_lo[j - 1] + s_hi[j - 1]);
+      if (mid_p - mid_j > ortol) continue;
+      int c0 = j - 1;
+      while (c0 > 0 && 0.5 * (s_lo[c0 - 1] + s_hi[c0 - 1]) - 0.5 * (s_lo[c0] + s_hi[c0]) <= ortol)
+        --c0;
+      double* yj = Y + (size_t)j * ldy;
+      for (int attempt = 0; attempt < 2; ++attempt) {
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int i0 = c0; i0 < j; ++i0) {
+            const double* yi = Y + (size_t)i0 * ldy;
+            double dp = 0.0;
+            for (int q = lane; q < N; q += 64) dp += yi[q] * yj[q];
+            dp = wave_sum(dp);
+            for (int q = lane; q < N; q += 64) yj[q] -= dp * yi[q];
+            __threadfence_block();
+          }
+        }
+        double nn = 0.0;
+        for (int q = lane; q < N; q += 64) nn += yj[q] * yj[q];
+        nn = wave_sum(nn);
+        if (nn > 0.25 || attempt == 1) {
+          const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+          for (int q = lane; q < N; q += 64) yj[q] *= inv;
+          __threadfence_block();
+          break;
+        }
+        // the vector collapsed onto its predecessors (repeated eigenvalue):
+        // inverse iteration from a fixed start vector, factors in Tb/Wb
+        if (lane == 0) {
+          for (int i = 0; i < N; ++i) yj[i] = start_entry(i, j);
+          double* U0 = Tb;
+          tri_solve(d, e, N, mid_j, pfloor, yj, U0, U0 + N, U0 + 2 * N, 1);
+          double mx = 0.0;
+          for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(yj[i]));
+          const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+          for (int i = 0; i < N; ++i) yj[i] *= sc;
+        }
+        __threadfence_block();
+      }
+    }
+  }
+  __syncthreads();
+  // Rayleigh quotients y^T T y
+  for (int j = tid; j < mk; j += nt) {
+    const double* y = Y + (size_t)j * ldy;
+    double rq = 0.0;
+    for (int i = 0; i < N; ++i) {
+      double ty = d[i] * y[i];
+      if (i > 0) ty += e[i - 1] * y[i - 1];
+      if (i + 1 < N) ty += e[i] * y[i + 1];
+      rq += y[i] * ty;
+    }
+    pv[j] = rq;
+  }
+  __syncthreads();
+  if (tid == 0) st->t_phase[3] = wall_clock64();
+
+  // ---- 4. back-transformation Z = H_0 H_1 ... H_{N-3} Y by blocks of
+  // reflectors, last block first: Y <- (I - V T V^T) Y with V the block's
+  // reflectors (unit at row k + 1, zero above) and T = U^{-1},
+  // U = diag(1 / tau) + strictly upper part of V^T V (a zero tau gives a
+  // zero row and column of T)
+  {
+    const int nref = N - 2;  // reflectors 0 .. N - 3
+    for (int b0 = nref > 0 ? ((nref - 1) / kWYBlock) * kWYBlock : -1; b0 >= 0; b0 -= kWYBlock) {
+      const int bs = min(kWYBlock, nref - b0);
+      // U's strictly upper part v_l . v_q (l < q) into Tb
+      for (int x = tid; x < bs * bs; x += nt) {
+        const int l = x % bs, q = x / bs;
+        if (l < q) {
+          const int cl = pk_cb(b0 + l, N), cq = pk_cb(b0 + q, N), kq = b0 + q;
+          double s0 = P[cl + kq + 1], s1 = 0.0, s2 = 0.0, s3 = 0.0;  // v_q(kq + 1) = 1
+          int i = kq + 2;
+          for (; i + 3 < N; i += 4) {
+            const double a0 = P[cl + i], a1 = P[cl + i + 1], a2 = P[cl + i + 2], a3 = P[cl + i + 3];
+            const double b0 = P[cq + i], b1 = P[cq + i + 1], b2 = P[cq + i + 2], b3 = P[cq + i + 3];
+            s0 = fma(a0, b0, s0);
+            s1 = fma(a1, b1, s1);
+            s2 = fma(a2, b2, s2);
+            s3 = fma(a3, b3, s3);
+          }
+          for (; i < N; ++i) s0 = fma(P[cl + i], P[cq + i], s0);
+          Tb[l + kWYBlock * q] = (s0 + s1) + (s2 + s3);
+        }
+      }
+      __syncthreads();
+      // column q of T by back substitution in lane q (U t = e_q)
+      double tcol[kWYBlock];
+      if (tid < bs) {
+        const int q = tid;
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) tcol[l] = 0.0;
+        const double tq = tau[b0 + q];
+        for (int l = kWYBlock - 1; l >= 0; --l) {
+          if (l > q) continue;
+          double val;
+          if (l == q) {
+            val = tq;
+          } else {
+            const double tl = tau[b0 + l];
+            double s = 0.0;
+#pragma unroll
+            for (int cc = 0; cc < kWYBlock; ++cc)
+              if (cc > l && cc <= q) s = fma(Tb[l + kWYBlock * cc], tcol[cc], s);
+            val = (tl == 0.0) ? 0.0 : -tl * s;
+          }
+#pragma unroll
+          for (int cc = 0; cc < kWYBlock; ++cc)
+            if (cc == l) tcol[cc] = val;
+        }
+      }
+      __syncthreads();  // every lane has read U
+      if (tid < bs) {
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) Tb[l + kWYBlock * tid] = (l <= tid) ? tcol[l] : 0.0;
+      }
+      // W = V^T Y (bs x mk): thread (j, lg) forms rows lg, lg + 8 of column j
+      for (int x = tid; x < 8 * mk; x += nt) {
+        const int j = x % mk, lg = x / mk;
+        const double* y = Y + (size_t)j * ldy;
+        const int l0 = lg, l1 = lg + 8;
+        double w0 = 0.0, w1 = 0.0;
+        if (l0 < bs) {
+          const int k0 = b0 + l0, c0 = pk_cb(k0, N);
+          double u0 = y[k0 + 1], u1 = 0.0, u2 = 0.0, u3 = 0.0;
+          int i = k0 + 2;
+          for (; i + 3 < N; i += 4) {
+            const double a0 = P[c0 + i], a1 = P[c0 + i + 1], a2 = P[c0 + i + 2], a3 = P[c0 + i + 3];
+            const double b0_ = y[i], b1 = y[i + 1], b2 = y[i + 2], b3 = y[i + 3];
+            u0 = fma(a0, b0_, u0);
+            u1 = fma(a1, b1, u1);
+            u2 = fma(a2, b2, u2);
+            u3 = fma(a3, b3, u3);
+          }
+          for (; i < N; ++i) u0 = fma(P[c0 + i], y[i], u0);
+          w0 = (u0 + u1) + (u2 + u3);
+        }
+        if (l1 < bs) {
+          const int k1 = b0 + l1, c1 = pk_cb(k1, N);
+          double u0 = y[k1 + 1], u1 = 0.0, u2 = 0.0, u3 = 0.0;
+          int i = k1 + 2;
+          for (; i + 3 < N; i += 4) {
+            const double a0 = P[c1 + i], a1 = P[c1 + i + 1], a2 = P[c1 + i + 2], a3 = P[c1 + i + 3];
+            const double b0_ = y[i], b1 = y[i + 1], b2 = y[i + 2], b3 = y[i + 3];
+            u0 = fma(a0, b0_, u0);
+            u1 = fma(a1, b1, u1);
+            u2 = fma(a2, b2, u2);
+            u3 = fma(a3, b3, u3);
+          }
+          for (; i < N; ++i) u0 = fma(P[c1 + i], y[i], u0);
+          w1 = (u0 + u1) + (u2 + u3);
+        }
+        if (l0 < bs) Wb[l0 + kWYBlock * j] = w0;
+        if (l1 < bs) Wb[l1 + kWYBlock * j] = w1;
+      }
+      __syncthreads();
+      // W <- T W (one thread per column of W)
+      for (int j = tid; j < mk; j += nt) {
+        double w[kWYBlock];
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) w[l] = (l < bs) ? Wb[l + kWYBlock * j] : 0.0;
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) {
+          double s = 0.0;
+#pragma unroll
+          for (int cc = 0; cc < kWYBlock; ++cc)
+            if (cc >= l) s = fma(Tb[l + kWYBlock * cc], w[cc], s);
+          if (l < bs) Wb[l + kWYBlock * j] = s;
+        }
+      }
+      __syncthreads();
+      // Y -= V W: thread per row (rows above b0 + 1 are untouched)
+      for (int i = b0 + 1 + tid; i < N; i += nt) {
+        double vrow[kWYBlock];
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) {
+          const int kl = b0 + l;
+          vrow[l] = (l < bs && i >= kl + 1) ? ((i == kl + 1) ? 1.0 : P[pk_cb(kl, N) + i]) : 0.0;
+        }
+        for (int j = 0; j < mk; ++j) {
+          double s = 0.0;
+#pragma unroll
+          for (int l = 0; l < kWYBlock; ++l) s = fma(vrow[l], Wb[l + kWYBlock * j], s);
+          Y[i + (size_t)j * ldy] -= s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) st->t_phase[4] = wall_clock64();
+  // ---- outputs: C = Z (N x mk), Ritz values descending
+  for (int x = tid; x < N * mk; x += nt) {
+    const int i = x % N, j = x / N;
+    a.C[i + (size_t)j * a.ldc] = Y[i + (size_t)j * ldy];
+  }
+  for (int j = tid; j < mk; j += nt) st->theta[j] = pv[j];
+  if (tid == 0) {
+    st->npos_rr = s_npos;
+    st->mk = mk;
+    st->expand_req = (s_npos > a.mtarget) ? 1 : 0;
+    st->jacobi_rounds = 0;
+    if (a.count_iter) st->iter += 1;
+  }
+}
+
+}  // namespace psdp

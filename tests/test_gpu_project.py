@@ -136,24 +136,28 @@ def test_trivial_inputs(proj):
     assert abs(to_host(res.Pi)[0, 0] - 2.5) <= 1e-12
 
 
-def test_rr_methods_agree():
-    """The Jacobi Rayleigh-Ritz (kept as a cross-check) and the tridiagonal
-    one give the same projection to the parity bar."""
+@pytest.mark.parametrize("n,npos,m_cap", [(120, 10, 24), (400, 40, 48)])
+def test_rr_methods_agree(n, npos, m_cap):
+    """The Jacobi Rayleigh-Ritz (kept as a cross-check), the first
+    tridiagonal design and the column-parallel one give the same projection
+    to the parity bar (n = 400 with block 48 reaches trial bases of 144)."""
     import os
     import torch
     import paper_1912_02767_amd as psdp
     from gpu_util import to_dev, to_host
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    c = random_spectrum_matrix(120, 10, rng_for(53, 0))
+    c = random_spectrum_matrix(n, npos, rng_for(53, n))
     outs = []
-    for method in ("1", "0"):
+    for method in ("1", "2", "0"):
         os.environ["PSDP_RR_METHOD"] = method
         p = psdp.Projector(0)
-        res = p.project(to_dev(c.X), m_cap=24, side="pos", tol=1e-10, pos_hint=10)
+        res = p.project(to_dev(c.X), m_cap=m_cap, side="pos", tol=1e-10, pos_hint=npos,
+                        block_guard=m_cap - npos)
         assert res.status == 0
         outs.append(to_host(res.Pi))
         _check(res, c.X)
         p.close()
     os.environ.pop("PSDP_RR_METHOD", None)
     assert np.abs(outs[0] - outs[1]).max() <= 1e-8
+    assert np.abs(outs[0] - outs[2]).max() <= 1e-8
