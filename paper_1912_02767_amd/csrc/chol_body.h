@@ -73,6 +73,7 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   State* st = a.st;
   const int tid = threadIdx.x;
   const int m = a.m;
+  if (tid == 0 && a.mode != -1) st->t_phase[5] = wall_clock64();
 
   if (a.mode == kModeFull || a.mode == kModeXR || a.mode == kModeEval) {
     // ---- decisions from the residual norms (paper §5.2 / §6 stopping rule)
@@ -115,8 +116,16 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       // decisions are left to the FP64 phase and a low-precision phase that
       // asks for one ends as stalled.
       const bool lowp = a.phase_lowprec != 0;
+      // Rounding floor of residuals formed with low-precision products:
+      // about u_p ||A||_F / sqrt(n) per unit column (entry-wise rounding of A
+      // and of the accumulation); a phase ends once its largest positive
+      // residual is within a small factor of it.
+      const double up = a.phase_lowprec == 2 ? 3.9e-3 : 6.0e-8;
+      const double lp_floor = lowp ? 8.0 * up * sqrt(st->fro2_x / (double)max(st->n, 1)) : 0.0;
       if (nonfin) {
         stop = kNonFinite;
+      } else if (lowp && npos > 0 && rmax <= lp_floor) {
+        stop = kStalled;  // at the floor: continue with the next precision
       } else if (st->expand_req) {
         stop = lowp ? kStalled : kExpand;
       } else if (npos == m && rmax <= tol && m >= st->n) {
@@ -203,6 +212,8 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       return;
     }
   }
+  const bool mark = (a.mode != -1) && tid == 0;
+  if (mark) st->t_phase[6] = wall_clock64();
   double* Lp = lds;                      // N(N+1)/2
   double* dsc = Lp + N * (N + 1) / 2;    // N scales
   double* row = dsc + N;                 // scratch: inverse blocks + 16 x N
@@ -219,41 +230,117 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
     Lp[e] = g * dsc[i] * dsc[j];
   }
   __syncthreads();
-  // right-looking Cholesky with dropping on the packed lower triangle: at
-  // step j the trailing Schur complement is in place; column j is dropped
-  // when its pivot (squared distance of the scaled column to the span of
-  // the kept ones) is below tau, and then contributes nothing.
-  int& s_drop = *sh.drop;
-  double& s_piv = *sh.piv;
-  for (int j = 0; j < N; ++j) {
-    if (tid == 0) {
-      double d = Lp[plo(j, j)];
-      bool drop = !(d > a.tau) || dsc[j] == 0.0;
-      s_drop = drop;
-      s_piv = drop ? 0.0 : sqrt(d);
-      Lp[plo(j, j)] = s_piv;
-    }
-    __syncthreads();
-    const bool drop = s_drop;
-    const double ljj = s_piv;
-    for (int i = j + 1 + tid; i < N; i += blockDim.x)
-      Lp[plo(i, j)] = drop ? 0.0 : Lp[plo(i, j)] / ljj;
-    if (drop)
-      for (int k = tid; k < j; k += blockDim.x) Lp[plo(j, k)] = 0.0;
-    __syncthreads();
-    if (!drop) {
-      // trailing update: G[i,k] -= L[i,j] L[k,j] for j < k <= i
-      const int t = N - j - 1;
-      const int cnt = t * (t + 1) / 2;
-      for (int e = tid; e < cnt; e += blockDim.x) {
-        int r = tri_row(e);
-        int c = e - r * (r + 1) / 2;
-        int i = j + 1 + r, k = j + 1 + c;
-        Lp[plo(i, k)] -= Lp[plo(i, j)] * Lp[plo(k, j)];
+  if (mark) st->t_phase[7] = wall_clock64();
+  // Blocked right-looking Cholesky with dropping on the packed lower
+  // triangle, panels of 16 columns; at the start of panel [o, o + bs) the
+  // trailing Schur complement is in place.  A column is dropped when its
+  // pivot (squared distance of the scaled column to the span of the kept
+  // ones) is below tau: its column and row of L are zero and it contributes
+  // nothing to later columns.
+  //   (1) one wave factors the diagonal block column by column;
+  //   (2) rows below the block solve against it, one row per thread;
+  //   (3) the trailing triangle takes the rank-bs update in 4 x 4 tiles.
+  {
+    double* pinv = row;  // 16 inverse pivots of the panel (0: dropped)
+    const int lane = tid & 63;
+    for (int o = 0; o < N; o += 16) {
+      const int bs = min(16, N - o);
+      if (tid < 64) {
+        for (int j = 0; j < bs; ++j) {
+          const int jj = o + j;
+          const double d = Lp[plo(jj, jj)];
+          const bool drop = !(d > a.tau) || dsc[jj] == 0.0;
+          const double ljj = drop ? 0.0 : sqrt(d);
+          __threadfence_block();
+          if (lane == 0) {
+            Lp[plo(jj, jj)] = ljj;
+            pinv[j] = drop ? 0.0 : 1.0 / ljj;
+          }
+          if (lane < bs - j - 1) {
+            const int i = jj + 1 + lane;
+            Lp[plo(i, jj)] = drop ? 0.0 : Lp[plo(i, jj)] / ljj;
+          }
+          if (drop)
+            for (int k = lane; k < jj; k += 64) Lp[plo(jj, k)] = 0.0;
+          __threadfence_block();
+          if (!drop) {
+            const int t = bs - j - 1;
+            for (int e = lane; e < t * t; e += 64) {
+              const int r = e / t, c = e - r * t;
+              if (c <= r) {
+                const int i = jj + 1 + r, k = jj + 1 + c;
+                Lp[plo(i, k)] -= Lp[plo(i, jj)] * Lp[plo(k, jj)];
+              }
+            }
+          }
+          __threadfence_block();
+        }
+      }
+      __syncthreads();
+      // (2) L[i, o:o+bs] = S[i, o:o+bs] L_D^-T, dropped columns zero
+      for (int i = o + bs + tid; i < N; i += blockDim.x) {
+        double* Li = Lp + plo(i, o);
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (j < bs) {
+            const double* Lj = Lp + plo(o + j, o);
+            double s = Li[j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) s = fma(-v[k], Lj[k], s);
+            v[j] = s * pinv[j];
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (j < bs) Li[j] = v[j];
+      }
+      __syncthreads();
+      // (3) S[i, k] -= sum_j L[i, o + j] L[k, o + j] for o + bs <= k <= i
+      const int b0 = o + bs;
+      const int t = N - b0;
+      if (t > 0) {
+        const int nt = (t + 3) / 4;
+        for (int tile = tid; tile < nt * (nt + 1) / 2; tile += blockDim.x) {
+          const int ti = tri_row(tile), tj = tile - ti * (ti + 1) / 2;
+          const int i0 = b0 + 4 * ti, k0 = b0 + 4 * tj;
+          double acc[4][4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+          for (int j0 = 0; j0 < bs; j0 += 4) {
+            double x[4][4], y[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int i = min(i0 + r, N - 1), k = min(k0 + r, N - 1);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const bool in = j0 + q < bs;
+                x[r][q] = in ? Lp[plo(i, o + j0 + q)] : 0.0;
+                y[r][q] = in ? Lp[plo(k, o + j0 + q)] : 0.0;
+              }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[r][c] = fma(x[r][q], y[c][q], acc[r][c]);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const int i = i0 + r, k = k0 + c;
+              if (i < N && k <= i) Lp[plo(i, k)] -= acc[r][c];
+            }
+        }
       }
       __syncthreads();
     }
   }
+  if (mark) st->t_phase[8] = wall_clock64();
   // kept list
   if (tid == 0) {
     int np = 0, nx = 0;
@@ -325,6 +412,7 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       __syncthreads();
     }
   }
+  if (mark) st->t_phase[9] = wall_clock64();
   // T = D Linv^T restricted to kept columns: T[t, c] = d_t * Linv[keep[c], t]
   for (int e = tid; e < N * Np; e += blockDim.x) {
     int t = e % N, c = e / N;
@@ -353,6 +441,7 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
     st->Np = Np;
     st->nx = s_nx;
     if (Np == 0) st->stop = kBreakdown;
+    if (a.mode != -1) st->t_phase[10] = wall_clock64();
   }
 }
 

@@ -70,7 +70,8 @@ struct State {
   int eval_stop;        // decision an evaluation pass would have taken
   int last_npos;        // positive count at the last progress check
   int pad1;
-  long long t_phase[8]; // device clock at phase boundaries of the last RR
+  long long t_phase[12]; // device clock at phase boundaries of the last RR (0-4)
+                         // and of the last first-pass Cholesky-QR (6-10)
   // per column data (block order = descending Ritz value)
   double theta[kMaxM];
   double rnorm[kMaxM];
@@ -174,7 +175,7 @@ struct DecideArgs {
   int m;                // block size
   int nz;               // expansion columns (mode XZ)
   int has_p;
-  int phase_lowprec;    // 1 when the product precision is below FP64
+  int phase_lowprec;    // product precision of the phase: 0 FP64, 1 FP32, 2 BF16
   double tau;           // dropping threshold on the scaled pivot
   const double* bases[5];  // X, R, P, Z, S1 column bases
   int ld;               // leading dim of the bases
@@ -216,8 +217,6 @@ struct CholShared {
   int* Np;
   int* nx;
   int* stop;
-  int* drop;
-  double* piv;
   double* red;  // blockDim.x / 64 doubles
 };
 hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st);

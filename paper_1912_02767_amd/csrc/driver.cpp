@@ -376,7 +376,7 @@ struct Solver {
     // ---- decisions + first Cholesky-QR pass
     DecideArgs da{};
     da.G = w.G; da.ldg = NC; da.Ng = Ng; da.mode = mode; da.m = m; da.nz = nz;
-    da.has_p = has_p; da.phase_lowprec = pprec != 0; da.tau = 1e-10;
+    da.has_p = has_p; da.phase_lowprec = pprec; da.tau = 1e-10;
     da.bases[0] = w.X; da.bases[1] = w.R; da.bases[2] = w.P; da.bases[3] = w.Z; da.bases[4] = w.S1;
     da.ld = L; da.T = w.T; da.ldt = NC; da.colptr = w.colptr; da.st = w.st;
     int Nmax = Ng;  // upper bound on the trial width
@@ -457,13 +457,15 @@ struct Solver {
     psdp_status rs = read_state();
     if (rs != PSDP_OK) return rs;
     if (h->trace) {
-      double ph[4];
+      double ph[4], pc[5];
       for (int q = 0; q < 4; ++q) ph[q] = (hs->t_phase[q + 1] - hs->t_phase[q]) * 1e-2;  // us
+      for (int q = 0; q < 5; ++q) pc[q] = (hs->t_phase[q + 6] - hs->t_phase[q + 5]) * 1e-2;
       std::fprintf(stderr,
                    "psdp: iter %d mode %d prec %d N %d Np %d mk %d npos %d/%d stop %d rmax %.3e "
-                   "rguard %.3e tol %.3e rr_us %.0f %.0f %.0f %.0f\n",
+                   "rguard %.3e tol %.3e rr_us %.0f %.0f %.0f %.0f chol_us %.0f %.0f %.0f %.0f %.0f\n",
                    hs->iter, mode, pprec, hs->N, hs->Np, hs->mk, hs->npos_blk, hs->npos_rr,
-                   hs->stop, hs->res_max_pos, hs->guard_res, hs->tol, ph[0], ph[1], ph[2], ph[3]);
+                   hs->stop, hs->res_max_pos, hs->guard_res, hs->tol, ph[0], ph[1], ph[2], ph[3],
+                   pc[0], pc[1], pc[2], pc[3], pc[4]);
     }
     if (h->prof && hs->stop == kRunning) {
       auto& e = h->prof_tab["rr_stats"];  // launches: RR calls, bytes: sum Np, flops: sum rounds

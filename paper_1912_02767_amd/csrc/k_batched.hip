@@ -184,7 +184,7 @@ struct ConeSolver {
     gram(Ng, Ng, cand, w.XRP, ld, w.G, NC);
     DecideArgs da{};
     da.G = w.G; da.ldg = NC; da.Ng = Ng; da.mode = mode; da.m = m; da.nz = nz;
-    da.has_p = has_p; da.phase_lowprec = pprec != 0; da.tau = 1e-10;
+    da.has_p = has_p; da.phase_lowprec = pprec; da.tau = 1e-10;
     da.bases[0] = X; da.bases[1] = R; da.bases[2] = P; da.bases[3] = R; da.bases[4] = w.S1;
     da.ld = ld; da.T = w.T; da.ldt = NC; da.colptr = w.colptr; da.st = st;
     decide_chol_body(da, lds, sh.ch);
@@ -469,13 +469,12 @@ __global__ __launch_bounds__(kBThreads, RRFULL ? 1 : 2) void k_batched(BatchArgs
   extern __shared__ double lds[];
   __shared__ double red[kBThreads / 64];
   __shared__ int s_list[kMaxN], s_kind[kMaxN], s_col[kMaxN], s_keep[kMaxN];
-  __shared__ int s_N, s_Np, s_nx, s_stop, s_drop, s_next;
-  __shared__ double s_piv;
+  __shared__ int s_N, s_Np, s_nx, s_stop, s_next;
   __shared__ double s_lo[kMaxM], s_hi[kMaxM];
   __shared__ int s_npos;
   __shared__ double s_tnorm, s_pivmin;
   BShared sh;
-  sh.ch = CholShared{s_list, s_kind, s_col, s_keep, &s_N, &s_Np, &s_nx, &s_stop, &s_drop, &s_piv,
+  sh.ch = CholShared{s_list, s_kind, s_col, s_keep, &s_N, &s_Np, &s_nx, &s_stop,
                      red};
   sh.rr = RRShared{s_lo, s_hi, &s_npos, &s_tnorm, &s_pivmin};
   BScratch ws = bscratch_at(ba.scratch + (size_t)blockIdx.x * ba.scratch_stride, ba.nmax, ba.mmax);
