@@ -75,10 +75,10 @@ inline size_t batched_lds_doubles(int mmax, bool /*one_per_cu*/, int kc) {
   const size_t N = 3 * (size_t)mmax;
   const size_t n2 = N * (N + 1) / 2;
   const size_t ldy = (N & 1) ? N : N + 1;
-  const size_t wy = 16 * 16 + 16 * (size_t)mmax;
+  const size_t wy = 16 * 16 + 17 * (size_t)mmax;  // rr_fast_tbw: T block + W (ld 17)
   const size_t lp = 96;  // 16 row groups x 6 = 16 column groups x 6
   size_t ysp = ldy * mmax;
-  if (ysp < 5 * lp) ysp = 5 * lp;
+  if (ysp < 6 * lp) ysp = 6 * lp;
   if (ysp < (size_t)kBThreads) ysp = kBThreads;
   const size_t rr = n2 + 5 * N + ysp + (wy > 3 * N ? wy : 3 * N) + kBThreads / 64 + 4;
   const size_t chol = n2 + N + (N * 16 > 1024 ? N * 16 : 1024) + 8;

@@ -40,6 +40,14 @@ __device__ inline double block_max(double v, double* red) {
   return s;
 }
 
+// value of lane l (compile-time or uniform) in every lane
+__device__ inline double bcast_d(double v, int l) {
+  int2 x = __builtin_bit_cast(int2, v);
+  x.x = __builtin_amdgcn_readlane(x.x, l);
+  x.y = __builtin_amdgcn_readlane(x.y, l);
+  return __builtin_bit_cast(double, x);
+}
+
 // e -> (row, col) of a packed triangle: row r with r(r+1)/2 <= e < (r+1)(r+2)/2
 __device__ inline int tri_row(int e) {
   int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
@@ -76,90 +84,109 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   if (tid == 0 && a.mode != -1) st->t_phase[5] = wall_clock64();
 
   if (a.mode == kModeFull || a.mode == kModeXR || a.mode == kModeEval) {
-    // ---- decisions from the residual norms (paper §5.2 / §6 stopping rule)
-    if (tid < m) st->rnorm[tid] = sqrt(fmax(a.G[(m + tid) + (size_t)(m + tid) * a.ldg], 0.0));
-    __syncthreads();
-    if (tid == 0) {
-      double tol = st->tol;
-      int npos = 0;
-      for (int i = 0; i < m; ++i) npos += (st->theta[i] > 0.0);
-      st->npos_blk = npos;
-      double rmax = 0.0, rfro = 0.0;
-      for (int i = 0; i < npos; ++i) {
-        rmax = fmax(rmax, st->rnorm[i]);
-        rfro += st->rnorm[i] * st->rnorm[i];
+    // ---- decisions from the residual norms (paper §5.2 / §6 stopping rule),
+    // in wave 0 with one lane per block column (m <= 64; theta descending)
+    double* s_th = red + blockDim.x / 64;  // 64 + 64 doubles after the reduction slots
+    double* s_rn = s_th + 64;
+    if (tid < 64) {
+      const int i = tid;
+      const bool in = i < m;
+      const double th = st->theta[min(i, m - 1)];
+      const double rn = sqrt(fmax(a.G[(m + min(i, m - 1)) + (size_t)(m + min(i, m - 1)) * a.ldg], 0.0));
+      if (in) {
+        st->rnorm[i] = rn;
+        s_th[i] = th;
+        s_rn[i] = rn;
       }
-      st->res_max_pos = rmax;
-      st->res_fro_pos = sqrt(rfro);
-      st->theta_min_pos = npos > 0 ? st->theta[npos - 1] : 0.0;
-      int stop = kRunning;
-      bool nonfin = !isfinite(rfro);
-      for (int i = 0; i < m; ++i) nonfin |= !isfinite(st->theta[i]) || !isfinite(st->rnorm[i]);
-      // guard: largest non-positive Ritz pair, resolved to half its gap
-      double q;  // progress metric, <= 1 when converged
-      bool guard_ok = false;
-      if (npos < m) {
-        int g = npos;
-        double delta = npos > 0 ? (st->theta[npos - 1] - st->theta[g]) : fabs(st->theta[g]);
-        double gtol = fmax(tol, 0.5 * delta);
-        st->guard_theta = st->theta[g];
-        st->guard_res = st->rnorm[g];
-        guard_ok = st->rnorm[g] <= gtol;
-        q = fmax(rmax / tol, st->rnorm[g] / gtol);
-      } else {
-        st->guard_theta = NAN;
-        st->guard_res = NAN;
-        q = rmax / tol;
+      const unsigned long long posm = __ballot(in && th > 0.0);
+      const int npos = __popcll(posm);
+      double rm = (in && i < npos) ? rn : 0.0;
+      double r2 = rm * rm;
+      for (int o = 32; o > 0; o >>= 1) {
+        rm = fmax(rm, __shfl_xor(rm, o, 64));
+        r2 += __shfl_xor(r2, o, 64);
       }
-      // Below FP64 the products carry rounding noise of order u_p ||A||, so
-      // counts of positive Ritz values near zero are unreliable: expansion
-      // decisions are left to the FP64 phase and a low-precision phase that
-      // asks for one ends as stalled.
-      const bool lowp = a.phase_lowprec != 0;
-      // Rounding floor of residuals formed with low-precision products:
-      // about u_p ||A||_F / sqrt(n) per unit column (entry-wise rounding of A
-      // and of the accumulation); a phase ends once its largest positive
-      // residual is within a small factor of it.
-      const double up = a.phase_lowprec == 2 ? 3.9e-3 : 6.0e-8;
-      const double lp_floor = lowp ? 8.0 * up * sqrt(st->fro2_x / (double)max(st->n, 1)) : 0.0;
-      if (nonfin) {
-        stop = kNonFinite;
-      } else if (lowp && npos > 0 && rmax <= lp_floor) {
-        stop = kStalled;  // at the floor: continue with the next precision
-      } else if (st->expand_req) {
-        stop = lowp ? kStalled : kExpand;
-      } else if (npos == m && rmax <= tol && m >= st->n) {
-        stop = kConverged;  // the block spans the whole space
-      } else if (npos == m && rmax <= tol) {
-        stop = lowp ? kStalled : kExpand;  // no room left for a non-positive guard pair
-      } else if (rmax <= tol && guard_ok) {
-        stop = kConverged;
-      } else {
-        // stalled: no 10% progress within the window; in FP64 a newly found
-        // positive pair counts as progress even when the residual jumps
-        if ((!lowp && npos != st->last_npos) || q < 0.9 * st->best_res) {
-          st->best_res = q;
-          st->best_iter = st->iter;
-          st->last_npos = npos;
-        } else if (st->iter - st->best_iter >= st->stall_window) {
-          stop = kStalled;
+      const bool bad = in && (!isfinite(th) || !isfinite(rn));
+      const bool nonfin_any = __ballot(bad) != 0ull;
+      const double tol = st->tol;
+      const bool act = in && rn > tol;
+      const unsigned long long actm = __ballot(act);
+      const int nact = __popcll(actm);
+      const int pre = __popcll(actm & ((1ull << i) - 1ull));
+      __threadfence_block();  // s_th, s_rn visible to lane 0
+      if (i == 0) {
+        st->npos_blk = npos;
+        const double rmax = rm, rfro = r2;
+        st->res_max_pos = rmax;
+        st->res_fro_pos = sqrt(rfro);
+        st->theta_min_pos = npos > 0 ? s_th[npos - 1] : 0.0;
+        int stop = kRunning;
+        const bool nonfin = nonfin_any || !isfinite(rfro);
+        // guard: largest non-positive Ritz pair, resolved to half its gap
+        double q;  // progress metric, <= 1 when converged
+        bool guard_ok = false;
+        if (npos < m) {
+          const int g = npos;
+          const double delta = npos > 0 ? (s_th[npos - 1] - s_th[g]) : fabs(s_th[g]);
+          const double gtol = fmax(tol, 0.5 * delta);
+          st->guard_theta = s_th[g];
+          st->guard_res = s_rn[g];
+          guard_ok = s_rn[g] <= gtol;
+          q = fmax(rmax / tol, s_rn[g] / gtol);
+        } else {
+          st->guard_theta = NAN;
+          st->guard_res = NAN;
+          q = rmax / tol;
         }
+        // Below FP64 the products carry rounding noise of order u_p ||A||, so
+        // counts of positive Ritz values near zero are unreliable: expansion
+        // decisions are left to the FP64 phase and a low-precision phase that
+        // asks for one ends as stalled.
+        const bool lowp = a.phase_lowprec != 0;
+        // Rounding floor of residuals formed with low-precision products:
+        // about u_p ||A||_F / sqrt(n) per unit column (entry-wise rounding of A
+        // and of the accumulation); a phase ends once its largest positive
+        // residual is within a small factor of it.
+        const double up = a.phase_lowprec == 2 ? 3.9e-3 : 6.0e-8;
+        const double lp_floor = lowp ? 8.0 * up * sqrt(st->fro2_x / (double)max(st->n, 1)) : 0.0;
+        if (nonfin) {
+          stop = kNonFinite;
+        } else if (lowp && npos > 0 && rmax <= lp_floor) {
+          stop = kStalled;  // at the floor: continue with the next precision
+        } else if (st->expand_req) {
+          stop = lowp ? kStalled : kExpand;
+        } else if (npos == m && rmax <= tol && m >= st->n) {
+          stop = kConverged;  // the block spans the whole space
+        } else if (npos == m && rmax <= tol) {
+          stop = lowp ? kStalled : kExpand;  // no room left for a non-positive guard pair
+        } else if (rmax <= tol && guard_ok) {
+          stop = kConverged;
+        } else {
+          // stalled: no 10% progress within the window; in FP64 a newly found
+          // positive pair counts as progress even when the residual jumps
+          if ((!lowp && npos != st->last_npos) || q < 0.9 * st->best_res) {
+            st->best_res = q;
+            st->best_iter = st->iter;
+            st->last_npos = npos;
+          } else if (st->iter - st->best_iter >= st->stall_window) {
+            stop = kStalled;
+          }
+        }
+        st->eval_stop = stop;
+        if (a.mode == kModeEval) stop = kEvaluated;
+        st->stop = stop;
+        s_stop = stop;
       }
-      st->eval_stop = stop;
-      if (a.mode == kModeEval) stop = kEvaluated;
-      st->stop = stop;
-      s_stop = stop;
+      __threadfence_block();  // s_stop visible to the wave
+      const int stop = s_stop;
       // logical trial basis: X, then active R, then active P
-      int N = 0;
-      for (int i = 0; i < m; ++i) { s_list[N] = i; s_kind[N] = 0; s_col[N] = i; ++N; }
-      if (stop == kRunning) {
-        for (int i = 0; i < m; ++i)
-          if (st->rnorm[i] > tol) { s_list[N] = m + i; s_kind[N] = 1; s_col[N] = i; ++N; }
-        if (a.has_p && a.mode == kModeFull)
-          for (int i = 0; i < m; ++i)
-            if (st->rnorm[i] > tol) { s_list[N] = 2 * m + i; s_kind[N] = 2; s_col[N] = i; ++N; }
+      if (in) { s_list[i] = i; s_kind[i] = 0; s_col[i] = i; }
+      const bool withp = a.has_p && a.mode == kModeFull;
+      if (stop == kRunning && act) {
+        s_list[m + pre] = m + i; s_kind[m + pre] = 1; s_col[m + pre] = i;
+        if (withp) { s_list[m + nact + pre] = 2 * m + i; s_kind[m + nact + pre] = 2; s_col[m + nact + pre] = i; }
       }
-      s_N = N;
+      if (i == 0) s_N = (stop == kRunning) ? m + nact * (withp ? 2 : 1) : m;
     }
     __syncthreads();
     if (s_stop != kRunning) return;
@@ -223,11 +250,25 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
     dsc[i] = (gii > 0.0 && isfinite(gii)) ? 1.0 / sqrt(gii) : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < N * (N + 1) / 2; e += blockDim.x) {
-    int i = tri_row(e);
-    int j = e - i * (i + 1) / 2;
-    double g = a.G[s_list[i] + (size_t)s_list[j] * a.ldg];
-    Lp[e] = g * dsc[i] * dsc[j];
+  {
+    // four independent loads in flight per thread
+    const int n2 = N * (N + 1) / 2, nt4 = 4 * blockDim.x;
+    for (int e0 = tid; e0 < n2; e0 += nt4) {
+      double g[4];
+      int ii[4], jj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = min(e0 + u * (int)blockDim.x, n2 - 1);
+        ii[u] = tri_row(e);
+        jj[u] = e - ii[u] * (ii[u] + 1) / 2;
+        g[u] = a.G[s_list[ii[u]] + (size_t)s_list[jj[u]] * a.ldg];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        if (e < n2) Lp[e] = g[u] * dsc[ii[u]] * dsc[jj[u]];
+      }
+    }
   }
   __syncthreads();
   if (mark) st->t_phase[7] = wall_clock64();
@@ -243,59 +284,84 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   {
     double* pinv = row;  // 16 inverse pivots of the panel (0: dropped)
     const int lane = tid & 63;
+    long long tc = wall_clock64(), tca[3] = {0, 0, 0};
     for (int o = 0; o < N; o += 16) {
       const int bs = min(16, N - o);
       if (tid < 64) {
-        for (int j = 0; j < bs; ++j) {
-          const int jj = o + j;
-          const double d = Lp[plo(jj, jj)];
-          const bool drop = !(d > a.tau) || dsc[jj] == 0.0;
-          const double ljj = drop ? 0.0 : sqrt(d);
-          __threadfence_block();
-          if (lane == 0) {
-            Lp[plo(jj, jj)] = ljj;
-            pinv[j] = drop ? 0.0 : 1.0 / ljj;
-          }
-          if (lane < bs - j - 1) {
-            const int i = jj + 1 + lane;
-            Lp[plo(i, jj)] = drop ? 0.0 : Lp[plo(i, jj)] / ljj;
-          }
-          if (drop)
-            for (int k = lane; k < jj; k += 64) Lp[plo(jj, k)] = 0.0;
-          __threadfence_block();
-          if (!drop) {
-            const int t = bs - j - 1;
-            for (int e = lane; e < t * t; e += 64) {
-              const int r = e / t, c = e - r * t;
-              if (c <= r) {
-                const int i = jj + 1 + r, k = jj + 1 + c;
-                Lp[plo(i, k)] -= Lp[plo(i, jj)] * Lp[plo(k, jj)];
-              }
-            }
-          }
-          __threadfence_block();
-        }
-      }
-      __syncthreads();
-      // (2) L[i, o:o+bs] = S[i, o:o+bs] L_D^-T, dropped columns zero
-      for (int i = o + bs + tid; i < N; i += blockDim.x) {
-        double* Li = Lp + plo(i, o);
-        double v[16];
+        // lane l < bs holds row o + l of the diagonal block; pivots by
+        // reciprocal square root (two Newton steps), the block column by
+        // lane reads, the rank-1 updates in registers
+        const int l = lane;
+        double rw[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) rw[k] = (l < bs && k <= l) ? Lp[plo(o + min(l, bs - 1), o + min(k, l))] : 0.0;
+        const double dsl = dsc[o + min(l, bs - 1)];
+        unsigned long long dropm = 0ull;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
           if (j < bs) {
-            const double* Lj = Lp + plo(o + j, o);
-            double s = Li[j];
+            const double d = bcast_d(rw[j], j);
+            const double dsj = bcast_d(dsl, j);
+            const bool drop = !(d > a.tau) || dsj == 0.0;
+            double r = 0.0;
+            if (!drop) {
+              r = __builtin_amdgcn_rsq(d);
+              r = r * fma(-0.5 * d * r, r, 1.5);
+              r = r * fma(-0.5 * d * r, r, 1.5);
+            }
+            if (drop) dropm |= 1ull << j;
+            if (l == j) rw[j] = drop ? 0.0 : d * r;  // L(j, j) = sqrt(d)
+            if (l > j) rw[j] = drop ? 0.0 : rw[j] * r;
+            if (l == 0) pinv[j] = r;
+            if (!drop) {
 #pragma unroll
-            for (int k = 0; k < j; ++k) s = fma(-v[k], Lj[k], s);
-            v[j] = s * pinv[j];
+              for (int k = j + 1; k < 16; ++k) {
+                const double lkj = bcast_d(rw[j], k);  // L(k, j)
+                if (k <= l) rw[k] = fma(-rw[j], lkj, rw[k]);
+              }
+            }
           }
+        }
+        // rows of dropped columns are zero (in this block and to its left)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (l == j && ((dropm >> j) & 1ull)) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) rw[k] = 0.0;
+          }
+        if (l < bs)
+#pragma unroll
+          for (int k = 0; k < 16; ++k)
+            if (k <= l) Lp[plo(o + l, o + k)] = rw[k];
+        for (int j = 0; j < bs; ++j)
+          if ((dropm >> j) & 1ull)
+            for (int k = lane; k < o; k += 64) Lp[plo(o + j, k)] = 0.0;
+      }
+      __syncthreads();
+      if (mark) { const long long tn = wall_clock64(); tca[0] += tn - tc; tc = tn; }
+      // (2) L[i, o:o+bs] = S[i, o:o+bs] L_D^-T, dropped columns zero
+      for (int i = o + bs + tid; i < N; i += blockDim.x) {
+        // right-looking: the dependent chain is one multiply and one fma per column
+        double* Li = Lp + plo(i, o);
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = (j < bs) ? Li[min(j, bs - 1)] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          if (j < bs) {
+            v[j] *= pinv[j];
+#pragma unroll
+            for (int k = j + 1; k < 16; ++k)
+              if (k < bs) v[k] = fma(-v[j], Lp[plo(o + k, o + j)], v[k]);
+          }
+          asm volatile("" ::: "memory");  // one column of the block in flight
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j)
           if (j < bs) Li[j] = v[j];
       }
       __syncthreads();
+      if (mark) { const long long tn = wall_clock64(); tca[1] += tn - tc; tc = tn; }
       // (3) S[i, k] -= sum_j L[i, o + j] L[k, o + j] for o + bs <= k <= i
       const int b0 = o + bs;
       const int t = N - b0;
@@ -309,16 +375,16 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
           for (int r = 0; r < 4; ++r)
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-          for (int j0 = 0; j0 < bs; j0 += 4) {
+#pragma unroll 1
+          for (int j0 = 0; j0 < 16; j0 += 4) {
             double x[4][4], y[4][4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
               const int i = min(i0 + r, N - 1), k = min(k0 + r, N - 1);
 #pragma unroll
-              for (int q = 0; q < 4; ++q) {
-                const bool in = j0 + q < bs;
-                x[r][q] = in ? Lp[plo(i, o + j0 + q)] : 0.0;
-                y[r][q] = in ? Lp[plo(k, o + j0 + q)] : 0.0;
+              for (int q = 0; q < 4; ++q) {  // bs = 16 whenever a trailing block exists
+                x[r][q] = Lp[plo(i, o + j0 + q)];
+                y[r][q] = Lp[plo(k, o + j0 + q)];
               }
             }
 #pragma unroll
@@ -338,7 +404,10 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
         }
       }
       __syncthreads();
+      if (mark) { const long long tn = wall_clock64(); tca[2] += tn - tc; tc = tn; }
     }
+    if (mark)
+      for (int q = 0; q < 3; ++q) st->t_sub[8 + q] = tca[q];
   }
   if (mark) st->t_phase[8] = wall_clock64();
   // kept list
@@ -417,7 +486,8 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   for (int e = tid; e < N * Np; e += blockDim.x) {
     int t = e % N, c = e / N;
     int kc = s_keep[c];
-    double v = (t <= kc) ? Lp[plo(kc, t)] * dsc[t] : 0.0;
+    const double lv = Lp[plo(kc, min(t, kc))] * dsc[t];
+    const double v = (t <= kc) ? lv : 0.0;
     a.T[t + (size_t)c * a.ldt] = v;
   }
   for (int t = tid; t < N; t += blockDim.x) {

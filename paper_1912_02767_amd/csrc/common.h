@@ -72,6 +72,11 @@ struct State {
   int pad1;
   long long t_phase[12]; // device clock at phase boundaries of the last RR (0-4)
                          // and of the last first-pass Cholesky-QR (6-10)
+  long long t_sub[12];    // device clock ticks inside the last RR: tridiagonalization
+                          // (a)+(c), (b); back-transformation stages (i), (ii) T,
+                          // (ii) T W, (iii); multisection rounds; cluster
+                          // orthogonalization; and inside the last first-pass
+                          // Cholesky factorization: diagonal blocks, panels, trailing
   // per column data (block order = descending Ritz value)
   double theta[kMaxM];
   double rnorm[kMaxM];
@@ -217,7 +222,8 @@ struct CholShared {
   int* Np;
   int* nx;
   int* stop;
-  double* red;  // blockDim.x / 64 doubles
+  double* red;  // blockDim.x / 64 + 128 doubles: reduction slots, then the
+                // block's Ritz values and residual norms (64 each)
 };
 hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st);
 hipError_t launch_rr(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);

@@ -120,7 +120,7 @@ struct psdp_handle_s {
   unsigned long long calls = 0;
   int rr_method = 0;  // 0: column-parallel tridiagonal + twisted vectors + WY back-transform,
                       // 1: Jacobi, 2: first tridiagonal design (inverse iteration)
-  bool trace = false; // PSDP_TRACE=1: one line per iteration on stderr
+  int trace = 0;      // PSDP_TRACE=1: one line per iteration on stderr (2: RR stages)
   bool prof = false;
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<PendingEvent> pending;
@@ -466,6 +466,14 @@ struct Solver {
                    hs->iter, mode, pprec, hs->N, hs->Np, hs->mk, hs->npos_blk, hs->npos_rr,
                    hs->stop, hs->res_max_pos, hs->guard_res, hs->tol, ph[0], ph[1], ph[2], ph[3],
                    pc[0], pc[1], pc[2], pc[3], pc[4]);
+      if (h->trace > 1)
+        std::fprintf(stderr,
+                     "psdp:   rr_sub_us %.0f %.0f | %.0f %.0f %.0f %.0f | rounds %lld mgs %.0f"
+                     " | chol_sub_us %.0f %.0f %.0f\n",
+                     hs->t_sub[0] * 1e-2, hs->t_sub[1] * 1e-2, hs->t_sub[2] * 1e-2,
+                     hs->t_sub[3] * 1e-2, hs->t_sub[4] * 1e-2, hs->t_sub[5] * 1e-2,
+                     hs->t_sub[6], hs->t_sub[7] * 1e-2, hs->t_sub[8] * 1e-2,
+                     hs->t_sub[9] * 1e-2, hs->t_sub[10] * 1e-2);
     }
     if (h->prof && hs->stop == kRunning) {
       auto& e = h->prof_tab["rr_stats"];  // launches: RR calls, bytes: sum Np, flops: sum rounds
@@ -596,7 +604,7 @@ psdp_status psdp_create(psdp_handle* out, int device, void* stream) {
     const int v = std::atoi(m);
     h->rr_method = (v == 1 || v == 2) ? v : 0;
   }
-  if (const char* t = std::getenv("PSDP_TRACE")) h->trace = std::atoi(t) != 0;
+  if (const char* t = std::getenv("PSDP_TRACE")) h->trace = std::atoi(t);
   if (hipHostMalloc((void**)&h->h_state, sizeof(State), hipHostMallocDefault) != hipSuccess) {
     delete h;
     return PSDP_ERR_OUT_OF_MEMORY;

@@ -229,7 +229,7 @@ struct ConeSolver {
       ra.lds_cap = ba.lds_doubles;
       ra.scratch = w.rrs;
       ra.st = st;
-      rr_fast_body<6, 6, kBThreads>(ra, lds, sh.rr);  // 16 x 16 thread grid, N <= 96
+      rr_fast_body<6, 6, kBThreads, false>(ra, lds, sh.rr);  // 16 x 16 thread grid, N <= 96
       __syncthreads();
     }
     // X = S2 C, AX = AS C, P = S2[:, nx:] C[nx:, :], R = AX - X diag(theta)
@@ -467,7 +467,7 @@ struct ConeSolver {
 template <bool RRFULL>
 __global__ __launch_bounds__(kBThreads, RRFULL ? 1 : 2) void k_batched(BatchArgs ba) {
   extern __shared__ double lds[];
-  __shared__ double red[kBThreads / 64];
+  __shared__ double red[kBThreads / 64 + 128];
   __shared__ int s_list[kMaxN], s_kind[kMaxN], s_col[kMaxN], s_keep[kMaxN];
   __shared__ int s_N, s_Np, s_nx, s_stop, s_next;
   __shared__ double s_lo[kMaxM], s_hi[kMaxM];

@@ -25,19 +25,64 @@ __global__ __launch_bounds__(kFastThreads) void k_rr_fast(RRArgs a) {
   __shared__ double s_tnorm, s_pivmin;
   if (a.st->stop) return;
   RRShared sh{s_lo, s_hi, &s_npos, &s_tnorm, &s_pivmin};
-  rr_fast_body<5, 9, kFastThreads>(a, lds, sh);  // 32 x 16 thread grid, N <= 144
+  // 32 x 16 thread grid, N <= 144; the reflectors go to a.scratch
+  rr_fast_body<5, 9, kFastThreads, true>(a, lds, sh);
+}
+
+// Back-transformation of the Ritz vectors of the tridiagonal matrix (C, in
+// place) by the reflectors k_rr_fast left in a.scratch (packed lower
+// triangle, then tau): one workgroup per 16 columns of C.
+constexpr int kBackThreads = 256;
+constexpr int kBackCols = 16;
+
+__host__ __device__ inline size_t rr_back_lds_doubles(int N) {
+  const size_t n = N, ldy = (N & 1) ? n : n + 1;
+  return n * (n + 1) / 2 + n + ldy * kBackCols + kWYBlock * kWYBlock + kWYLd * kBackCols;
+}
+
+__global__ __launch_bounds__(kBackThreads) void k_rr_back(RRArgs a) {
+  extern __shared__ double lds[];
+  State* st = a.st;
+  if (st->stop) return;
+  const int N = st->Np, mk = min(a.mtarget, N);
+  const int j0 = blockIdx.x * kBackCols;
+  if (j0 >= mk) return;
+  const int nc = min(kBackCols, mk - j0);
+  const int ldy = (N & 1) ? N : N + 1;
+  const size_t n2 = (size_t)N * (N + 1) / 2;
+  double* P = lds;
+  double* tau = P + n2;
+  double* Y = tau + N;
+  double* Tb = Y + (size_t)ldy * kBackCols;
+  double* Wb = Tb + kWYBlock * kWYBlock;
+  for (size_t x = threadIdx.x; x < n2 + N; x += kBackThreads) P[x] = a.scratch[x];  // P, tau
+  for (int x = threadIdx.x; x < ldy * kBackCols; x += kBackThreads) {
+    const int i = x % ldy, j = x / ldy;
+    Y[x] = (i < N && j < nc) ? a.C[i + (size_t)(j0 + j) * a.ldc] : 0.0;
+  }
+  __syncthreads();
+  wy_back<kBackThreads, 9, 2>(N, P, tau, Y, ldy, nc, Tb, Wb, blockIdx.x == 0 ? st : nullptr);
+  for (int x = threadIdx.x; x < N * nc; x += kBackThreads) {
+    const int i = x % N, j = x / N;
+    a.C[i + (size_t)(j0 + j) * a.ldc] = Y[i + (size_t)j * ldy];
+  }
 }
 
 static int g_tri_lds_limit = 56 * 1024;
 
 hipError_t launch_rr_fast(const RRArgs& a_in, int Np_host, int mk_host, hipStream_t st) {
   RRArgs a = a_in;
-  if (Np_host > 144) return hipErrorInvalidValue;
+  if (Np_host > 144 || std::min(mk_host, Np_host) > kMaxM) return hipErrorInvalidValue;
   const size_t doubles =
       rr_fast_lds_doubles(Np_host, std::min(mk_host, Np_host), kFastThreads, 5, 9);
   if (doubles * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
+  const size_t back = rr_back_lds_doubles(Np_host);
+  if (back * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
   a.lds_cap = doubles;
   hipLaunchKernelGGL(k_rr_fast, dim3(1), dim3(kFastThreads), doubles * 8, st, a);
+  const int mk = std::min(mk_host, Np_host);
+  hipLaunchKernelGGL(k_rr_back, dim3((mk + kBackCols - 1) / kBackCols), dim3(kBackThreads),
+                     back * 8, st, a);
   return hipGetLastError();
 }
 
@@ -72,6 +117,8 @@ hipError_t rr_tri_init() {
     (void)hipFuncSetAttribute((const void*)k_rr_tri<false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void*)k_rr_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr_back, hipFuncAttributeMaxDynamicSharedMemorySize,
                               dyn);
   }
   (void)hipGetLastError();

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kRRThreads) void k_rr(RRArgs a) {
 
 __global__ __launch_bounds__(kSmallThreads) void k_decide_chol(DecideArgs a) {
   extern __shared__ double lds[];
-  __shared__ double red[kSmallThreads / 64];
+  __shared__ double red[kSmallThreads / 64 + 128];
   __shared__ int s_list[kMaxN], s_kind[kMaxN], s_col[kMaxN], s_keep[kMaxN];
   __shared__ int s_N, s_Np, s_nx, s_stop;
   CholShared sh{s_list, s_kind, s_col, s_keep, &s_N, &s_Np, &s_nx, &s_stop, red};

@@ -25,6 +25,7 @@
 namespace psdp {
 
 constexpr int kWYBlock = 16;
+constexpr int kWYLd = 17;  // leading dimension of W in LDS (odd: no bank conflicts)
 
 __host__ __device__ inline int pk_cb(int j, int N) { return j * N - (j * (j + 1)) / 2; }
 
@@ -32,12 +33,12 @@ __host__ __device__ inline int pk_cb(int j, int N) { return j * N - (j * (j + 1)
 // Tb + Wb region: the block reflector factor and V^T Y, or the three
 // factor diagonals of one inverse-iteration solve
 __host__ __device__ inline size_t rr_fast_tbw(int N, int mk) {
-  const size_t wy = (size_t)kWYBlock * kWYBlock + (size_t)kWYBlock * mk;
+  const size_t wy = (size_t)kWYBlock * kWYBlock + (size_t)kWYLd * mk;
   return wy > 3 * (size_t)N ? wy : 3 * (size_t)N;
 }
 
-// The Y region also hosts the reflector buffers and per-wave partial
-// products of phase 1 and the Sturm counts of phase 2.
+// The Y region also hosts the six LP-vectors of phase 1 and the Sturm
+// counts of phase 2.
 // LP: padded length of the phase-1 vectors (rows covered by the thread grid)
 __host__ __device__ inline size_t rr_fast_lp(int nthreads, int nbr, int nbc) {
   const size_t a = (size_t)(nthreads / 16) * nbr, b = 16 * (size_t)nbc;
@@ -48,7 +49,7 @@ __host__ __device__ inline size_t rr_fast_yspace(int N, int mk, int nthreads, si
   const size_t n = N;
   const size_t ldy = (N & 1) ? n : n + 1;
   size_t y = ldy * (size_t)mk;
-  if (y < 5 * lp) y = 5 * lp;
+  if (y < 6 * lp) y = 6 * lp;
   if (y < (size_t)nthreads) y = nthreads;
   return y;
 }
@@ -172,24 +173,27 @@ __device__ inline double sel(const double (&row)[NB], int q) {
 
 // Householder tridiagonalization with the matrix in registers.  The NT
 // threads form an RG x 16 grid (RG = NT / 16 row groups, 16 column groups):
-// thread (r, c) = (tid >> 4, tid & 15) holds A(r + RG li, c + 16 lj) for
-// li < NBR, lj < NBC (both triangles), so the 16 threads of one row group
-// are 16 lanes of one wave.  Per step k:
-//   (a) with x the raw column k below the diagonal (LDS column buffer),
-//       every thread forms its partial rows of A x, summed over the 16
-//       lanes of the row group (DPP), its part of x^T A x, and every wave
-//       the norm of x; the owners of column k + 1 publish that column;
-//   (b) every thread forms the reflector scalars; with v = scale x +
-//       g e_{k+1} (g = 1 - scale x_{k+1}), A v and v^T A v follow from A x,
-//       x^T A x and column k + 1; one thread per trailing row forms
-//       w = t A v - (t^2 / 2)(v^T A v) v, keeps the reflector in P, and forms
-//       column k + 1 after the update (the next column buffer) and its
-//       diagonal entry;
-//   (c) every thread applies A -= v w^T + w v^T to its block.
-// Two barriers per step.  Vectors in LDS are zero-padded to LP entries so
-// that threads read them without bounds tests.  On return: d, e (N - 1
-// entries), tau, and the reflectors (unit entry at row k + 1 included) in
-// the packed column-major lower triangle P.
+// thread (r, c) = (tid >> 4, tid & 15) holds A(r NBR + li, c + 16 lj) for
+// li < NBR, lj < NBC (both triangles): contiguous row blocks, so the 16
+// threads of one row group are 16 lanes of one wave and each wave owns 4 NBR
+// consecutive rows.  LDS vectors (LP entries, zero-padded) hold the current
+// column x (rows <= k zero), the reflector v and w (rows <= k zero), A x and
+// column k + 1 before the update.  Per step k:
+//   (a) every thread loads x on its columns and forms |x|^2 over the 16 lanes
+//       of its row group (DPP); waves that own a row below k form their
+//       rows of A x (summed over the row group) and their part of x^T A x;
+//       the owners of column k + 1 publish it;
+//   (b) every thread forms the reflector scalars (dlarfg convention); with
+//       v = scale x + g e_{k+1} (g = 1 - scale x_{k+1}), A v and v^T A v follow
+//       from A x, x^T A x and column k + 1; one thread per trailing row forms
+//       w = t A v - (t^2 / 2)(v^T A v) v, stores v and w, keeps the reflector
+//       in P, and forms column k + 1 after the update (the next column
+//       buffer) and its diagonal entry;
+//   (c) waves that own a row below k apply A -= v w^T + w v^T to their block
+//       (entries in finished rows or columns see zero v and w and stay put).
+// Two barriers per step.  On return: d, e (N - 1 entries), tau, and the
+// reflectors (unit entry at row k + 1 included) in the packed column-major
+// lower triangle P.
 template <int NBR, int NBC, int NT>
 __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d, double* e,
                                    double* tau, double* buf, double* red) {
@@ -197,82 +201,97 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
   constexpr int LP = (RG * NBR > 16 * NBC) ? RG * NBR : 16 * NBC;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int r = tid >> 4, c = tid & 15;
-  // LDS vectors (LP each): column buffers (2), w, the published column, t A v
-  double* colb[2] = {buf, buf + LP};
-  double* wb = buf + 2 * LP;
-  double* cpre = buf + 3 * LP;
+  const int row0 = r * NBR;
+  const int wave_last_row = (4 * wv + 4) * NBR - 1;
+  // LDS vectors: two column buffers at buf and buf + LP (addressed by offset:
+  // a pointer picked from an array loses its LDS address space), v, w, A x,
+  // column k + 1
+  double* vb = buf + 2 * LP;
+  double* wb = buf + 3 * LP;
   double* pf = buf + 4 * LP;
+  double* cpre = buf + 5 * LP;
   double A[NBR][NBC];
 #pragma unroll
   for (int li = 0; li < NBR; ++li)
 #pragma unroll
     for (int lj = 0; lj < NBC; ++lj) {
-      const int i = r + RG * li, j = c + 16 * lj;
+      const int i = row0 + li, j = c + 16 * lj;
       A[li][lj] = (i < N && j < N) ? 0.5 * (a.K[i + (size_t)j * a.ldk] + a.K[j + (size_t)i * a.ldk])
                                    : 0.0;
     }
   // column 0 below the diagonal, and d[0]
   for (int i = tid; i < LP; i += NT) {
-    colb[0][i] = (i >= 1 && i < N) ? 0.5 * (a.K[i] + a.K[(size_t)i * a.ldk]) : 0.0;
-    colb[1][i] = 0.0;  // rows at or beyond N stay zero in every buffer
+    buf[i] = (i >= 1 && i < N) ? 0.5 * (a.K[i] + a.K[(size_t)i * a.ldk]) : 0.0;
+    buf[LP + i] = 0.0;  // rows at or beyond N stay zero in every vector
+    vb[i] = 0.0;
     wb[i] = 0.0;
-    cpre[i] = 0.0;
     pf[i] = 0.0;
+    cpre[i] = 0.0;
   }
   if (tid == 0) d[0] = a.K[0];
   __syncthreads();
+  long long tl = wall_clock64(), tacc0 = 0, tacc1 = 0;
   for (int k = 0; k + 2 < N; ++k) {
-    const double* col = colb[k & 1];
-    double* coln = colb[(k + 1) & 1];
-    // ---- (a) products with the raw column x (x_i = A(i, k) for i > k, 0
-    // otherwise); the reflector is v = scale x + g e_{k+1}, g = 1 - scale x_{k+1}
+    const double* col = buf + (k & 1) * LP;
+    double* coln = buf + ((k + 1) & 1) * LP;
+    const bool live = wave_last_row > k;  // uniform: this wave owns a row below k
+    // ---- (a)
+    double xc[NBC];
+#pragma unroll
+    for (int q = 0; q < NBC; ++q) xc[q] = col[c + 16 * q];
     double xs = 0.0;
-    for (int i = k + 2 + lane; i < N; i += 64) xs = fma(col[i], col[i], xs);
-    double xr[NBR], xc[NBC];
 #pragma unroll
-    for (int q = 0; q < NBR; ++q) {
-      const int i = r + RG * q;
-      xr[q] = (i > k) ? col[i] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < NBC; ++q) {
-      const int j = c + 16 * q;
-      xc[q] = (j > k) ? col[j] : 0.0;
-    }
-    // the owners of column k + 1 publish it (before this step's update)
-    if (c == ((k + 1) & 15)) {
-      const int lj1 = (k + 1) >> 4;
-#pragma unroll
-      for (int li = 0; li < NBR; ++li) {
-        double x = A[li][0];
-#pragma unroll
-        for (int q = 1; q < NBC; ++q) x = (q == lj1) ? A[li][q] : x;
-        cpre[r + RG * li] = x;
-      }
+    for (int q = 0; q < NBC; ++q) xs = fma(xc[q], xc[q], xs);
+    xs = row16_sum(xs);  // |x|^2, x_{k+1} included
+    // reflector scalars (dlarfg convention), off the critical path of (b)
+    const double alpha = col[k + 1];
+    double t = 0.0, beta = alpha, scale = 0.0;
+    if (xs - alpha * alpha > 0.0) {
+      beta = -copysign(sqrt(xs), alpha);
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
     }
     double xax = 0.0;
+    if (live) {
+      double xr[NBR];
 #pragma unroll
-    for (int li = 0; li < NBR; ++li) {
-      double s0 = 0.0;
-      if (RG * li + RG - 1 > k) {
+      for (int q = 0; q < NBR; ++q) xr[q] = col[row0 + q];
+#pragma unroll
+      for (int li = 0; li < NBR; ++li) {
+        double s0 = 0.0;
 #pragma unroll
         for (int lj = 0; lj < NBC; ++lj) s0 = fma(A[li][lj], xc[lj], s0);
-      }
-      s0 = row16_sum(s0);  // (A x) for row r + RG li
-      if (c == 0) {
+        s0 = row16_sum(s0);  // (A x) for row row0 + li
+        if (c == 0) pf[row0 + li] = s0;
         xax = fma(xr[li], s0, xax);
-        pf[r + RG * li] = s0;
       }
     }
-    xs = wave_sum(xs);  // same value in every wave
-    xax = wave_sum(xax);
-    if (lane == 0) red[wv] = xax;
+    // the owners of column k + 1 publish it (before this step's update)
+    {
+      const int lj1 = (k + 1) >> 4;
+#pragma unroll
+      for (int q = 0; q < NBC; ++q)
+        if (q == lj1 && c == ((k + 1) & 15)) {
+#pragma unroll
+          for (int li = 0; li < NBR; ++li) cpre[row0 + li] = A[li][q];
+        }
+    }
+    // x^T A x of the wave: the four row groups (equal over their 16 lanes)
+    {
+      int2 v2 = __builtin_bit_cast(int2, xax);
+      double s4 = 0.0;
+#pragma unroll
+      for (int g4 = 0; g4 < 4; ++g4) {
+        int2 u;
+        u.x = __builtin_amdgcn_readlane(v2.x, 16 * g4);
+        u.y = __builtin_amdgcn_readlane(v2.y, 16 * g4);
+        s4 += __builtin_bit_cast(double, u);
+      }
+      if (lane == 0) red[wv] = s4;
+    }
     __syncthreads();
-    // ---- (b) reflector scalars (every thread), w, the reflector kept in P,
-    // the next column
-    const double alpha = col[k + 1];
-    double t, beta, scale;
-    reflector(alpha, xs, t, beta, scale);
+    if (tid == 0) { const long long tn = wall_clock64(); tacc0 += tn - tl; tl = tn; }
+    // ---- (b) v and w, the reflector kept in P, the next column
     const double g = 1.0 - scale * alpha;
     double xaxs = 0.0;
 #pragma unroll
@@ -286,6 +305,9 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
     if (tid == 0) {
       tau[k] = t;
       e[k] = beta;
+      coln[k] = 0.0;  // rows <= k + 1 of the next column, v and w are zero
+      vb[k] = 0.0;
+      wb[k] = 0.0;
     }
     const int ck = pk_cb(k, N);
     for (int i = k + 1 + tid; i < N; i += NT) {
@@ -293,6 +315,7 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
       const double vi = (i == k + 1) ? 1.0 : x * scale;
       const double ci = cpre[i];
       const double wi = (t != 0.0) ? t * (scale * pf[i] + g * ci) + alf * vi : 0.0;
+      vb[i] = (t != 0.0) ? vi : 0.0;
       wb[i] = wi;
       // reflector kept below the diagonal of column k (identity if t = 0)
       P[ck + i] = (t != 0.0) ? vi : ((i == k + 1) ? 1.0 : 0.0);
@@ -302,28 +325,25 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
       coln[i] = (i >= k + 2) ? ci - upd : 0.0;
     }
     __syncthreads();
+    if (tid == 0) { const long long tn = wall_clock64(); tacc1 += tn - tl; tl = tn; }
     // ---- (c) rank-2 update of this thread's block
-    if (t != 0.0) {
+    if (live && t != 0.0) {
       double vr[NBR], vc[NBC], wr[NBR], wc[NBC];
 #pragma unroll
       for (int q = 0; q < NBR; ++q) {
-        const int i = r + RG * q;
-        vr[q] = (i == k + 1) ? 1.0 : xr[q] * scale;
-        wr[q] = (i > k) ? wb[i] : 0.0;
+        vr[q] = vb[row0 + q];
+        wr[q] = wb[row0 + q];
       }
 #pragma unroll
       for (int q = 0; q < NBC; ++q) {
-        const int j = c + 16 * q;
-        vc[q] = (j == k + 1) ? 1.0 : xc[q] * scale;
-        wc[q] = (j > k) ? wb[j] : 0.0;
+        vc[q] = vb[c + 16 * q];
+        wc[q] = wb[c + 16 * q];
       }
 #pragma unroll
       for (int li = 0; li < NBR; ++li)
-        if (RG * li + RG - 1 > k) {
 #pragma unroll
-          for (int lj = 0; lj < NBC; ++lj)
-            A[li][lj] = fma(-vr[li], wc[lj], fma(-wr[li], vc[lj], A[li][lj]));
-        }
+        for (int lj = 0; lj < NBC; ++lj)
+          A[li][lj] = fma(-vr[li], wc[lj], fma(-wr[li], vc[lj], A[li][lj]));
     }
   }
   // last diagonal entry and last off-diagonal from the registers
@@ -331,18 +351,172 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
   for (int li = 0; li < NBR; ++li)
 #pragma unroll
     for (int lj = 0; lj < NBC; ++lj) {
-      const int i = r + RG * li, j = c + 16 * lj;
+      const int i = row0 + li, j = c + 16 * lj;
       if (N >= 2 && i == N - 1 && j == N - 1) d[N - 1] = A[li][lj];
       if (N >= 2 && i == N - 1 && j == N - 2) e[N - 2] = A[li][lj];
     }
   if (tid == 0) {
     tau[max(N - 2, 0)] = 0.0;
     if (N == 1) d[0] = a.K[0];
+    a.st->t_sub[0] = tacc0;
+    a.st->t_sub[1] = tacc1;
   }
   __syncthreads();
 }
 
-template <int NBR, int NBC, int NT>
+// Back-transformation Z = H_0 H_1 ... H_{N-3} Y by blocks of
+// reflectors, last block first, on ncols <= 16 (NTQ - 1) columns of Y:
+// Y <- (I - V T V^T) Y with V the block's reflectors (unit at row k + 1,
+// zero above) and T = U^{-1}, U = diag(1 / tau) + strictly upper part of
+// V^T V (a zero tau gives a zero row and column of T).  Per block:
+//   (i)   G = V^T [V, Y] (16 x (16 + ncols)): each 16-lane row group forms an
+//         LPG x 16 tile over rows b0 + 1 + s + 16 u (lane s), summed over
+//         the row group (DPP);
+//   (ii)  W <- T W by back substitution with U = T^{-1}, one thread per column;
+//   (iii) Y -= V W in the RG x 16 thread grid, rows b0 + 1 + r + RG li,
+//         columns c + 16 lj.
+template <int NT, int NBC, int NTQ>
+__device__ inline void wy_back(int N, const double* P, const double* tau, double* Y, int ldy,
+                               int ncols, double* Tb, double* Wb, State* st) {
+  const int tid = threadIdx.x;
+  {
+    constexpr int RG = NT / 16;            // 16-lane row groups
+    constexpr int LPG = 16 * NTQ / RG;     // reflectors per group in (i)
+    static_assert(16 * NTQ % RG == 0 && 16 % (16 * NTQ / RG) == 0, "row groups per target tile");
+    constexpr int LQ = kWYBlock / LPG;     // groups per target quarter
+    constexpr int NCW = NTQ - 1;           // column tiles of Y (ncols <= 16 NCW)
+    const int g = tid >> 4, s16 = tid & 15, r = tid >> 4, c = tid & 15;
+    const int nref = N - 2;  // reflectors 0 .. N - 3
+    long long tw = wall_clock64(), twa[4] = {0, 0, 0, 0};
+    for (int b0 = nref > 0 ? ((nref - 1) / kWYBlock) * kWYBlock : -1; b0 >= 0; b0 -= kWYBlock) {
+      const int bs = min(kWYBlock, nref - b0);
+      {
+        const int lq = g % LQ, tq = g / LQ;  // reflectors lq LPG .., targets 16 tq ..
+        double acc[LPG][16];
+#pragma unroll
+        for (int x = 0; x < LPG; ++x)
+#pragma unroll
+          for (int tt = 0; tt < 16; ++tt) acc[x][tt] = 0.0;
+#pragma unroll 1
+        for (int u = 0; u < NBC; ++u) {
+          const int i = b0 + 1 + s16 + 16 * u, ic = min(i, N - 1);
+          double vx[LPG];
+#pragma unroll
+          for (int x = 0; x < LPG; ++x) {
+            const int l = lq * LPG + x, kl = b0 + l;
+            const double pv_ = P[pk_cb(min(kl, N - 3), N) + ic];
+            vx[x] = (l < bs && i >= kl + 1 && i < N) ? ((i == kl + 1) ? 1.0 : pv_) : 0.0;
+          }
+          if (tq == 0) {  // V^T V (uniform per wave)
+#pragma unroll
+            for (int tt = 0; tt < 16; ++tt) {
+              const int kq = b0 + tt;
+              const double pq = P[pk_cb(min(kq, N - 3), N) + ic];
+              const double vq = (tt < bs && i >= kq + 1 && i < N) ? ((i == kq + 1) ? 1.0 : pq) : 0.0;
+#pragma unroll
+              for (int x = 0; x < LPG; ++x) acc[x][tt] = fma(vx[x], vq, acc[x][tt]);
+            }
+          } else {  // V^T Y on columns 16 (tq - 1) .. (v is zero past N)
+#pragma unroll
+            for (int tt = 0; tt < 16; ++tt) {
+              const int jc = min(16 * (tq - 1) + tt, ncols - 1);
+              const double yv = Y[ic + (size_t)jc * ldy];
+#pragma unroll
+              for (int x = 0; x < LPG; ++x) acc[x][tt] = fma(vx[x], yv, acc[x][tt]);
+            }
+          }
+        }
+#pragma unroll
+        for (int x = 0; x < LPG; ++x)
+#pragma unroll
+          for (int tt = 0; tt < 16; ++tt) acc[x][tt] = row16_sum(acc[x][tt]);
+        if (s16 == 0) {
+#pragma unroll
+          for (int x = 0; x < LPG; ++x) {
+            const int l = lq * LPG + x;
+#pragma unroll
+            for (int tt = 0; tt < 16; ++tt) {
+              if (tq == 0) {
+                Tb[l + kWYBlock * tt] = acc[x][tt];
+              } else {
+                const int j = 16 * (tq - 1) + tt;
+                if (j < ncols) Wb[l + kWYLd * j] = acc[x][tt];
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) { const long long tn = wall_clock64(); twa[0] += tn - tw; tw = tn; }
+      // W <- T W with T = U^{-1}, U = diag(1 / tau) + strictly upper part of
+      // V^T V: back substitution U W' = W, one thread per column of W,
+      // W'(l) = tau_l (W(l) - sum_{m > l} G(l, m) W'(m)) (zero when tau_l = 0)
+      for (int j = tid; j < ncols; j += NT) {
+        double w[kWYBlock];
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) {
+          const double wl = Wb[l + kWYLd * j];
+          w[l] = (l < bs) ? wl : 0.0;
+        }
+#pragma unroll
+        for (int l = kWYBlock - 1; l >= 0; --l) {
+          double s = w[l];
+#pragma unroll
+          for (int m = l + 1; m < kWYBlock; ++m) s = fma(-Tb[l + kWYBlock * m], w[m], s);
+          const double tl = (l < bs) ? tau[b0 + min(l, bs - 1)] : 0.0;
+          w[l] = tl * s;
+          asm volatile("" ::: "memory");  // one row of G in flight at a time
+        }
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) Wb[l + kWYLd * j] = w[l];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const long long tn = wall_clock64();
+        twa[1] += tn - tw;
+        tw = tn;
+      }
+      // Y -= V W on rows b0 + 1 .. N - 1
+      {
+        const int i0 = b0 + 1;
+        double wr3[NCW][kWYBlock];  // this thread's columns of W (rows >= bs are zero)
+#pragma unroll
+        for (int lj = 0; lj < NCW; ++lj) {
+          const int jc = min(c + 16 * lj, ncols - 1);
+#pragma unroll
+          for (int l = 0; l < kWYBlock; ++l) {
+            const double wl = Wb[l + kWYLd * jc];
+            wr3[lj][l] = (l < bs) ? wl : 0.0;
+          }
+        }
+        for (int li = 0; i0 + r + RG * li < N; ++li) {
+          const int i = i0 + r + RG * li;
+          double vr[kWYBlock];
+#pragma unroll
+          for (int l = 0; l < kWYBlock; ++l) {
+            const int kl = b0 + l;
+            const double pl = P[pk_cb(min(kl, N - 3), N) + i];  // in range for every l
+            vr[l] = (l < bs && i >= kl + 1) ? ((i == kl + 1) ? 1.0 : pl) : 0.0;
+          }
+#pragma unroll
+          for (int lj = 0; lj < NCW; ++lj) {
+            const int j = c + 16 * lj, jc = min(j, ncols - 1);
+            double s = Y[i + (size_t)jc * ldy];
+#pragma unroll
+            for (int l = 0; l < kWYBlock; ++l) s = fma(-vr[l], wr3[lj][l], s);
+            if (j < ncols) Y[i + (size_t)j * ldy] = s;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid == 0) { const long long tn = wall_clock64(); twa[3] += tn - tw; tw = tn; }
+    }
+    if (tid == 0 && st)
+      for (int q = 0; q < 4; ++q) st->t_sub[2 + q] = twa[q];
+  }
+}
+
+template <int NBR, int NBC, int NT, bool EXPORT>
 __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared& sh) {
   double* s_lo = sh.lo;
   double* s_hi = sh.hi;
@@ -399,11 +573,32 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
     const double pad = 2.2e-16 * tnorm * 4.0 * N + 2.0 * pivmin;
     gl -= pad;
     gu += pad;
-    for (int j = tid; j < mk; j += nt) { s_lo[j] = gl; s_hi[j] = gu; }
-    if (tid == nt - 1) s_npos = N - sturm_count(d, e2, N, 0.0, pivmin);
-    __syncthreads();
+    // shared first round: nt - 1 equispaced shifts over [gl, gu] for all
+    // the eigenvalues at once, and the count below zero; each eigenvalue's
+    // bracket follows by binary search over the counts, keeping
+    // count(lo) <= target < count(hi)
+    {
+      const int ng = nt - 1;
+      const double x = (tid < ng) ? gl + (gu - gl) * (double)(tid + 1) / (double)(ng + 1) : 0.0;
+      cnts[tid] = sturm_count(d, e2, N, x, pivmin);
+      __syncthreads();
+      if (tid == nt - 1) s_npos = N - cnts[tid];
+      for (int j = tid; j < mk; j += nt) {
+        const int target = N - 1 - j;
+        int a0 = -1, a1 = ng;  // virtual counts: cnt(-1) = 0 at gl, cnt(ng) = N at gu
+        while (a1 - a0 > 1) {
+          const int mid = (a0 + a1) >> 1;
+          if (cnts[mid] <= target) a0 = mid;
+          else a1 = mid;
+        }
+        s_lo[j] = (a0 < 0) ? gl : gl + (gu - gl) * (double)(a0 + 1) / (double)(ng + 1);
+        s_hi[j] = (a1 >= ng) ? gu : gl + (gu - gl) * (double)(a1 + 1) / (double)(ng + 1);
+      }
+      __syncthreads();
+    }
     const int per = max(1, nt / max(mk, 1));  // shifts per eigenvalue per round
     const int j_me = tid / per, s_me = tid % per;
+    int rounds = 1;
     for (int round = 0; round < 64; ++round) {
       bool done = true;
       for (int j = 0; j < mk; ++j) {
@@ -412,6 +607,7 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
         if (w > tolj) { done = false; break; }
       }
       if (done) break;
+      ++rounds;
       if (j_me < mk) {
         const double lo = s_lo[j_me], hi = s_hi[j_me];
         const double x = lo + (hi - lo) * (double)(s_me + 1) / (double)(per + 1);
@@ -433,8 +629,10 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
       }
       __syncthreads();
     }
+    if (tid == 0) st->t_sub[6] = rounds;
   }
   if (tid == 0) st->t_phase[2] = wall_clock64();
+  long long t_mgs = wall_clock64();
 
   // ---- 3. eigenvectors: twisted factorization, one thread per vector
   const double pfloor = fmax(2.2e-16 * tnorm, 1e-300);
@@ -451,6 +649,7 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
     for (int i = 0; i < N; ++i) y[i] *= inv;
   }
   __syncthreads();
+  if (tid == 0) t_mgs = wall_clock64();
   // modified Gram-Schmidt inside clusters (wave 0)
   if (wv == 0) {
     for (int j = 1; j < mk; ++j) {
@@ -497,6 +696,7 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
     }
   }
   __syncthreads();
+  if (tid == 0) st->t_sub[7] = wall_clock64() - t_mgs;
   // Rayleigh quotients y^T T y
   for (int j = tid; j < mk; j += nt) {
     const double* y = Y + (size_t)j * ldy;
@@ -512,137 +712,13 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
   __syncthreads();
   if (tid == 0) st->t_phase[3] = wall_clock64();
 
-  // ---- 4. back-transformation Z = H_0 H_1 ... H_{N-3} Y by blocks of
-  // reflectors, last block first: Y <- (I - V T V^T) Y with V the block's
-  // reflectors (unit at row k + 1, zero above) and T = U^{-1},
-  // U = diag(1 / tau) + strictly upper part of V^T V (a zero tau gives a
-  // zero row and column of T)
-  {
-    const int nref = N - 2;  // reflectors 0 .. N - 3
-    for (int b0 = nref > 0 ? ((nref - 1) / kWYBlock) * kWYBlock : -1; b0 >= 0; b0 -= kWYBlock) {
-      const int bs = min(kWYBlock, nref - b0);
-      // U's strictly upper part v_l . v_q (l < q) into Tb
-      for (int x = tid; x < bs * bs; x += nt) {
-        const int l = x % bs, q = x / bs;
-        if (l < q) {
-          const int cl = pk_cb(b0 + l, N), cq = pk_cb(b0 + q, N), kq = b0 + q;
-          double s0 = P[cl + kq + 1], s1 = 0.0, s2 = 0.0, s3 = 0.0;  // v_q(kq + 1) = 1
-          int i = kq + 2;
-          for (; i + 3 < N; i += 4) {
-            const double a0 = P[cl + i], a1 = P[cl + i + 1], a2 = P[cl + i + 2], a3 = P[cl + i + 3];
-            const double b0 = P[cq + i], b1 = P[cq + i + 1], b2 = P[cq + i + 2], b3 = P[cq + i + 3];
-            s0 = fma(a0, b0, s0);
-            s1 = fma(a1, b1, s1);
-            s2 = fma(a2, b2, s2);
-            s3 = fma(a3, b3, s3);
-          }
-          for (; i < N; ++i) s0 = fma(P[cl + i], P[cq + i], s0);
-          Tb[l + kWYBlock * q] = (s0 + s1) + (s2 + s3);
-        }
-      }
-      __syncthreads();
-      // column q of T by back substitution in lane q (U t = e_q)
-      double tcol[kWYBlock];
-      if (tid < bs) {
-        const int q = tid;
-#pragma unroll
-        for (int l = 0; l < kWYBlock; ++l) tcol[l] = 0.0;
-        const double tq = tau[b0 + q];
-        for (int l = kWYBlock - 1; l >= 0; --l) {
-          if (l > q) continue;
-          double val;
-          if (l == q) {
-            val = tq;
-          } else {
-            const double tl = tau[b0 + l];
-            double s = 0.0;
-#pragma unroll
-            for (int cc = 0; cc < kWYBlock; ++cc)
-              if (cc > l && cc <= q) s = fma(Tb[l + kWYBlock * cc], tcol[cc], s);
-            val = (tl == 0.0) ? 0.0 : -tl * s;
-          }
-#pragma unroll
-          for (int cc = 0; cc < kWYBlock; ++cc)
-            if (cc == l) tcol[cc] = val;
-        }
-      }
-      __syncthreads();  // every lane has read U
-      if (tid < bs) {
-#pragma unroll
-        for (int l = 0; l < kWYBlock; ++l) Tb[l + kWYBlock * tid] = (l <= tid) ? tcol[l] : 0.0;
-      }
-      // W = V^T Y (bs x mk): thread (j, lg) forms rows lg, lg + 8 of column j
-      for (int x = tid; x < 8 * mk; x += nt) {
-        const int j = x % mk, lg = x / mk;
-        const double* y = Y + (size_t)j * ldy;
-        const int l0 = lg, l1 = lg + 8;
-        double w0 = 0.0, w1 = 0.0;
-        if (l0 < bs) {
-          const int k0 = b0 + l0, c0 = pk_cb(k0, N);
-          double u0 = y[k0 + 1], u1 = 0.0, u2 = 0.0, u3 = 0.0;
-          int i = k0 + 2;
-          for (; i + 3 < N; i += 4) {
-            const double a0 = P[c0 + i], a1 = P[c0 + i + 1], a2 = P[c0 + i + 2], a3 = P[c0 + i + 3];
-            const double b0_ = y[i], b1 = y[i + 1], b2 = y[i + 2], b3 = y[i + 3];
-            u0 = fma(a0, b0_, u0);
-            u1 = fma(a1, b1, u1);
-            u2 = fma(a2, b2, u2);
-            u3 = fma(a3, b3, u3);
-          }
-          for (; i < N; ++i) u0 = fma(P[c0 + i], y[i], u0);
-          w0 = (u0 + u1) + (u2 + u3);
-        }
-        if (l1 < bs) {
-          const int k1 = b0 + l1, c1 = pk_cb(k1, N);
-          double u0 = y[k1 + 1], u1 = 0.0, u2 = 0.0, u3 = 0.0;
-          int i = k1 + 2;
-          for (; i + 3 < N; i += 4) {
-            const double a0 = P[c1 + i], a1 = P[c1 + i + 1], a2 = P[c1 + i + 2], a3 = P[c1 + i + 3];
-            const double b0_ = y[i], b1 = y[i + 1], b2 = y[i + 2], b3 = y[i + 3];
-            u0 = fma(a0, b0_, u0);
-            u1 = fma(a1, b1, u1);
-            u2 = fma(a2, b2, u2);
-            u3 = fma(a3, b3, u3);
-          }
-          for (; i < N; ++i) u0 = fma(P[c1 + i], y[i], u0);
-          w1 = (u0 + u1) + (u2 + u3);
-        }
-        if (l0 < bs) Wb[l0 + kWYBlock * j] = w0;
-        if (l1 < bs) Wb[l1 + kWYBlock * j] = w1;
-      }
-      __syncthreads();
-      // W <- T W (one thread per column of W)
-      for (int j = tid; j < mk; j += nt) {
-        double w[kWYBlock];
-#pragma unroll
-        for (int l = 0; l < kWYBlock; ++l) w[l] = (l < bs) ? Wb[l + kWYBlock * j] : 0.0;
-#pragma unroll
-        for (int l = 0; l < kWYBlock; ++l) {
-          double s = 0.0;
-#pragma unroll
-          for (int cc = 0; cc < kWYBlock; ++cc)
-            if (cc >= l) s = fma(Tb[l + kWYBlock * cc], w[cc], s);
-          if (l < bs) Wb[l + kWYBlock * j] = s;
-        }
-      }
-      __syncthreads();
-      // Y -= V W: thread per row (rows above b0 + 1 are untouched)
-      for (int i = b0 + 1 + tid; i < N; i += nt) {
-        double vrow[kWYBlock];
-#pragma unroll
-        for (int l = 0; l < kWYBlock; ++l) {
-          const int kl = b0 + l;
-          vrow[l] = (l < bs && i >= kl + 1) ? ((i == kl + 1) ? 1.0 : P[pk_cb(kl, N) + i]) : 0.0;
-        }
-        for (int j = 0; j < mk; ++j) {
-          double s = 0.0;
-#pragma unroll
-          for (int l = 0; l < kWYBlock; ++l) s = fma(vrow[l], Wb[l + kWYBlock * j], s);
-          Y[i + (size_t)j * ldy] -= s;
-        }
-      }
-      __syncthreads();
-    }
+  if (EXPORT) {
+    // reflectors and tau to the global scratch for the back-transformation kernel
+    const size_t n2 = (size_t)N * (N + 1) / 2;
+    for (size_t x = tid; x < n2; x += nt) a.scratch[x] = P[x];
+    for (int x = tid; x < N; x += nt) a.scratch[n2 + x] = tau[x];
+  } else {
+    wy_back<NT, NBC, 4>(N, P, tau, Y, ldy, mk, Tb, Wb, st);
   }
   if (tid == 0) st->t_phase[4] = wall_clock64();
   // ---- outputs: C = Z (N x mk), Ritz values descending
