@@ -1189,6 +1189,10 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     if (stop == kStalled) {
       if (phase == 2 && opt.ladder) {
         phase = 1;
+        // the low-precision copy of A holds BF16: convert it to FP32 again
+        int nb2 = 0;
+        HIP_TRY(launch_ingest(X, ldx, n, sign, w.A64, w.L, w.L, w.Alp, 1, w.fro_part, w.nonfinite,
+                              s, &nb2));
         if ((rc = refresh(1)) != PSDP_OK) return rc;
         reset_stall();
         continue;

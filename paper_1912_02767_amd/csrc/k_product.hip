@@ -80,140 +80,156 @@ __global__ __launch_bounds__(256) void k_product_ref(const void* __restrict__ A,
 }
 
 // ----------------------------------------------------------- MFMA path --
-// Y = A S on the matrix cores, split over K (rows of S) into `splitk`
-// slices whose partial products are summed afterwards in a fixed order.
-// Workgroup: 4 waves, 64 rows of Y (16 per wave) and every column of S
-// (up to kMaxN, 16 per MFMA tile); S is staged through LDS in the product
-// precision, k-contiguous per column; A is read straight from HBM.
-//   FP64: v_mfma_f64_16x16x4f64   A[i][k]: lane -> (l % 16, l / 16)
-//   FP32: v_mfma_f32_16x16x4f32   same operand layout, FP32 accumulate
-//   BF16: v_mfma_f32_16x16x32_bf16 lane holds 8 consecutive k: (l % 16,
-//         8 (l / 16) + 0..7); A is symmetric, so A[i][k] is read as A[k][i]
-//         (k contiguous in memory)
+// Y = A S on the matrix cores, split over K (rows of S) into slices whose
+// partial products are summed afterwards in a fixed order.  Workgroup: four
+// waves, 16 rows of Y each, every column of S (up to kPMaxCols, 16 per MFMA
+// tile).  A is symmetric, so row i of A is read as column i: each lane loads
+// 16 contiguous bytes of one row per step, which feed TPL MFMAs:
+//   FP64 v_mfma_f64_16x16x4f64   2 k per lane, slot g = l / 16 <-> k = kb + 2 g + t
+//   FP32 v_mfma_f32_16x16x4f32   4 k per lane, slot g <-> k = kb + 4 g + t
+//   BF16 v_mfma_f32_16x16x32_bf16 8 k per lane (the instruction's own layout)
+// (row l % 16 of the tile); B takes the same k for the same slot, so the
+// lane's B values of one step are 16 contiguous bytes of a column of the S
+// chunk in LDS (k contiguous, padded).  The A loads of the next chunk are in
+// flight while the current chunk is multiplied (a ring of KC / KPL loads).
 // D[i][j]: lane -> column l % 16; rows 4 (l / 16) + r for the FP32
 // accumulating shapes and l / 16 + 4 r for FP64 (register r = 0..3).
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int kMT = 12;  // column tiles of 16 (up to 192 columns)
+constexpr int kPMaxCols = 192;  // 12 column tiles
 
 template <int PREC>
-struct MfmaCfg;
+struct PCfg;
 template <>
-struct MfmaCfg<0> {
+struct PCfg<0> {
+  using el = double;
   using acc_t = d4_t;
   using part_t = double;
-  static constexpr int KC = 32;   // k per staged chunk
-  static constexpr int KS = 4;    // k per MFMA
+  static constexpr int KPL = 8, TPL = 2, KC = 32, PAD = 2;
 };
 template <>
-struct MfmaCfg<1> {
+struct PCfg<1> {
+  using el = float;
   using acc_t = f4_t;
   using part_t = float;
-  static constexpr int KC = 32;
-  static constexpr int KS = 4;
+  static constexpr int KPL = 16, TPL = 4, KC = 64, PAD = 4;
 };
 template <>
-struct MfmaCfg<2> {
+struct PCfg<2> {
+  using el = uint16_t;
   using acc_t = f4_t;
   using part_t = float;
-  static constexpr int KC = 64;
-  static constexpr int KS = 32;
+  static constexpr int KPL = 32, TPL = 1, KC = 128, PAD = 8;
 };
 
 template <int PREC>
+__device__ inline void mfma_step(const uint4& av, const uint4& bv, typename PCfg<PREC>::acc_t& acc) {
+  if constexpr (PREC == 0) {
+    const double2 a2 = __builtin_bit_cast(double2, av), b2 = __builtin_bit_cast(double2, bv);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.x, b2.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2.y, b2.y, acc, 0, 0, 0);
+  } else if constexpr (PREC == 1) {
+    const f4_t a4 = __builtin_bit_cast(f4_t, av), b4 = __builtin_bit_cast(f4_t, bv);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[0], b4[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[1], b4[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[2], b4[2], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[3], b4[3], acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, av),
+                                                  __builtin_bit_cast(bf8_t, bv), acc, 0, 0, 0);
+  }
+}
+
+// zero the entries of a 16-byte fragment whose k (first = k0) is at or past kend
+template <int PREC>
+__device__ inline uint4 mask_k(uint4 v, int k0, int kend) {
+  using el = typename PCfg<PREC>::el;
+  constexpr int E = 16 / (int)sizeof(el);
+  el x[E];
+  __builtin_memcpy(x, &v, 16);
+#pragma unroll
+  for (int q = 0; q < E; ++q)
+    if (k0 + q >= kend) x[q] = (el)0;
+  __builtin_memcpy(&v, x, 16);
+  return v;
+}
+
+template <int PREC, int NCT>
 __global__ __launch_bounds__(256) void k_product_mfma(const void* __restrict__ A, int lda, int n,
                                                       const double* __restrict__ S, int lds,
-                                                      void* __restrict__ part, int ldp,
-                                                      size_t part_stride, const int* cols_dev,
-                                                      int cols_host, int kslice,
-                                                      const int* stop) {
+                                                      int cols_alloc, void* __restrict__ part,
+                                                      int ldp, size_t part_stride,
+                                                      const int* cols_dev, int cols_host,
+                                                      int kslice, const int* stop) {
   if (stop && *stop) return;
-  using C = MfmaCfg<PREC>;
+  using C = PCfg<PREC>;
+  using el = typename C::el;
   using acc_t = typename C::acc_t;
   using part_t = typename C::part_t;
-  constexpr int KC = C::KC;
-  const int cols = cols_dev ? *cols_dev : cols_host;
-  const int nct = (cols + 15) / 16;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int KC = C::KC, LDK = KC + C::PAD, KPL = C::KPL, NL = KC / KPL;
+  constexpr int EPL = 16 / (int)sizeof(el);  // elements per 16-byte fragment
+  const int cols = min(cols_dev ? *cols_dev : cols_host, NCT * 16);
+  const int colsr = (cols + 15) / 16 * 16;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, g = lane >> 4;
   const int row0 = blockIdx.x * 64 + wv * 16;
   const int kbeg = blockIdx.y * kslice, kend = min(n, kbeg + kslice);
-  // S chunk in LDS: [column j][k], k contiguous, padded leading dim
-  constexpr int LDK = (PREC == 2) ? KC + 8 : KC + 1;
-  __shared__ __align__(16) unsigned char sraw[kMT * 16 * LDK * (PREC == 0 ? 8 : (PREC == 1 ? 4 : 2))];
-  acc_t acc[kMT];
+  __shared__ __align__(16) el sB[NCT * 16 * LDK];
+  acc_t acc[NCT];
 #pragma unroll
-  for (int t = 0; t < kMT; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  const int li = lane & 15, lk = lane >> 4;
-  for (int k0 = kbeg; k0 < kend; k0 += KC) {
-    // stage S[k0 : k0 + KC, 0 : 16 nct]
-    for (int e = threadIdx.x; e < KC * 16 * nct; e += 256) {
-      const int kk = e % KC, j = e / KC;
-      const int k = k0 + kk;
-      const double v = (k < kend && j < cols) ? S[k + (size_t)j * lds] : 0.0;
-      if constexpr (PREC == 0) ((double*)sraw)[j * LDK + kk] = v;
-      else if constexpr (PREC == 1) ((float*)sraw)[j * LDK + kk] = (float)v;
-      else ((uint16_t*)sraw)[j * LDK + kk] = f32_to_bf16_rne((float)v);
+  for (int t = 0; t < NCT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  // this lane's row of A, read as a column; loads past the slice stay inside
+  // the row (clamped) and are never used
+  const el* arow = (const el*)A + (size_t)(row0 + li) * lda + EPL * g;
+  const int kmax = lda - KPL;
+  uint4 ring[NL];
+#pragma unroll
+  for (int s = 0; s < NL; ++s) ring[s] = *(const uint4*)(arow + min(kbeg + s * KPL, kmax));
+  for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
+    // stage S[kc0 : kc0 + KC, 0 : colsr] in the product precision (rows past
+    // kend are zero), two FP64 values per load
+    for (int e = tid; e < colsr * (KC / 2); e += 256) {
+      const int j = e / (KC / 2), kk = 2 * (e % (KC / 2));
+      const int k = kc0 + kk;
+      const double2 v = *(const double2*)(S + min(k, lda - 2) + (size_t)min(j, cols_alloc - 1) * lds);
+      const double v0 = (k < kend) ? v.x : 0.0, v1 = (k + 1 < kend) ? v.y : 0.0;
+      el* dst = sB + j * LDK + kk;
+      if constexpr (PREC == 0) {
+        dst[0] = v0;
+        dst[1] = v1;
+      } else if constexpr (PREC == 1) {
+        *(f2_t*)dst = f2_t{(float)v0, (float)v1};
+      } else {
+        dst[0] = f32_to_bf16_rne((float)v0);
+        dst[1] = f32_to_bf16_rne((float)v1);
+      }
     }
     __syncthreads();
-    const int ksteps = (min(KC, kend - k0) + C::KS - 1) / C::KS;
-    for (int ks = 0; ks < ksteps; ++ks) {
-      const int kb = k0 + ks * C::KS;
-      if constexpr (PREC == 0) {
-        const int k = kb + lk;
-        const double av = (k < kend) ? ((const double*)A)[(row0 + li) + (size_t)k * lda] : 0.0;
-        const double* sb = (const double*)sraw;
+    const bool tail = kc0 + KC > kend;  // uniform
 #pragma unroll
-        for (int t = 0; t < kMT; ++t)
-          if (t < nct) {
-            const double bv = sb[(t * 16 + li) * LDK + ks * 4 + lk];
-            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
-          }
-      } else if constexpr (PREC == 1) {
-        const int k = kb + lk;
-        const float av = (k < kend) ? ((const float*)A)[(row0 + li) + (size_t)k * lda] : 0.0f;
-        const float* sb = (const float*)sraw;
+    for (int s = 0; s < NL; ++s) {
+      const int kb = kc0 + s * KPL;
+      uint4 av = ring[s];
+      ring[s] = *(const uint4*)(arow + min(kb + KC, kmax));  // next chunk, same step
+      if (tail) av = mask_k<PREC>(av, kb + EPL * g, kend);
+      const el* bcol = sB + li * LDK + s * KPL + EPL * g;
 #pragma unroll
-        for (int t = 0; t < kMT; ++t)
-          if (t < nct) {
-            const float bv = sb[(t * 16 + li) * LDK + ks * 4 + lk];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
-          }
-      } else {
-        // A[row0 + li][kb + 8 lk .. +7] read as A[k][i] (symmetric), 16 bytes
-        const int kq = kb + 8 * lk;
-        bf8_t av;
-        if (kq + 8 <= kend) {
-          av = *(const bf8_t*)((const uint16_t*)A + kq + (size_t)(row0 + li) * lda);
-        } else {
-          uint16_t tmp[8];
-          for (int q = 0; q < 8; ++q)
-            tmp[q] = (kq + q < kend) ? ((const uint16_t*)A)[kq + q + (size_t)(row0 + li) * lda] : 0;
-          av = __builtin_bit_cast(bf8_t, *(const uint4*)tmp);
-        }
-        const uint16_t* sb = (const uint16_t*)sraw;
-#pragma unroll
-        for (int t = 0; t < kMT; ++t)
-          if (t < nct) {
-            const bf8_t bv = *(const bf8_t*)(sb + (t * 16 + li) * LDK + ks * 32 + 8 * lk);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
-          }
-      }
+      for (int t = 0; t < NCT; ++t)
+        if (16 * t < colsr) mfma_step<PREC>(av, *(const uint4*)(bcol + 16 * t * LDK), acc[t]);
     }
     __syncthreads();
   }
   // partial tile -> part[slice]
   part_t* out = (part_t*)part + (size_t)blockIdx.y * part_stride;
 #pragma unroll
-  for (int t = 0; t < kMT; ++t)
-    if (t < nct) {
+  for (int t = 0; t < NCT; ++t)
+    if (16 * t < cols) {
       const int j = t * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // FP64 16x16x4: register r of lane l holds row l/16 + 4r; the FP32
-        // accumulating shapes hold row 4(l/16) + r (checked on gfx950)
-        const int i = (PREC == 0) ? row0 + lk + 4 * r : row0 + 4 * lk + r;
+        const int i = (PREC == 0) ? row0 + g + 4 * r : row0 + 4 * g + r;
         if (j < cols) out[i + (size_t)j * ldp] = (part_t)acc[t][r];
       }
     }
@@ -243,27 +259,39 @@ hipError_t launch_product(const ProductArgs& a, hipStream_t st) {
     const char* e = getenv("PSDP_PRODUCT_REF");
     g_force_ref = (e && atoi(e) == 1) ? 1 : 0;
   }
-  const bool mfma_ok = a.partial && a.cols_max <= kMT * 16 && a.lda % 64 == 0 && !g_force_ref;
+  const bool mfma_ok = a.partial && a.cols_max <= kPMaxCols && a.lda % 8 == 0 &&
+                       a.lds % 2 == 0 && a.lds >= a.lda && !g_force_ref;
   if (mfma_ok) {
     const int rt = (a.n + 63) / 64;
-    // K slices: enough workgroups to cover the chip, at least 256 k each
+    // K slices: about two workgroups per compute unit, slices a multiple of
+    // the staging chunk (128 covers every precision)
     int sk = std::max(1, std::min((512 + rt - 1) / rt, a.n / 256));
     sk = std::min(sk, a.max_slices);
-    const int kslice = ((a.n + sk - 1) / sk + 63) / 64 * 64;
+    const int kslice = ((a.n + sk - 1) / sk + 127) / 128 * 128;
     sk = (a.n + kslice - 1) / kslice;
     const size_t pstride = (size_t)a.lda * a.cols_max;
     const size_t elem = a.prec == 0 ? 8 : 4;
     if ((size_t)sk * pstride * elem > a.partial_bytes) return hipErrorInvalidValue;
     dim3 grid(rt, sk);
-    if (a.prec == 0)
-      hipLaunchKernelGGL(k_product_mfma<0>, grid, dim3(256), 0, st, a.A, a.lda, a.n, a.S, a.lds,
-                         (void*)a.partial, a.lda, pstride, a.cols_dev, a.cols_max, kslice, a.stop);
-    else if (a.prec == 1)
-      hipLaunchKernelGGL(k_product_mfma<1>, grid, dim3(256), 0, st, a.A, a.lda, a.n, a.S, a.lds,
-                         (void*)a.partial, a.lda, pstride, a.cols_dev, a.cols_max, kslice, a.stop);
-    else
-      hipLaunchKernelGGL(k_product_mfma<2>, grid, dim3(256), 0, st, a.A, a.lda, a.n, a.S, a.lds,
-                         (void*)a.partial, a.lda, pstride, a.cols_dev, a.cols_max, kslice, a.stop);
+    const int nct = (a.cols_max + 15) / 16;
+#define PSDP_LAUNCH_PRODUCT(P, T)                                                            \
+  hipLaunchKernelGGL((k_product_mfma<P, T>), grid, dim3(256), 0, st, a.A, a.lda, a.n, a.S, a.lds, \
+                     a.cols_max, (void*)a.partial, a.lda, pstride, a.cols_dev, a.cols_max,   \
+                     kslice, a.stop)
+#define PSDP_LAUNCH_PREC(P)                        \
+  if (nct <= 3) PSDP_LAUNCH_PRODUCT(P, 3);         \
+  else if (nct <= 6) PSDP_LAUNCH_PRODUCT(P, 6);    \
+  else if (nct <= 9) PSDP_LAUNCH_PRODUCT(P, 9);    \
+  else PSDP_LAUNCH_PRODUCT(P, 12);
+    if (a.prec == 0) {
+      PSDP_LAUNCH_PREC(0)
+    } else if (a.prec == 1) {
+      PSDP_LAUNCH_PREC(1)
+    } else {
+      PSDP_LAUNCH_PREC(2)
+    }
+#undef PSDP_LAUNCH_PREC
+#undef PSDP_LAUNCH_PRODUCT
     const size_t total = (size_t)a.n * a.cols_max;
     dim3 rg((unsigned)((total + 255) / 256));
     if (a.prec == 0)

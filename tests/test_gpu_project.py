@@ -161,3 +161,29 @@ def test_rr_methods_agree(n, npos, m_cap):
     os.environ.pop("PSDP_RR_METHOD", None)
     assert np.abs(outs[0] - outs[1]).max() <= 1e-8
     assert np.abs(outs[0] - outs[2]).max() <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_precision_ladder_warm(proj, prec):
+    """Warm-started projection with low-precision products (paper §6.2
+    mixed precision): the ladder (BF16 -> FP32 -> FP64) ends in FP64 at the
+    1e-6 bar, and starting from BF16 costs at most a few more iterations than
+    starting from FP32 (the FP32 copy of A is rebuilt at the switch)."""
+    from gpu_util import to_dev
+    from workloads import large_cone_sequence
+    seq = large_cone_sequence(n=640, n_pos=12, steps=2, cumulative=False)
+    X0, lam, basis = next(seq)
+    X1 = next(seq)
+    lam0 = np.sort(lam)[::-1]
+    tol = 1e-7 * float(np.linalg.norm(np.maximum(lam0, 0))) / np.sqrt(32)
+    r0 = proj.project(to_dev(X0), m_cap=20, side="pos", prec="fp64", tol=tol, pos_hint=12)
+    assert r0.status == 0
+    iters = {}
+    for p in ("fp32", prec):
+        res = proj.project(to_dev(X1), V=r0.V[:, :r0.info["m_out"]].clone(), m_cap=20, side="pos",
+                           prec=p, tol=tol, pos_hint=12)
+        assert res.status == 0 and res.info["prec_final"] == 0, res.info
+        _check(res, X1)
+        iters[p] = res.info["iters"]
+    print("iters", iters)
+    assert iters[prec] <= iters["fp32"] + 10
