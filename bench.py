@@ -50,7 +50,7 @@ import numpy as np  # noqa: E402
 PEAKS = {  # MI355X published dense peaks
     "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
 }
-FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rebuild", "ingest", "batched", "fulleig"]
+FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rrback", "rebuild", "ingest", "batched", "fulleig"]
 
 # HBM bytes per launch measured with rocprofv3 PMC counters (FETCH_SIZE x 2.0
 # + WRITE_SIZE x 1.0, factors from a plain 256 MiB copy), keyed by workload
@@ -59,10 +59,10 @@ FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rebuild", "ingest", "batch
 # kernel and is reported as null.
 TRAFFIC = {
     ("n1000_warm_seq", "rr"): {
-        "bytes": 68.0e3,
-        "files": ["paper_1912_02767_amd/csrc/rr_body.h", "paper_1912_02767_amd/csrc/k_rr_tri.hip",
-                  "paper_1912_02767_amd/csrc/common.h"],
-        "sha256": "8510b3652702efc8a0cc92154c30103558df3feb9a38d0e014f313769e505061",
+        "bytes": 107.4e3,
+        "files": ["paper_1912_02767_amd/csrc/rr_fast.h", "paper_1912_02767_amd/csrc/rr_body.h",
+                  "paper_1912_02767_amd/csrc/k_rr_tri.hip", "paper_1912_02767_amd/csrc/common.h"],
+        "sha256": "3734ba5be3ff8f2b025dacaf165c22bc5731d6c0c928463324c43100677a4490",
         "profile": "profiles/hbm_traffic_n1000_warm_seq.txt",
     },
 }

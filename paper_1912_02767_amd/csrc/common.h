@@ -229,6 +229,8 @@ hipError_t launch_decide_chol(const DecideArgs& a, int N_host, hipStream_t st);
 hipError_t launch_rr(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
 hipError_t launch_rr_tri(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
 hipError_t launch_rr_fast(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
+// back-transformation of the Ritz vectors left by launch_rr_fast (C in place)
+hipError_t launch_rr_back(const RRArgs& a, int Np_host, int mk_host, hipStream_t st);
 hipError_t rr_tri_init();
 hipError_t small_kernels_init();
 

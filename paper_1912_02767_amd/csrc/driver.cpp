@@ -333,8 +333,17 @@ struct Solver {
         p.bytes = 16.0 * c * c;
         ++chol_i;
       } else if (p.family == "rr") {
-        p.flops = 9.0 * N2 * N2 * N2;     // dense symmetric eigendecomposition
-        p.bytes = 8.0 * N2 * N2 + 8.0 * N2 * mk;
+        if (h->rr_method == 0) {
+          // tridiagonalization (4/3 N^3), eigenvalues and vectors of T
+          p.flops = 4.0 / 3.0 * N2 * N2 * N2;
+          p.bytes = 8.0 * N2 * N2 + 4.0 * N2 * N2 + 8.0 * N2 * mk;
+        } else {
+          p.flops = 9.0 * N2 * N2 * N2;  // dense symmetric eigendecomposition
+          p.bytes = 8.0 * N2 * N2 + 8.0 * N2 * mk;
+        }
+      } else if (p.family == "rrback") {
+        p.flops = 4.0 * N2 * N2 * mk;  // N - 2 reflectors applied to mk columns
+        p.bytes = 4.0 * N2 * N2 + 16.0 * N2 * mk;
       } else if (p.family == "tsmm") {
         if (tsmm_i == 0) { p.flops = 2 * nn * N * N1; p.bytes = 8 * nn * (N + N1); }
         else if (tsmm_i == 1) { p.flops = 2 * nn * N1 * N2; p.bytes = 8 * nn * (N1 + N2); }
@@ -446,6 +455,10 @@ struct Solver {
       } else {
         HIP_TRY(launch_rr(ra, Nmax, std::min(mtarget, Nmax), s));
       }
+    }
+    if (h->rr_method == 0) {
+      ProfScope ps(h, "rrback");
+      HIP_TRY(launch_rr_back(ra, Nmax, std::min(mtarget, Nmax), s));
     }
     // ---- update X, AX, P, R
     int want_p = (mode == kModeFull || mode == kModeXR) ? 1 : 0;

@@ -76,11 +76,17 @@ hipError_t launch_rr_fast(const RRArgs& a_in, int Np_host, int mk_host, hipStrea
   const size_t doubles =
       rr_fast_lds_doubles(Np_host, std::min(mk_host, Np_host), kFastThreads, 5, 9);
   if (doubles * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
-  const size_t back = rr_back_lds_doubles(Np_host);
-  if (back * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
+  if (rr_back_lds_doubles(Np_host) * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
   a.lds_cap = doubles;
   hipLaunchKernelGGL(k_rr_fast, dim3(1), dim3(kFastThreads), doubles * 8, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_back(const RRArgs& a, int Np_host, int mk_host, hipStream_t st) {
+  const size_t back = rr_back_lds_doubles(Np_host);
+  if (Np_host > 144 || back * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
   const int mk = std::min(mk_host, Np_host);
+  if (mk <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rr_back, dim3((mk + kBackCols - 1) / kBackCols), dim3(kBackThreads),
                      back * 8, st, a);
   return hipGetLastError();

@@ -212,9 +212,16 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
   int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= rows * cols) return;
   int i = e % rows, j = e / rows;
-  double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * part_stride + i + (size_t)j * ldp];
-  out[i + (size_t)j * ldo] = s;
+  // eight loads in flight; the partial sums are combined in a fixed order
+  const double* p = part + i + (size_t)j * ldp;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int b = 0;
+  for (; b + 8 <= nblk; b += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += p[(size_t)(b + u) * part_stride];
+  }
+  for (int u = 0; b < nblk; ++b, ++u) s[u] += p[(size_t)b * part_stride];
+  out[i + (size_t)j * ldo] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // --------------------------------------------------------------- tsmm ---
