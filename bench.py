@@ -62,7 +62,7 @@ TRAFFIC = {
         "bytes": 107.4e3,
         "files": ["paper_1912_02767_amd/csrc/rr_fast.h", "paper_1912_02767_amd/csrc/rr_body.h",
                   "paper_1912_02767_amd/csrc/k_rr_tri.hip", "paper_1912_02767_amd/csrc/common.h"],
-        "sha256": "3734ba5be3ff8f2b025dacaf165c22bc5731d6c0c928463324c43100677a4490",
+        "sha256": "dbcfb52bbebd208c06056d53cea371c2ac3451211c1079f0abd28b631118db0e",
         "profile": "profiles/hbm_traffic_n1000_warm_seq.txt",
     },
 }

@@ -1,23 +1,21 @@
-// Device body of the one-workgroup Rayleigh-Ritz step, second design:
-//   1. Householder tridiagonalization of the N x N projected matrix held as
-//      a packed lower triangle in column-major order (column j starts at
-//      cb(j) + j with cb(j) = j N - j (j + 1) / 2; element (i, j), i >= j, at
-//      cb(j) + i), one thread per column: thread j forms its entry of the
-//      symmetric product p = A v from its column (rows at and below j) and
-//      its row (columns left of j, read along those columns), updates its
-//      own column in the rank-2 step, and the owner of the next pivot column
-//      forms the next reflector's norm while it updates that column.  Two
-//      barriers per step; reflectors are scaled in place once at the end.
-//   2. multisection with Sturm counts for the mk largest eigenvalues,
-//      bracketed to a few ulps of ||T||;
-//   3. eigenvectors by the twisted factorization of T - sigma I (top-down
+// Device bodies of the Rayleigh-Ritz step on the N x N projected matrix
+// (N <= 144 in one workgroup):
+//   1. Householder tridiagonalization with the matrix in registers on an
+//      RG x 16 thread grid (tridiag_reg), two barriers per column; the
+//      reflectors, unit entry included, in a packed column-major lower
+//      triangle (column j starts at cb(j) + j, cb(j) = j N - j (j + 1) / 2);
+//   2. multisection with Sturm counts for the mk largest eigenvalues: one
+//      shared round over the Gershgorin interval, then per-eigenvalue shifts,
+//      to a few ulps of ||T||;
+//   3. eigenvectors of T by the twisted factorization of T - sigma I (top-down
 //      and bottom-up pivots, twist at the smallest |gamma|), one thread per
 //      vector; modified Gram-Schmidt inside clusters (with inverse iteration
 //      from a fixed start vector when a vector collapses onto its
 //      predecessors, as for exactly repeated eigenvalues); Rayleigh quotients;
-//   4. back-transformation by blocks of 16 reflectors in compact WY form,
-//      Y <- (I - V T V^T) Y, last block first, spread over the workgroup.
-// Included by the single-cone kernel and the batched persistent kernel;
+//   4. back-transformation by blocks of 16 reflectors in compact WY form
+//      (wy_back), in the same workgroup (batched engine) or in a separate
+//      kernel over column tiles of the vectors (single cone).
+// Included by the single-cone kernels and the batched persistent kernel;
 // needs blockDim.x >= N.
 #pragma once
 #include "rr_body.h"
