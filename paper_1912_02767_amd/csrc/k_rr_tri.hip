@@ -17,6 +17,7 @@ __global__ __launch_bounds__(kTriThreads) void k_rr_tri(RRArgs a) {
 }
 
 constexpr int kFastThreads = 512;
+constexpr int kFastThreadsS = 256;  // trial bases up to 80: 16 x 16 grid, 5 x 5 per thread
 
 __global__ __launch_bounds__(kFastThreads) void k_rr_fast(RRArgs a) {
   extern __shared__ double lds[];
@@ -27,6 +28,17 @@ __global__ __launch_bounds__(kFastThreads) void k_rr_fast(RRArgs a) {
   RRShared sh{s_lo, s_hi, &s_npos, &s_tnorm, &s_pivmin};
   // 32 x 16 thread grid, N <= 144; the reflectors go to a.scratch
   rr_fast_body<5, 9, kFastThreads, true>(a, lds, sh);
+}
+
+// the same for N <= 80: fewer waves, shorter chains per step
+__global__ __launch_bounds__(kFastThreadsS) void k_rr_fast_s(RRArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double s_lo[kMaxM], s_hi[kMaxM];
+  __shared__ int s_npos;
+  __shared__ double s_tnorm, s_pivmin;
+  if (a.st->stop) return;
+  RRShared sh{s_lo, s_hi, &s_npos, &s_tnorm, &s_pivmin};
+  rr_fast_body<5, 5, kFastThreadsS, true>(a, lds, sh);
 }
 
 // Back-transformation of the Ritz vectors of the tridiagonal matrix (C, in
@@ -40,6 +52,7 @@ __host__ __device__ inline size_t rr_back_lds_doubles(int N) {
   return n * (n + 1) / 2 + n + ldy * kBackCols + kWYBlock * kWYBlock + kWYLd * kBackCols;
 }
 
+template <int NBC>
 __global__ __launch_bounds__(kBackThreads) void k_rr_back(RRArgs a) {
   extern __shared__ double lds[];
   State* st = a.st;
@@ -61,7 +74,7 @@ __global__ __launch_bounds__(kBackThreads) void k_rr_back(RRArgs a) {
     Y[x] = (i < N && j < nc) ? a.C[i + (size_t)(j0 + j) * a.ldc] : 0.0;
   }
   __syncthreads();
-  wy_back<kBackThreads, 9, 2>(N, P, tau, Y, ldy, nc, Tb, Wb, blockIdx.x == 0 ? st : nullptr);
+  wy_back<kBackThreads, NBC, 2>(N, P, tau, Y, ldy, nc, Tb, Wb, blockIdx.x == 0 ? st : nullptr);
   for (int x = threadIdx.x; x < N * nc; x += kBackThreads) {
     const int i = x % N, j = x / N;
     a.C[i + (size_t)(j0 + j) * a.ldc] = Y[i + (size_t)j * ldy];
@@ -73,12 +86,17 @@ static int g_tri_lds_limit = 56 * 1024;
 hipError_t launch_rr_fast(const RRArgs& a_in, int Np_host, int mk_host, hipStream_t st) {
   RRArgs a = a_in;
   if (Np_host > 144 || std::min(mk_host, Np_host) > kMaxM) return hipErrorInvalidValue;
+  const bool small = Np_host <= 80;
   const size_t doubles =
-      rr_fast_lds_doubles(Np_host, std::min(mk_host, Np_host), kFastThreads, 5, 9);
+      small ? rr_fast_lds_doubles(Np_host, std::min(mk_host, Np_host), kFastThreadsS, 5, 5)
+            : rr_fast_lds_doubles(Np_host, std::min(mk_host, Np_host), kFastThreads, 5, 9);
   if (doubles * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
   if (rr_back_lds_doubles(Np_host) * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
   a.lds_cap = doubles;
-  hipLaunchKernelGGL(k_rr_fast, dim3(1), dim3(kFastThreads), doubles * 8, st, a);
+  if (small)
+    hipLaunchKernelGGL(k_rr_fast_s, dim3(1), dim3(kFastThreadsS), doubles * 8, st, a);
+  else
+    hipLaunchKernelGGL(k_rr_fast, dim3(1), dim3(kFastThreads), doubles * 8, st, a);
   return hipGetLastError();
 }
 
@@ -87,8 +105,12 @@ hipError_t launch_rr_back(const RRArgs& a, int Np_host, int mk_host, hipStream_t
   if (Np_host > 144 || back * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
   const int mk = std::min(mk_host, Np_host);
   if (mk <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rr_back, dim3((mk + kBackCols - 1) / kBackCols), dim3(kBackThreads),
-                     back * 8, st, a);
+  if (Np_host <= 80)
+    hipLaunchKernelGGL(k_rr_back<5>, dim3((mk + kBackCols - 1) / kBackCols), dim3(kBackThreads),
+                       back * 8, st, a);
+  else
+    hipLaunchKernelGGL(k_rr_back<9>, dim3((mk + kBackCols - 1) / kBackCols), dim3(kBackThreads),
+                       back * 8, st, a);
   return hipGetLastError();
 }
 
@@ -124,8 +146,12 @@ hipError_t rr_tri_init() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void*)k_rr_fast, hipFuncAttributeMaxDynamicSharedMemorySize,
                               dyn);
-    (void)hipFuncSetAttribute((const void*)k_rr_back, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr_fast_s,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr_back<5>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void*)k_rr_back<9>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
   }
   (void)hipGetLastError();
   return hipSuccess;

@@ -262,17 +262,29 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
     double xc[NBC];
 #pragma unroll
     for (int q = 0; q < NBC; ++q) xc[q] = col[c + 16 * q];
-    double xs = 0.0;
+    // short dependent chains: FP64 latency, not issue, bounds this kernel
+    double xs3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < NBC; ++q) xs = fma(xc[q], xc[q], xs);
-    xs = row16_sum(xs);  // |x|^2, x_{k+1} included
-    // reflector scalars (dlarfg convention), off the critical path of (b)
+    for (int q = 0; q < NBC; ++q) xs3[q % 3] = fma(xc[q], xc[q], xs3[q % 3]);
+    double xs = row16_sum((xs3[0] + xs3[1]) + xs3[2]);  // |x|^2, x_{k+1} included
+    // reflector scalars (dlarfg convention), off the critical path of (b):
+    // r = 1 / sqrt(|x|^2) by reciprocal square root and two Newton steps,
+    // beta = -sign(alpha) |x|, t = (beta - alpha) / beta = 1 + |alpha| r,
+    // scale = 1 / (alpha - beta) = sign(alpha) / (|alpha| + |x|)
     const double alpha = col[k + 1];
     double t = 0.0, beta = alpha, scale = 0.0;
     if (xs - alpha * alpha > 0.0) {
-      beta = -copysign(sqrt(xs), alpha);
-      t = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+      double r = __builtin_amdgcn_rsq(xs);
+      r = r * fma(-0.5 * xs * r, r, 1.5);
+      r = r * fma(-0.5 * xs * r, r, 1.5);
+      const double nx = xs * r, aa = fabs(alpha);
+      beta = -copysign(nx, alpha);
+      t = fma(aa, r, 1.0);
+      const double den = aa + nx;
+      double q = __builtin_amdgcn_rcp(den);
+      q = fma(fma(-den, q, 1.0), q, q);
+      q = fma(fma(-den, q, 1.0), q, q);
+      scale = copysign(q, alpha);
     }
     double xax = 0.0;
     if (live) {
@@ -281,10 +293,10 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
       for (int q = 0; q < NBR; ++q) xr[q] = col[row0 + q];
 #pragma unroll
       for (int li = 0; li < NBR; ++li) {
-        double s0 = 0.0;
+        double s3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int lj = 0; lj < NBC; ++lj) s0 = fma(A[li][lj], xc[lj], s0);
-        s0 = row16_sum(s0);  // (A x) for row row0 + li
+        for (int lj = 0; lj < NBC; ++lj) s3[lj % 3] = fma(A[li][lj], xc[lj], s3[lj % 3]);
+        const double s0 = row16_sum((s3[0] + s3[1]) + s3[2]);  // (A x) for row row0 + li
         if (c == 0) pf[row0 + li] = s0;
         xax = fma(xr[li], s0, xax);
       }
@@ -316,9 +328,14 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
     if (tid == 0) { const long long tn = wall_clock64(); tacc0 += tn - tl; tl = tn; }
     // ---- (b) v and w, the reflector kept in P, the next column
     const double g = 1.0 - scale * alpha;
-    double xaxs = 0.0;
+    double rw[nw];
 #pragma unroll
-    for (int q = 0; q < nw; ++q) xaxs += red[q];
+    for (int q = 0; q < nw; ++q) rw[q] = red[q];
+#pragma unroll
+    for (int h = 1; h < nw; h *= 2)  // pairwise: log2(nw) dependent adds
+#pragma unroll
+      for (int q = 0; q + h < nw; q += 2 * h) rw[q] += rw[q + h];
+    const double xaxs = rw[0];
     const double ax1 = pf[k + 1], a11 = cpre[k + 1];
     // v^T A v = scale^2 x^T A x + 2 scale g (A x)_{k+1} + g^2 A(k+1, k+1)
     const double vav = scale * scale * xaxs + 2.0 * scale * g * ax1 + g * g * a11;

@@ -136,11 +136,13 @@ def test_trivial_inputs(proj):
     assert abs(to_host(res.Pi)[0, 0] - 2.5) <= 1e-12
 
 
-@pytest.mark.parametrize("n,npos,m_cap", [(120, 10, 24), (400, 40, 48)])
+@pytest.mark.parametrize("n,npos,m_cap", [(120, 10, 24), (300, 20, 26), (300, 22, 27), (400, 40, 48)])
 def test_rr_methods_agree(n, npos, m_cap):
     """The Jacobi Rayleigh-Ritz (kept as a cross-check), the first
     tridiagonal design and the column-parallel one give the same projection
-    to the parity bar (n = 400 with block 48 reaches trial bases of 144)."""
+    to the parity bar (block 26 keeps trial bases within the 256-thread
+    variant's 80, block 27 crosses to the 512-thread one; n = 400 with block
+    48 reaches trial bases of 144)."""
     import os
     import torch
     import paper_1912_02767_amd as psdp
