@@ -69,6 +69,7 @@ __device__ inline int pup(int i, int j) {
 // + row buffer (N) + scale (N) + misc.
 // Body shared by the single-cone kernel and the batched persistent kernel.
 __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const CholShared& sh) {
+  lds = lds_base();  // callers pass the dynamic LDS base; keep its address space
   double* red = sh.red;
   int* s_list = sh.list;   // logical trial column -> candidate index in G
   int* s_kind = sh.kind;

@@ -86,6 +86,15 @@ struct State {
   int keep_col[kMaxN];   // logical columns kept after dropping (Np entries)
 };
 
+// Base of the launch's dynamic LDS.  The device bodies take their LDS
+// pointer from here rather than from a parameter: a pointer that passed
+// through a struct in memory loses its address space, and every access
+// through it becomes a flat access.
+__device__ inline double* lds_base() {
+  extern __shared__ double psdp_dyn_lds[];
+  return psdp_dyn_lds;
+}
+
 // Bit-cast helpers for BF16 (round to nearest even from float).
 __host__ __device__ inline uint16_t f32_to_bf16_rne(float f) {
   uint32_t u;

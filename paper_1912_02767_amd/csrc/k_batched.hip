@@ -33,6 +33,7 @@ struct ColsT {
 template <typename TA, typename TC, bool AT, bool BT>
 __device__ void wg_gemm(int M, int N, int K, ColsT<TA> A, const double* B, int ldb, double* C,
                         int ldc, void* smem, int kc) {
+  smem = lds_base();            // callers pass the dynamic LDS base; keep its address space
   TC* sA = (TC*)smem;           // kc x 65
   TC* sB = sA + kc * 65;        // kc x 65
   const int tid = threadIdx.x, nt = blockDim.x;

@@ -142,11 +142,16 @@ __global__ __launch_bounds__(256) void k_gram_partial(ColMap bptr, ColMap yptr, 
   __shared__ double sy[kGR][kGT + 1];
   __shared__ const double* pb[kGT];
   __shared__ const double* py[kGT];
+  __shared__ int okb[kGT], oky[kGT];
   if (threadIdx.x < kGT) {
-    int c = threadIdx.x;
-    pb[c] = (ti + c < nb) ? bptr.col(ti + c) : nullptr;
-    if (sym) py[c] = (tj + c < nb) ? bptr.col(tj + c) : nullptr;
-    else py[c] = (tj + c < ny) ? yptr.col(tj + c) : nullptr;
+    // inactive columns alias column 0 (always valid) and are masked to zero
+    const int c = threadIdx.x;
+    const bool vb = ti + c < nb;
+    const bool vy = sym ? (tj + c < nb) : (tj + c < ny);
+    pb[c] = bptr.col(vb ? ti + c : 0);
+    py[c] = sym ? bptr.col(vy ? tj + c : 0) : yptr.col(vy ? tj + c : 0);
+    okb[c] = vb;
+    oky[c] = vy;
   }
   __syncthreads();
   const int r0 = blockIdx.x * kGramRows;
@@ -157,20 +162,31 @@ __global__ __launch_bounds__(256) void k_gram_partial(ColMap bptr, ColMap yptr, 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+  // kGR rows x 64 columns of B and Y per stage, eight values each per thread;
+  // the next stage's loads are in flight while this stage is multiplied
+  constexpr int PER = kGR * kGT / 256;
+  double cb[PER], cy[PER];
+  auto load_stage = [&](int rr) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int r = e % kGR, c = e / kGR;
+      const int row = rr + r, rowc = min(row, r1 - 1);
+      const double vb = pb[c][rowc], vy = py[c][rowc];
+      cb[u] = (row < r1 && okb[c]) ? vb : 0.0;
+      cy[u] = (row < r1 && oky[c]) ? vy : 0.0;
+    }
+  };
+  load_stage(r0);
   for (int rr = r0; rr < r1; rr += kGR) {
-    // stage kGR rows x 64 columns of B (cols ti..) and Y (cols tj..)
-    for (int e = threadIdx.x; e < kGR * kGT; e += 256) {
-      int r = e % kGR, c = e / kGR;
-      int row = rr + r;
-      double vb = 0.0, vy = 0.0;
-      if (row < r1) {
-        if (pb[c]) vb = pb[c][row];
-        if (py[c]) vy = py[c][row];
-      }
-      sb[r][c] = vb;
-      sy[r][c] = vy;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      sb[e % kGR][e / kGR] = cb[u];
+      sy[e % kGR][e / kGR] = cy[u];
     }
     __syncthreads();
+    if (rr + kGR < r1) load_stage(rr + kGR);
 #pragma unroll 4
     for (int r = 0; r < kGR; ++r) {
       double bv[4], yv[4];
@@ -241,18 +257,42 @@ __device__ inline void tsmm_tile(const ColMap& src, int kk, int q,
   const int r = threadIdx.x % kTR;
   const int cg = threadIdx.x / kTR;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < kk; k0 += kTK) {
-    for (int e = threadIdx.x; e < kTK * kTR; e += 256) {
-      int rr = e % kTR, kc = e / kTR;
-      int row = row0 + rr, k = k0 + kc;
-      sS[kc][rr] = (row < n && k < kk) ? src.col(k)[row] : 0.0;
+  // per chunk: 32 source columns x 64 rows (8 values per thread) and 32 x 16
+  // of M (2 per thread); the next chunk's loads are in flight during the FMAs
+  constexpr int PS = kTK * kTR / 256, PM = kTK * kTQ / 256;
+  double cs[PS], cm[PM];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int rr = e % kTR, kc = e / kTR;
+      const int row = row0 + rr, k = k0 + kc;
+      const double v = src.col(min(k, kk - 1))[min(row, n - 1)];
+      cs[u] = (row < n && k < kk) ? v : 0.0;
     }
-    for (int e = threadIdx.x; e < kTK * kTQ; e += 256) {
-      int kc = e % kTK, c = e / kTK;
-      int k = k0 + kc, j = col0 + c;
-      sM[kc][c] = (k < kk && j < q) ? M[k + (size_t)j * ldm] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PM; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int kc = e % kTK, c = e / kTK;
+      const int k = k0 + kc, j = col0 + c;
+      const double v = M[min(k, kk - 1) + (size_t)min(j, q - 1) * ldm];
+      cm[u] = (k < kk && j < q) ? v : 0.0;
+    }
+  };
+  if (kk > 0) load_chunk(0);
+  for (int k0 = 0; k0 < kk; k0 += kTK) {
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      sS[e / kTR][e % kTR] = cs[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PM; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      sM[e % kTK][e / kTK] = cm[u];
     }
     __syncthreads();
+    if (k0 + kTK < kk) load_chunk(k0 + kTK);
 #pragma unroll 8
     for (int kc = 0; kc < kTK; ++kc) {
       double s = sS[kc][r];
@@ -307,20 +347,44 @@ __global__ __launch_bounds__(256) void k_update(const double* __restrict__ S,
   __shared__ double sA[kTK][kTR + 1];
   __shared__ double sC[kTK][kTQ + 1];
   double ax[4] = {0, 0, 0, 0}, xx[4] = {0, 0, 0, 0}, pp[4] = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < Np; k0 += kTK) {
-    for (int e = threadIdx.x; e < kTK * kTR; e += 256) {
-      int rr = e % kTR, kc = e / kTR;
-      int row = row0 + rr, k = k0 + kc;
-      bool ok = (row < n && k < Np);
-      sS[kc][rr] = ok ? S[row + (size_t)k * lds] : 0.0;
-      sA[kc][rr] = ok ? AS[row + (size_t)k * lds] : 0.0;
+  constexpr int PS = kTK * kTR / 256, PC = kTK * kTQ / 256;
+  double cs[PS], ca[PS], cc_[PC];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int rr = e % kTR, kc = e / kTR;
+      const int row = row0 + rr, k = k0 + kc;
+      const size_t o = min(row, n - 1) + (size_t)min(k, Np - 1) * lds;
+      const double vs = S[o], va = AS[o];
+      const bool ok = (row < n && k < Np);
+      cs[u] = ok ? vs : 0.0;
+      ca[u] = ok ? va : 0.0;
     }
-    for (int e = threadIdx.x; e < kTK * kTQ; e += 256) {
-      int kc = e % kTK, c = e / kTK;
-      int k = k0 + kc, j = col0 + c;
-      sC[kc][c] = (k < Np && j < mk) ? C[k + (size_t)j * ldc] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PC; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int kc = e % kTK, c = e / kTK;
+      const int k = k0 + kc, j = col0 + c;
+      const double v = C[min(k, Np - 1) + (size_t)min(j, mk - 1) * ldc];
+      cc_[u] = (k < Np && j < mk) ? v : 0.0;
+    }
+  };
+  if (Np > 0) load_chunk(0);
+  for (int k0 = 0; k0 < Np; k0 += kTK) {
+#pragma unroll
+    for (int u = 0; u < PS; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      sS[e / kTR][e % kTR] = cs[u];
+      sA[e / kTR][e % kTR] = ca[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PC; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      sC[e % kTK][e / kTK] = cc_[u];
     }
     __syncthreads();
+    if (k0 + kTK < Np) load_chunk(k0 + kTK);
 #pragma unroll 8
     for (int kc = 0; kc < kTK; ++kc) {
       double s = sS[kc][r], a = sA[kc][r];

@@ -558,6 +558,7 @@ __device__ inline void wy_back(int N, const double* P, const double* tau, double
 
 template <int NBR, int NBC, int NT, bool EXPORT>
 __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared& sh) {
+  lds = lds_base();  // callers pass the dynamic LDS base; keep its address space
   double* s_lo = sh.lo;
   double* s_hi = sh.hi;
   int& s_npos = *sh.npos;
