@@ -11,7 +11,7 @@ constexpr int kWave = 64;
 constexpr int kMaxM = 48;             // largest block (X columns) of the single-cone engine
 constexpr int kMaxN = 3 * kMaxM;      // largest trial basis [X, R, P]
 constexpr int kRowBlk = 256;          // rows per workgroup in the tall-skinny kernels
-constexpr int kGramRows = 128;        // rows per partial Gram block
+constexpr int kGramRows = 32;         // rows per partial Gram block
 
 // Why an iteration stopped (device state `stop`).
 enum StopReason : int {
