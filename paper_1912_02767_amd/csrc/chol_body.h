@@ -411,73 +411,135 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       for (int q = 0; q < 3; ++q) st->t_sub[8 + q] = tca[q];
   }
   if (mark) st->t_phase[8] = wall_clock64();
-  // kept list
-  if (tid == 0) {
+  // kept list, in wave 0: 64 candidates per ballot, prefix counts by popcount
+  if (tid < 64) {
+    const int nxcand = (a.mode == -1) ? st->nx : m;  // candidates that came from X
     int np = 0, nx = 0;
-    int nxcand = (a.mode == -1) ? st->nx : m;  // candidates that came from X
-    for (int j = 0; j < N; ++j)
-      if (Lp[plo(j, j)] != 0.0) {
-        s_keep[np++] = j;
-        if (j < nxcand) ++nx;
-      }
-    s_Np = np;
-    s_nx = nx;
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      const int j = j0 + tid;
+      const bool kept = j < N && Lp[plo(min(j, N - 1), min(j, N - 1))] != 0.0;
+      const unsigned long long km = __ballot(kept);
+      if (kept) s_keep[np + __popcll(km & ((1ull << tid) - 1ull))] = j;
+      np += __popcll(km);
+      nx += __popcll(__ballot(kept && j < nxcand));
+    }
+    if (tid == 0) {
+      s_Np = np;
+      s_nx = nx;
+    }
   }
   __syncthreads();
   const int Np = s_Np;
-  // in-place inverse of the lower-triangular factor by 16 x 16 block
-  // forward substitution (dropped rows/columns are zero and stay zero):
-  //   Linv[I,I] = inv(L[I,I]);  Linv[I,J] = -Linv[I,I] sum_{J<=K<I} L[I,K] Linv[K,J]
-  // Diagonal blocks are inverted in place first (one wave each, through a
-  // per-wave 16 x 16 buffer); block rows then follow in order, each in
-  // parallel over its entries.  L[I,I] is not needed once inverted.
+  // in-place inverse of the lower-triangular factor by 16 x 16 blocks
+  // (dropped rows and columns are zero and stay zero):
+  //   (1) diagonal blocks, one wave per block and one lane per column:
+  //       forward substitution L x = e_j in registers;
+  //   (2) block rows I = 1, 2, ...: wave J forms
+  //       Linv[I, J] = -Linv[I, I] sum_{J <= K < I} L[I, K] Linv[K, J]
+  //       (a 16 x 16 tile, four entries per lane); all waves have read
+  //       L[I, :] before any of them writes its block.
   {
     const int NB = (N + 15) / 16;
-    double* scratch = row;  // max(waves * 256, 16 * N) doubles
-    const int lane = tid % 64, wv = tid / 64, nw = blockDim.x / 64;
-    double* D = scratch + (size_t)wv * 256;
+    const int lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
     for (int B = wv; B < NB; B += nw) {
       const int o = B * 16, bs = min(16, N - o);
-      for (int e = lane; e < 256; e += 64) D[e] = 0.0;
-      __threadfence_block();
-      for (int j = bs - 1; j >= 0; --j) {
-        double ljj = Lp[plo(o + j, o + j)];
-        double inv = (ljj != 0.0) ? 1.0 / ljj : 0.0;
-        double v = 0.0;
-        int i = j + 1 + lane;
-        if (i < bs && ljj != 0.0) {
-          double sum = 0.0;
-          for (int c = j + 1; c <= i; ++c) sum += D[i + 16 * c] * Lp[plo(o + c, o + j)];
-          v = -inv * sum;
+      if (lane < 16) {
+        const int j = lane;
+        double x[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          x[i] = 0.0;
+          if (i < bs) {
+            const double lii = Lp[plo(o + i, o + i)];
+            double inv = 0.0;
+            if (lii != 0.0) {
+              inv = __builtin_amdgcn_rcp(lii);
+              inv = fma(fma(-lii, inv, 1.0), inv, inv);
+              inv = fma(fma(-lii, inv, 1.0), inv, inv);
+            }
+            double s0 = (i == j) ? 1.0 : 0.0, s1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < i; ++k) {
+              const double l = Lp[plo(o + i, o + k)];
+              if (k & 1) s1 = fma(-l, x[k], s1);
+              else s0 = fma(-l, x[k], s0);
+            }
+            x[i] = (i >= j) ? (s0 + s1) * inv : 0.0;
+          }
         }
-        if (i < bs) D[i + 16 * j] = v;
-        if (lane == 0) D[j + 16 * j] = inv;
-        __threadfence_block();
+        __threadfence_block();  // the wave has read the block before it is overwritten
+        if (j < bs)
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i >= j && i < bs) Lp[plo(o + i, o + j)] = x[i];
       }
-      for (int e = lane; e < bs * bs; e += 64) {
-        int r = e % bs, c = e / bs;
-        if (c <= r) Lp[plo(o + r, o + c)] = D[r + 16 * c];
-      }
-      __threadfence_block();
     }
     __syncthreads();
-    double* tmp = scratch;  // 16 x N
+    if (mark) st->t_sub[11] = wall_clock64() - st->t_phase[8];  // diagonal blocks (and kept list)
+    double* Wt = row + (size_t)wv * 256;  // per-wave 16 x 16 tile
+    const int r = lane & 15, c4 = lane >> 4;
     for (int I = 1; I < NB; ++I) {
       const int oi = I * 16, bi = min(16, N - oi);
-      // tmp[r, c] = sum_{c <= k < oi} L[oi + r, k] Linv[k, c]   (c < oi)
-      for (int e = tid; e < bi * oi; e += blockDim.x) {
-        int r = e % bi, c = e / bi;
-        double sum = 0.0;
-        for (int k = c; k < oi; ++k) sum += Lp[plo(oi + r, k)] * Lp[plo(k, c)];
-        tmp[r + 16 * c] = sum;
+      const int ri = oi + min(r, bi - 1);  // rows past N are computed from a valid row and dropped
+      double out[2][4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int J = wv + h * nw;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) out[h][q] = 0.0;
+        if (J < I) {  // uniform per wave
+          const int oj = J * 16;
+          double acc[4] = {0.0, 0.0, 0.0, 0.0};
+          {
+            // K = J: the diagonal block of Linv is lower triangular
+            const double* lrow = Lp + plo(ri, oj);
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+              const double l = lrow[kk];
+              const double* vrow = Lp + plo(oj + kk, oj);  // row oj + kk, columns oj ..
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int c = 4 * c4 + q;
+                const double v = vrow[min(c, kk)];
+                acc[q] = fma(l, (kk >= c) ? v : 0.0, acc[q]);
+              }
+            }
+          }
+          for (int K = J + 1; K < I; ++K) {
+            // below the diagonal blocks: contiguous rows, no masks
+            const int ok = K * 16;
+            const double* lrow = Lp + plo(ri, ok);
+            double lv[16];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) lv[kk] = lrow[kk];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+              const double* vrow = Lp + plo(ok + kk, oj) + 4 * c4;
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[q] = fma(lv[kk], vrow[q], acc[q]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Wt[r * 16 + 4 * c4 + q] = acc[q];
+          __threadfence_block();
+#pragma unroll
+          for (int qq = 0; qq < 16; ++qq) {
+            const double lq = Lp[plo(ri, oi + min(qq, ri - oi))];  // Linv[I, I](r, qq)
+            const double lqm = (qq <= ri - oi) ? lq : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) out[h][q] = fma(-lqm, Wt[qq * 16 + 4 * c4 + q], out[h][q]);
+          }
+          __threadfence_block();  // the tile buffer is reused by the next J of this wave
+        }
       }
-      __syncthreads();
-      // Linv[oi + r, c] = -sum_{q <= r} Linv[oi + r, oi + q] tmp[q, c]
-      for (int e = tid; e < bi * oi; e += blockDim.x) {
-        int r = e % bi, c = e / bi;
-        double sum = 0.0;
-        for (int q = 0; q <= r; ++q) sum += Lp[plo(oi + r, oi + q)] * tmp[q + 16 * c];
-        Lp[plo(oi + r, c)] = -sum;
+      __syncthreads();  // every wave has read L[I, :]
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int J = wv + h * nw;
+        if (J < I && r < bi) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Lp[plo(oi + r, J * 16 + 4 * c4 + q)] = out[h][q];
+        }
       }
       __syncthreads();
     }

@@ -482,11 +482,11 @@ struct Solver {
       if (h->trace > 1)
         std::fprintf(stderr,
                      "psdp:   rr_sub_us %.0f %.0f | %.0f %.0f %.0f %.0f | rounds %lld mgs %.0f"
-                     " | chol_sub_us %.0f %.0f %.0f\n",
+                     " | chol_sub_us %.0f %.0f %.0f | inv_diag_us %.0f\n",
                      hs->t_sub[0] * 1e-2, hs->t_sub[1] * 1e-2, hs->t_sub[2] * 1e-2,
                      hs->t_sub[3] * 1e-2, hs->t_sub[4] * 1e-2, hs->t_sub[5] * 1e-2,
                      hs->t_sub[6], hs->t_sub[7] * 1e-2, hs->t_sub[8] * 1e-2,
-                     hs->t_sub[9] * 1e-2, hs->t_sub[10] * 1e-2);
+                     hs->t_sub[9] * 1e-2, hs->t_sub[10] * 1e-2, hs->t_sub[11] * 1e-2);
     }
     if (h->prof && hs->stop == kRunning) {
       auto& e = h->prof_tab["rr_stats"];  // launches: RR calls, bytes: sum Np, flops: sum rounds
