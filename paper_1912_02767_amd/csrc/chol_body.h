@@ -341,25 +341,21 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       __syncthreads();
       if (mark) { const long long tn = wall_clock64(); tca[0] += tn - tc; tc = tn; }
       // (2) L[i, o:o+bs] = S[i, o:o+bs] L_D^-T, dropped columns zero
+      // (rows below the block exist only when the block is full: bs = 16)
       for (int i = o + bs + tid; i < N; i += blockDim.x) {
         // right-looking: the dependent chain is one multiply and one fma per column
         double* Li = Lp + plo(i, o);
         double v[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = (j < bs) ? Li[min(j, bs - 1)] : 0.0;
+        for (int j = 0; j < 16; ++j) v[j] = Li[j];
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-          if (j < bs) {
-            v[j] *= pinv[j];
+          v[j] *= pinv[j];
 #pragma unroll
-            for (int k = j + 1; k < 16; ++k)
-              if (k < bs) v[k] = fma(-v[j], Lp[plo(o + k, o + j)], v[k]);
-          }
-          asm volatile("" ::: "memory");  // one column of the block in flight
+          for (int k = j + 1; k < 16; ++k) v[k] = fma(-v[j], Lp[plo(o + k, o) + j], v[k]);
         }
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (j < bs) Li[j] = v[j];
+        for (int j = 0; j < 16; ++j) Li[j] = v[j];
       }
       __syncthreads();
       if (mark) { const long long tn = wall_clock64(); tca[1] += tn - tc; tc = tn; }
