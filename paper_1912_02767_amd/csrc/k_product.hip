@@ -187,26 +187,44 @@ __global__ __launch_bounds__(256) void k_product_mfma(const void* __restrict__ A
   uint4 ring[NL];
 #pragma unroll
   for (int s = 0; s < NL; ++s) ring[s] = *(const uint4*)(arow + min(kbeg + s * KPL, kmax));
-  for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
-    // stage S[kc0 : kc0 + KC, 0 : colsr] in the product precision (rows past
-    // kend are zero), two FP64 values per load
-    for (int e = tid; e < colsr * (KC / 2); e += 256) {
+  // S[kc0 : kc0 + KC, 0 : colsr], two FP64 values per load, is fetched into
+  // registers one chunk ahead (in flight while the current chunk is
+  // multiplied) and stored to LDS in the product precision (rows past kend
+  // are zero)
+  constexpr int PFN = (NCT * 16 * (KC / 2) + 255) / 256;
+  double2 pf[PFN];
+  const int nfe = colsr * (KC / 2);
+  auto fetch = [&](int kc0) {
+#pragma unroll
+    for (int u = 0; u < PFN; ++u) {
+      const int e = min(tid + 256 * u, nfe - 1);
       const int j = e / (KC / 2), kk = 2 * (e % (KC / 2));
-      const int k = kc0 + kk;
-      const double2 v = *(const double2*)(S + min(k, lda - 2) + (size_t)min(j, cols_alloc - 1) * lds);
-      const double v0 = (k < kend) ? v.x : 0.0, v1 = (k + 1 < kend) ? v.y : 0.0;
-      el* dst = sB + j * LDK + kk;
-      if constexpr (PREC == 0) {
-        dst[0] = v0;
-        dst[1] = v1;
-      } else if constexpr (PREC == 1) {
-        *(f2_t*)dst = f2_t{(float)v0, (float)v1};
-      } else {
-        dst[0] = f32_to_bf16_rne((float)v0);
-        dst[1] = f32_to_bf16_rne((float)v1);
+      pf[u] = *(const double2*)(S + min(kc0 + kk, lda - 2) + (size_t)min(j, cols_alloc - 1) * lds);
+    }
+  };
+  fetch(kbeg);
+  for (int kc0 = kbeg; kc0 < kend; kc0 += KC) {
+#pragma unroll
+    for (int u = 0; u < PFN; ++u) {
+      const int e = tid + 256 * u;
+      if (e < nfe) {
+        const int j = e / (KC / 2), kk = 2 * (e % (KC / 2));
+        const int k = kc0 + kk;
+        const double v0 = (k < kend) ? pf[u].x : 0.0, v1 = (k + 1 < kend) ? pf[u].y : 0.0;
+        el* dst = sB + j * LDK + kk;
+        if constexpr (PREC == 0) {
+          dst[0] = v0;
+          dst[1] = v1;
+        } else if constexpr (PREC == 1) {
+          *(f2_t*)dst = f2_t{(float)v0, (float)v1};
+        } else {
+          dst[0] = f32_to_bf16_rne((float)v0);
+          dst[1] = f32_to_bf16_rne((float)v1);
+        }
       }
     }
     __syncthreads();
+    if (kc0 + KC < kend) fetch(kc0 + KC);
     const bool tail = kc0 + KC > kend;  // uniform
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
