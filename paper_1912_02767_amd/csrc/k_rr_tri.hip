@@ -44,17 +44,20 @@ __global__ __launch_bounds__(kFastThreadsS) void k_rr_fast_s(RRArgs a) {
 // Back-transformation of the Ritz vectors of the tridiagonal matrix (C, in
 // place) by the reflectors k_rr_fast left in a.scratch (packed lower
 // triangle, then tau): one workgroup per 16 columns of C.
-constexpr int kBackThreads = 256;
+constexpr int kBackThreads = kWYDenseThreads;
 constexpr int kBackCols = 16;
+
+__host__ __device__ inline int rr_back_nbc(int N) { return N <= 80 ? 5 : 9; }
 
 __host__ __device__ inline size_t rr_back_lds_doubles(int N) {
   const size_t n = N, ldy = (N & 1) ? n : n + 1;
-  return n * (n + 1) / 2 + n + ldy * kBackCols + kWYBlock * kWYBlock + kWYLd * kBackCols;
+  const size_t vb = 16 * (size_t)(16 * rr_back_nbc(N) + 1);
+  return n * (n + 1) / 2 + n + ldy * kBackCols + kWYBlock * kWYBlock + kWYLd * kBackCols + vb;
 }
 
 template <int NBC>
 __global__ __launch_bounds__(kBackThreads) void k_rr_back(RRArgs a) {
-  extern __shared__ double lds[];
+  double* lds = lds_base();
   State* st = a.st;
   if (st->stop) return;
   const int N = st->Np, mk = min(a.mtarget, N);
@@ -68,13 +71,14 @@ __global__ __launch_bounds__(kBackThreads) void k_rr_back(RRArgs a) {
   double* Y = tau + N;
   double* Tb = Y + (size_t)ldy * kBackCols;
   double* Wb = Tb + kWYBlock * kWYBlock;
+  double* Vb = Wb + kWYLd * kBackCols;
   for (size_t x = threadIdx.x; x < n2 + N; x += kBackThreads) P[x] = a.scratch[x];  // P, tau
   for (int x = threadIdx.x; x < ldy * kBackCols; x += kBackThreads) {
     const int i = x % ldy, j = x / ldy;
     Y[x] = (i < N && j < nc) ? a.C[i + (size_t)(j0 + j) * a.ldc] : 0.0;
   }
   __syncthreads();
-  wy_back<kBackThreads, NBC, 2>(N, P, tau, Y, ldy, nc, Tb, Wb, blockIdx.x == 0 ? st : nullptr);
+  wy_back_dense<NBC>(N, P, tau, Y, ldy, nc, Tb, Wb, Vb, blockIdx.x == 0 ? st : nullptr);
   for (int x = threadIdx.x; x < N * nc; x += kBackThreads) {
     const int i = x % N, j = x / N;
     a.C[i + (size_t)(j0 + j) * a.ldc] = Y[i + (size_t)j * ldy];
@@ -105,7 +109,7 @@ hipError_t launch_rr_back(const RRArgs& a, int Np_host, int mk_host, hipStream_t
   if (Np_host > 144 || back * 8 > (size_t)g_tri_lds_limit) return hipErrorInvalidValue;
   const int mk = std::min(mk_host, Np_host);
   if (mk <= 0) return hipSuccess;
-  if (Np_host <= 80)
+  if (rr_back_nbc(Np_host) == 5)
     hipLaunchKernelGGL(k_rr_back<5>, dim3((mk + kBackCols - 1) / kBackCols), dim3(kBackThreads),
                        back * 8, st, a);
   else

@@ -556,6 +556,144 @@ __device__ inline void wy_back(int N, const double* P, const double* tau, double
   }
 }
 
+// The back-transformation of wy_back for 256 threads and up to 16 columns of
+// Y, with each block's reflectors first expanded into a dense zero-padded
+// 16 x ldv array Vb (ldv = 16 NBC + 1, rows b0 + 1 + i' at i', the unit
+// entries and the zeros above them written out).  Every load of the three
+// stages is then unconditional, and the row loops stop at the block's last
+// row instead of running over the whole trial basis.
+constexpr int kWYDenseThreads = 256;
+template <int NBC>
+__host__ __device__ constexpr int wy_dense_ldv() { return 16 * NBC + 1; }
+
+template <int NBC>
+__device__ inline void wy_back_dense(int N, const double* P, const double* tau, double* Y, int ldy,
+                                     int ncols, double* Tb, double* Wb, double* Vb, State* st) {
+  constexpr int NT = kWYDenseThreads;
+  constexpr int LDV = wy_dense_ldv<NBC>();
+  constexpr int LPG = 2;   // reflectors per 16-lane group in (i)
+  constexpr int LQ = 8;    // groups per target tile: groups 0-7 form V^T V, 8-15 V^T Y
+  const int tid = threadIdx.x;
+  const int g = tid >> 4, s16 = tid & 15;
+  const int nref = N - 2;  // reflectors 0 .. N - 3
+  long long tw = wall_clock64(), twa[4] = {0, 0, 0, 0};
+  for (int b0 = nref > 0 ? ((nref - 1) / kWYBlock) * kWYBlock : -1; b0 >= 0; b0 -= kWYBlock) {
+    const int bs = min(kWYBlock, nref - b0);
+    const int nrow = N - 1 - b0;          // rows b0 + 1 .. N - 1
+    const int nu = (nrow + 15) >> 4;      // 16-row chunks
+    // (0) Vb: thread (l = g, s16) fills rows s16 + 16 u of reflector b0 + l
+    {
+      const int l = g, kl = b0 + l, kc = min(kl, N - 3);
+      const int base = pk_cb(kc, N);
+      double pv[NBC];
+#pragma unroll
+      for (int u = 0; u < NBC; ++u) pv[u] = P[base + min(b0 + 1 + s16 + 16 * u, N - 1)];
+      asm volatile("" ::: "memory");  // all loads issued before the selects
+#pragma unroll
+      for (int u = 0; u < NBC; ++u) {
+        const int i = b0 + 1 + s16 + 16 * u;
+        const double v = (l < bs && i < N && i > kl) ? ((i == kl + 1) ? 1.0 : pv[u]) : 0.0;
+        Vb[l * LDV + s16 + 16 * u] = v;
+      }
+    }
+    __syncthreads();
+    // (i) G = V^T [V, Y]
+    {
+      const int lq = g % LQ, tq = g / LQ;
+      double acc[LPG][16];
+#pragma unroll
+      for (int x = 0; x < LPG; ++x)
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) acc[x][tt] = 0.0;
+#pragma unroll 1
+      for (int u = 0; u < nu; ++u) {
+        const int ip = s16 + 16 * u;
+        double vx[LPG], tv[16];
+#pragma unroll
+        for (int x = 0; x < LPG; ++x) vx[x] = Vb[(lq * LPG + x) * LDV + ip];
+        if (tq == 0) {  // uniform per wave
+#pragma unroll
+          for (int tt = 0; tt < 16; ++tt) tv[tt] = Vb[tt * LDV + ip];
+        } else {
+          const int ic = min(b0 + 1 + ip, N - 1);  // v is zero past the last row
+#pragma unroll
+          for (int tt = 0; tt < 16; ++tt) tv[tt] = Y[ic + (size_t)min(tt, ncols - 1) * ldy];
+        }
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt)
+#pragma unroll
+          for (int x = 0; x < LPG; ++x) acc[x][tt] = fma(vx[x], tv[tt], acc[x][tt]);
+      }
+#pragma unroll
+      for (int x = 0; x < LPG; ++x)
+#pragma unroll
+        for (int tt = 0; tt < 16; ++tt) acc[x][tt] = row16_sum(acc[x][tt]);
+      if (s16 == 0) {
+#pragma unroll
+        for (int x = 0; x < LPG; ++x) {
+          const int l = lq * LPG + x;
+#pragma unroll
+          for (int tt = 0; tt < 16; ++tt) {
+            if (tq == 0)
+              Tb[l + kWYBlock * tt] = acc[x][tt];
+            else if (tt < ncols)
+              Wb[l + kWYLd * tt] = acc[x][tt];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) { const long long tn = wall_clock64(); twa[0] += tn - tw; tw = tn; }
+    // (ii) W <- T W by back substitution with U = T^{-1}, one thread per
+    // column: W'(l) = tau_l (W(l) - sum_{m > l} G(l, m) W'(m)); rows l >= bs
+    // of G and W are zero, and tau_l = 0 there
+    if (tid < ncols) {
+      const int j = tid;
+      double w[kWYBlock];
+#pragma unroll
+      for (int l = 0; l < kWYBlock; ++l) {
+        const double wl = Wb[l + kWYLd * j];
+        w[l] = (l < bs) ? wl : 0.0;
+      }
+#pragma unroll
+      for (int l = kWYBlock - 1; l >= 0; --l) {
+        double s = w[l];
+#pragma unroll
+        for (int m = l + 1; m < kWYBlock; ++m) s = fma(-Tb[l + kWYBlock * m], w[m], s);
+        const double tl = tau[b0 + min(l, bs - 1)];
+        w[l] = (l < bs) ? tl * s : 0.0;
+        asm volatile("" ::: "memory");  // one row of G in flight at a time
+      }
+#pragma unroll
+      for (int l = 0; l < kWYBlock; ++l) Wb[l + kWYLd * j] = w[l];
+    }
+    __syncthreads();
+    if (tid == 0) { const long long tn = wall_clock64(); twa[1] += tn - tw; tw = tn; }
+    // (iii) Y -= V W: thread (r, c) on rows b0 + 1 + r + 16 li of column c
+    {
+      const int r = tid >> 4, c = tid & 15, jc = min(c, ncols - 1);
+      double wr[kWYBlock];
+#pragma unroll
+      for (int l = 0; l < kWYBlock; ++l) wr[l] = Wb[l + kWYLd * jc];
+#pragma unroll 1
+      for (int ip = r; ip < nrow; ip += 16) {
+        double vr[kWYBlock];
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) vr[l] = Vb[l * LDV + ip];
+        double* yp = Y + (b0 + 1 + ip) + (size_t)jc * ldy;
+        double s = *yp;
+#pragma unroll
+        for (int l = 0; l < kWYBlock; ++l) s = fma(-vr[l], wr[l], s);
+        if (c < ncols) *yp = s;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) { const long long tn = wall_clock64(); twa[3] += tn - tw; tw = tn; }
+  }
+  if (tid == 0 && st)
+    for (int q = 0; q < 4; ++q) st->t_sub[2 + q] = twa[q];
+}
+
 template <int NBR, int NBC, int NT, bool EXPORT>
 __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared& sh) {
   lds = lds_base();  // callers pass the dynamic LDS base; keep its address space
