@@ -155,6 +155,76 @@ __device__ inline int sturm_count_n1(const double* d, const double* e2, int N, d
   return cnt;
 }
 
+// Sturm count of T - x I by the three-term recurrence of its leading
+// principal minors, p_{i+1} = (d_i - x) p_i - e_{i-1}^2 p_{i-1} with p_0 = 1,
+// p_1 = d_0 - x: the number of sign changes along p_0 .. p_N is the number of
+// eigenvalues below x, a zero minor taking the sign opposite to its
+// predecessor (the limit of the ratio form's -pivmin).  ds, e2s and xs are d,
+// e^2 and x scaled by a power of two that brings ||T|| below one, so |p|
+// grows at most threefold per step; every 8 steps the pair (p_i, p_{i+1}) is
+// rescaled by a power of two.  The same backward error as the ratio form
+// (relative perturbations of d_i - x and e_i^2 of a few ulps), with one
+// dependent FMA per step in place of a division chain.  Returns -1 when the
+// pair fell below 2^-900, became zero or non-finite; the caller then counts
+// with the ratio form.
+__device__ inline void sturm_poly_step(double dsi, double e2m, double xs, double& a, double& b,
+                                       bool& sb, int& cnt) {
+  const double c = fma(dsi - xs, b, -e2m * a);
+  const bool sc = (c < 0.0) | ((c == 0.0) & !sb);  // no short circuit: no branches
+  cnt += (sc != sb) ? 1 : 0;
+  sb = sc;
+  a = b;
+  b = c;
+}
+
+__device__ inline int sturm_count_poly(const double* ds, const double* e2s, int N, double xs) {
+  double a = 1.0, b = ds[0] - xs;
+  bool sb = !(b > 0.0);  // p_0 = 1 > 0: a zero p_1 counts as negative
+  int cnt = sb ? 1 : 0, emin = 0;
+  // blocks of 8 steps; the next block's entries are loaded during the current one
+  double dn[8], en[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    dn[u] = ds[min(1 + u, N - 1)];
+    en[u] = e2s[min(u, N - 1)];
+  }
+  int i = 1;
+  for (; i + 8 <= N; i += 8) {
+    double dc[8], ec[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dc[u] = dn[u];
+      ec[u] = en[u];
+      dn[u] = ds[min(i + 8 + u, N - 1)];
+      en[u] = e2s[min(i + 7 + u, N - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sturm_poly_step(dc[u], ec[u], xs, a, b, sb, cnt);
+    const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(a), fabs(b)));
+    emin = min(emin, ex);
+    a = __builtin_amdgcn_ldexp(a, -ex);
+    b = __builtin_amdgcn_ldexp(b, -ex);
+  }
+  for (; i < N; ++i) sturm_poly_step(ds[i], e2s[i - 1], xs, a, b, sb, cnt);
+  const double m = fmax(fabs(a), fabs(b));
+  emin = min(emin, __builtin_amdgcn_frexp_exp(m));
+  const bool bad = !(m > 0.0) || !(m < 1e300) || emin < -900;
+  return bad ? -1 : cnt;
+}
+
+// The count for the shift x: the scaled recurrence, or the ratio form when
+// it reports underflow (d, e2 unscaled; sh the scaling exponent).
+__device__ inline int sturm_count_fast(const double* ds, const double* e2s, const double* d,
+                                       const double* e2, int N, double x, int sh, double pivmin) {
+  const int c = sturm_count_poly(ds, e2s, N, __builtin_amdgcn_ldexp(x, -sh));
+  return c >= 0 ? c : sturm_count_n1(d, e2, N, x, pivmin);
+}
+
+// An eigenvalue bracket [lo, hi] is still open above a few ulps of ||T||.
+__device__ inline bool bracket_open(double lo, double hi, double tnorm, double pivmin) {
+  return hi - lo > 4.4e-16 * (tnorm + fmax(fabs(lo), fabs(hi))) + 4.0 * pivmin;
+}
+
 // Reflector scalars of a column with leading entry alpha and squared norm
 // xn of the entries below it (LAPACK dlarfg convention, beta = -sign(alpha) |x|).
 __device__ inline void reflector(double alpha, double xn, double& t, double& beta, double& scale) {
@@ -200,20 +270,21 @@ __device__ inline double sel(const double (&row)[NB], int q) {
 // li < NBR, lj < NBC (both triangles): contiguous row blocks, so the 16
 // threads of one row group are 16 lanes of one wave and each wave owns 4 NBR
 // consecutive rows.  LDS vectors (LP entries, zero-padded) hold the current
-// column x (rows <= k zero), the reflector v and w (rows <= k zero), A x and
-// column k + 1 before the update.  Per step k:
+// column x (rows <= k zero), w (rows <= k zero), A x and column k + 1 before
+// the update.  Per step k:
 //   (a) every thread loads x on its columns and forms |x|^2 over the 16 lanes
 //       of its row group (DPP); waves that own a row below k form their
 //       rows of A x (summed over the row group) and their part of x^T A x;
-//       the owners of column k + 1 publish it;
-//   (b) every thread forms the reflector scalars (dlarfg convention); with
-//       v = scale x + g e_{k+1} (g = 1 - scale x_{k+1}), A v and v^T A v follow
-//       from A x, x^T A x and column k + 1; one thread per trailing row forms
-//       w = t A v - (t^2 / 2)(v^T A v) v, stores v and w, keeps the reflector
+//       the owners of column k + 1 publish it; every thread forms the
+//       reflector scalars (dlarfg convention);
+//   (b) with v = scale x + g e_{k+1} (g = 1 - scale x_{k+1}), A v and v^T A v
+//       follow from A x, x^T A x and column k + 1; one thread per trailing row
+//       forms w = t A v - (t^2 / 2)(v^T A v) v, stores w, keeps the reflector
 //       in P, and forms column k + 1 after the update (the next column
 //       buffer) and its diagonal entry;
-//   (c) waves that own a row below k apply A -= v w^T + w v^T to their block
-//       (entries in finished rows or columns see zero v and w and stay put).
+//   (c) waves that own a row below k apply A -= v w^T + w v^T to their block,
+//       v formed again from the x of (a) in the registers (entries in
+//       finished rows or columns see zero v and w and stay put).
 // Two barriers per step.  On return: d, e (N - 1 entries), tau, and the
 // reflectors (unit entry at row k + 1 included) in the packed column-major
 // lower triangle P.
@@ -227,12 +298,11 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
   const int row0 = r * NBR;
   const int wave_last_row = (4 * wv + 4) * NBR - 1;
   // LDS vectors: two column buffers at buf and buf + LP (addressed by offset:
-  // a pointer picked from an array loses its LDS address space), v, w, A x,
+  // a pointer picked from an array loses its LDS address space), w, A x,
   // column k + 1
-  double* vb = buf + 2 * LP;
-  double* wb = buf + 3 * LP;
-  double* pf = buf + 4 * LP;
-  double* cpre = buf + 5 * LP;
+  double* wb = buf + 2 * LP;
+  double* pf = buf + 3 * LP;
+  double* cpre = buf + 4 * LP;
   double A[NBR][NBC];
 #pragma unroll
   for (int li = 0; li < NBR; ++li)
@@ -246,7 +316,6 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
   for (int i = tid; i < LP; i += NT) {
     buf[i] = (i >= 1 && i < N) ? 0.5 * (a.K[i] + a.K[(size_t)i * a.ldk]) : 0.0;
     buf[LP + i] = 0.0;  // rows at or beyond N stay zero in every vector
-    vb[i] = 0.0;
     wb[i] = 0.0;
     pf[i] = 0.0;
     cpre[i] = 0.0;
@@ -267,28 +336,10 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
 #pragma unroll
     for (int q = 0; q < NBC; ++q) xs3[q % 3] = fma(xc[q], xc[q], xs3[q % 3]);
     double xs = row16_sum((xs3[0] + xs3[1]) + xs3[2]);  // |x|^2, x_{k+1} included
-    // reflector scalars (dlarfg convention), off the critical path of (b):
-    // r = 1 / sqrt(|x|^2) by reciprocal square root and two Newton steps,
-    // beta = -sign(alpha) |x|, t = (beta - alpha) / beta = 1 + |alpha| r,
-    // scale = 1 / (alpha - beta) = sign(alpha) / (|alpha| + |x|)
     const double alpha = col[k + 1];
-    double t = 0.0, beta = alpha, scale = 0.0;
-    if (xs - alpha * alpha > 0.0) {
-      double r = __builtin_amdgcn_rsq(xs);
-      r = r * fma(-0.5 * xs * r, r, 1.5);
-      r = r * fma(-0.5 * xs * r, r, 1.5);
-      const double nx = xs * r, aa = fabs(alpha);
-      beta = -copysign(nx, alpha);
-      t = fma(aa, r, 1.0);
-      const double den = aa + nx;
-      double q = __builtin_amdgcn_rcp(den);
-      q = fma(fma(-den, q, 1.0), q, q);
-      q = fma(fma(-den, q, 1.0), q, q);
-      scale = copysign(q, alpha);
-    }
     double xax = 0.0;
+    double xr[NBR];  // x on this thread's rows (also gives v there in (c))
     if (live) {
-      double xr[NBR];
 #pragma unroll
       for (int q = 0; q < NBR; ++q) xr[q] = col[row0 + q];
 #pragma unroll
@@ -324,60 +375,83 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
       }
       if (lane == 0) red[wv] = s4;
     }
+    // reflector scalars (dlarfg convention), branch-free so that they overlap
+    // the products above: r = 1 / sqrt(|x|^2) by reciprocal square root and
+    // two Newton steps, beta = -sign(alpha) |x|, t = (beta - alpha) / beta =
+    // 1 + |alpha| r, scale = 1 / (alpha - beta) = sign(alpha) / (|alpha| + |x|)
+    double t, beta, scale;
+    {
+      const bool refl = xs - alpha * alpha > 0.0;
+      const double xq = refl ? xs : 1.0;
+      double rs = __builtin_amdgcn_rsq(xq);
+      rs = rs * fma(-0.5 * xq * rs, rs, 1.5);
+      rs = rs * fma(-0.5 * xq * rs, rs, 1.5);
+      const double nx = xq * rs, aa = fabs(alpha);
+      const double den = aa + nx;
+      double q = __builtin_amdgcn_rcp(den);
+      q = fma(fma(-den, q, 1.0), q, q);
+      q = fma(fma(-den, q, 1.0), q, q);
+      t = refl ? fma(aa, rs, 1.0) : 0.0;
+      beta = refl ? -copysign(nx, alpha) : alpha;
+      scale = refl ? copysign(q, alpha) : 0.0;
+    }
     __syncthreads();
     if (tid == 0) { const long long tn = wall_clock64(); tacc0 += tn - tl; tl = tn; }
     // ---- (b) v and w, the reflector kept in P, the next column
-    const double g = 1.0 - scale * alpha;
-    double rw[nw];
-#pragma unroll
-    for (int q = 0; q < nw; ++q) rw[q] = red[q];
-#pragma unroll
-    for (int h = 1; h < nw; h *= 2)  // pairwise: log2(nw) dependent adds
-#pragma unroll
-      for (int q = 0; q + h < nw; q += 2 * h) rw[q] += rw[q + h];
-    const double xaxs = rw[0];
-    const double ax1 = pf[k + 1], a11 = cpre[k + 1];
-    // v^T A v = scale^2 x^T A x + 2 scale g (A x)_{k+1} + g^2 A(k+1, k+1)
-    const double vav = scale * scale * xaxs + 2.0 * scale * g * ax1 + g * g * a11;
-    const double alf = -0.5 * t * t * vav;
-    // (A v)_i = scale (A x)_i + g A(i, k+1)
-    const double w1 = (t != 0.0) ? t * (scale * ax1 + g * a11) + alf : 0.0;  // v_{k+1} = 1
-    if (tid == 0) {
-      tau[k] = t;
-      e[k] = beta;
-      coln[k] = 0.0;  // rows <= k + 1 of the next column, v and w are zero
-      vb[k] = 0.0;
-      wb[k] = 0.0;
-    }
-    const int ck = pk_cb(k, N);
-    for (int i = k + 1 + tid; i < N; i += NT) {
-      const double x = col[i];
-      const double vi = (i == k + 1) ? 1.0 : x * scale;
-      const double ci = cpre[i];
-      const double wi = (t != 0.0) ? t * (scale * pf[i] + g * ci) + alf * vi : 0.0;
-      vb[i] = (t != 0.0) ? vi : 0.0;
-      wb[i] = wi;
-      // reflector kept below the diagonal of column k (identity if t = 0)
-      P[ck + i] = (t != 0.0) ? vi : ((i == k + 1) ? 1.0 : 0.0);
-      // column k + 1 after the update: A(i, k+1) - v_i w_{k+1} - w_i v_{k+1}
-      const double upd = (t != 0.0) ? vi * w1 + wi : 0.0;
-      if (i == k + 1) d[k + 1] = ci - ((t != 0.0) ? 2.0 * w1 : 0.0);
-      coln[i] = (i >= k + 2) ? ci - upd : 0.0;
+    // (threads past the last trailing row skip the phase)
+    if (k + 1 + tid < N) {
+      const double g = 1.0 - scale * alpha;
+      double rw[nw];
+  #pragma unroll
+      for (int q = 0; q < nw; ++q) rw[q] = red[q];
+  #pragma unroll
+      for (int h = 1; h < nw; h *= 2)  // pairwise: log2(nw) dependent adds
+  #pragma unroll
+        for (int q = 0; q + h < nw; q += 2 * h) rw[q] += rw[q + h];
+      const double xaxs = rw[0];
+      const double ax1 = pf[k + 1], a11 = cpre[k + 1];
+      // v^T A v = scale^2 x^T A x + 2 scale g (A x)_{k+1} + g^2 A(k+1, k+1)
+      const double vav = scale * scale * xaxs + 2.0 * scale * g * ax1 + g * g * a11;
+      const double alf = -0.5 * t * t * vav;
+      // (A v)_i = scale (A x)_i + g A(i, k+1)
+      const double w1 = (t != 0.0) ? t * (scale * ax1 + g * a11) + alf : 0.0;  // v_{k+1} = 1
+      if (tid == 0) {
+        tau[k] = t;
+        e[k] = beta;
+        coln[k] = 0.0;  // rows <= k + 1 of the next column, v and w are zero
+        wb[k] = 0.0;
+      }
+      const int ck = pk_cb(k, N);
+      for (int i = k + 1 + tid; i < N; i += NT) {
+        const double x = col[i];
+        const double vi = (i == k + 1) ? 1.0 : x * scale;
+        const double ci = cpre[i];
+        const double wi = (t != 0.0) ? t * (scale * pf[i] + g * ci) + alf * vi : 0.0;
+        wb[i] = wi;
+        // reflector kept below the diagonal of column k (identity if t = 0)
+        P[ck + i] = (t != 0.0) ? vi : ((i == k + 1) ? 1.0 : 0.0);
+        // column k + 1 after the update: A(i, k+1) - v_i w_{k+1} - w_i v_{k+1}
+        const double upd = (t != 0.0) ? vi * w1 + wi : 0.0;
+        if (i == k + 1) d[k + 1] = ci - ((t != 0.0) ? 2.0 * w1 : 0.0);
+        coln[i] = (i >= k + 2) ? ci - upd : 0.0;
+      }
     }
     __syncthreads();
     if (tid == 0) { const long long tn = wall_clock64(); tacc1 += tn - tl; tl = tn; }
-    // ---- (c) rank-2 update of this thread's block
+    // ---- (c) rank-2 update of this thread's block; v comes from x in the
+    // registers (v = scale x below row k + 1, v_{k+1} = 1, the same products
+    // as in (b)), w from LDS
     if (live && t != 0.0) {
       double vr[NBR], vc[NBC], wr[NBR], wc[NBC];
 #pragma unroll
       for (int q = 0; q < NBR; ++q) {
-        vr[q] = vb[row0 + q];
         wr[q] = wb[row0 + q];
+        vr[q] = (row0 + q == k + 1) ? 1.0 : xr[q] * scale;
       }
 #pragma unroll
       for (int q = 0; q < NBC; ++q) {
-        vc[q] = vb[c + 16 * q];
         wc[q] = wb[c + 16 * q];
+        vc[q] = (c + 16 * q == k + 1) ? 1.0 : xc[q] * scale;
       }
 #pragma unroll
       for (int li = 0; li < NBR; ++li)
@@ -739,6 +813,17 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
   }
   __syncthreads();
   const double tnorm = s_tnorm, pivmin = s_pivmin;
+  // d and e^2 scaled by 2^-tsh (||T|| below one) for the polynomial Sturm
+  // counts, after the counts in the Y region (nt ints; the region holds
+  // max(nt, 6 lp) doubles with lp >= N)
+  const int tsh = tnorm > 0.0 ? __builtin_amdgcn_frexp_exp(tnorm) : 0;
+  double* dsc = Y + nt / 2;
+  double* e2sc = dsc + N;
+  for (int i = tid; i < N; i += nt) {
+    dsc[i] = __builtin_amdgcn_ldexp(d[i], -tsh);
+    e2sc[i] = (i + 1 < N) ? __builtin_amdgcn_ldexp(e2[i], -2 * tsh) : 0.0;
+  }
+  __syncthreads();
   if (tid == 0) st->t_phase[1] = wall_clock64();
 
   // ---- 2. multisection for the top mk eigenvalues (+ count of positives)
@@ -756,10 +841,14 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
     // the eigenvalues at once, and the count below zero; each eigenvalue's
     // bracket follows by binary search over the counts, keeping
     // count(lo) <= target < count(hi)
+    // open brackets: per-wave ballots in LDS (the tridiagonalization's
+    // reduction slots), read by every thread after the next barrier
+    int* oflag = reinterpret_cast<int*>(red);
+    bool open = false;
     {
       const int ng = nt - 1;
       const double x = (tid < ng) ? gl + (gu - gl) * (double)(tid + 1) / (double)(ng + 1) : 0.0;
-      cnts[tid] = sturm_count_n1(d, e2, N, x, pivmin);
+      cnts[tid] = sturm_count_fast(dsc, e2sc, d, e2, N, x, tsh, pivmin);
       __syncthreads();
       if (tid == nt - 1) s_npos = N - cnts[tid];
       for (int j = tid; j < mk; j += nt) {
@@ -770,41 +859,52 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
           if (cnts[mid] <= target) a0 = mid;
           else a1 = mid;
         }
-        s_lo[j] = (a0 < 0) ? gl : gl + (gu - gl) * (double)(a0 + 1) / (double)(ng + 1);
-        s_hi[j] = (a1 >= ng) ? gu : gl + (gu - gl) * (double)(a1 + 1) / (double)(ng + 1);
+        const double lo = (a0 < 0) ? gl : gl + (gu - gl) * (double)(a0 + 1) / (double)(ng + 1);
+        const double hi = (a1 >= ng) ? gu : gl + (gu - gl) * (double)(a1 + 1) / (double)(ng + 1);
+        s_lo[j] = lo;
+        s_hi[j] = hi;
+        open = open || bracket_open(lo, hi, tnorm, pivmin);
       }
-      __syncthreads();
     }
+    {
+      const unsigned long long bal = __ballot(open);
+      if (lane == 0) oflag[wv] = bal != 0ull;
+    }
+    __syncthreads();
     const int per = max(1, nt / max(mk, 1));  // shifts per eigenvalue per round
     const int j_me = tid / per, s_me = tid % per;
     int rounds = 1;
     for (int round = 0; round < 64; ++round) {
-      bool done = true;
-      for (int j = 0; j < mk; ++j) {
-        const double w = s_hi[j] - s_lo[j];
-        const double tolj = 4.4e-16 * (tnorm + fmax(fabs(s_lo[j]), fabs(s_hi[j]))) + 4.0 * pivmin;
-        if (w > tolj) { done = false; break; }
-      }
-      if (done) break;
+      bool any = false;
+      for (int q = 0; q < nt / 64; ++q) any = any || oflag[q] != 0;
+      if (!any) break;
       ++rounds;
       if (j_me < mk) {
         const double lo = s_lo[j_me], hi = s_hi[j_me];
         const double x = lo + (hi - lo) * (double)(s_me + 1) / (double)(per + 1);
-        cnts[tid] = sturm_count_n1(d, e2, N, x, pivmin);
+        cnts[tid] = sturm_count_fast(dsc, e2sc, d, e2, N, x, tsh, pivmin);
       }
       __syncthreads();
+      // new bracket: the first shift whose count exceeds the target (all
+      // counts loaded before the selects, no early exit)
+      open = false;
       if (tid < mk) {
         const int j = tid;
         const int target = N - 1 - j;  // ascending index of the j-th largest
         const double lo = s_lo[j], hi = s_hi[j];
-        double nlo = lo, nhi = hi;
-        for (int s2 = 0; s2 < per; ++s2) {
-          const double x = lo + (hi - lo) * (double)(s2 + 1) / (double)(per + 1);
-          if (cnts[j * per + s2] <= target) nlo = x;
-          else { nhi = x; break; }
-        }
+        int first = per;
+        for (int s2 = per - 1; s2 >= 0; --s2) first = (cnts[j * per + s2] > target) ? s2 : first;
+        const double nlo =
+            (first > 0) ? lo + (hi - lo) * (double)first / (double)(per + 1) : lo;
+        const double nhi =
+            (first < per) ? lo + (hi - lo) * (double)(first + 1) / (double)(per + 1) : hi;
         s_lo[j] = nlo;
         s_hi[j] = nhi;
+        open = bracket_open(nlo, nhi, tnorm, pivmin);
+      }
+      {
+        const unsigned long long bal = __ballot(open);
+        if (lane == 0) oflag[wv] = bal != 0ull;
       }
       __syncthreads();
     }
