@@ -799,17 +799,57 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
 
   // ---- 1. tridiagonalization (matrix in registers)
   tridiag_reg<NBR, NBC, NT>(a, N, P, d, e, tau, tbuf, red);
-  for (int i = tid; i + 1 < N; i += nt) e2[i] = e[i] * e[i];
-  __syncthreads();
-  if (tid == 0) {
-    double tn = 0.0, emax2 = 0.0;
-    for (int i = 0; i < N; ++i) {
-      double rr = fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
-      tn = fmax(tn, rr);
-      if (i + 1 < N) emax2 = fmax(emax2, e2[i]);
+  // e^2, and in one parallel pass the row-sum norm ||T||, max e^2 and the
+  // Gershgorin interval (max / min reductions: the same values as a serial loop)
+  double s_gl, s_gu;
+  {
+    double tn = 0.0, em = 0.0, gl = 0.0, gu = 0.0;
+    bool any = false;
+    for (int i = tid; i < N; i += nt) {
+      const double ea = (i > 0) ? fabs(e[i - 1]) : 0.0;
+      const double eb = (i + 1 < N) ? fabs(e[i]) : 0.0;
+      if (i + 1 < N) {
+        const double q = e[i] * e[i];
+        e2[i] = q;
+        em = fmax(em, q);
+      }
+      tn = fmax(tn, fabs(d[i]) + ea + eb);
+      const double rr = ea + eb;
+      gl = any ? fmin(gl, d[i] - rr) : d[i] - rr;
+      gu = any ? fmax(gu, d[i] + rr) : d[i] + rr;
+      any = true;
     }
-    s_tnorm = tn;
-    s_pivmin = 2.2250738585072014e-308 * fmax(1.0, emax2);
+    if (!any) {  // neutral elements for the reductions
+      gl = __builtin_inf();
+      gu = -__builtin_inf();
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      tn = fmax(tn, __shfl_xor(tn, o, 64));
+      em = fmax(em, __shfl_xor(em, o, 64));
+      gl = fmin(gl, __shfl_xor(gl, o, 64));
+      gu = fmax(gu, __shfl_xor(gu, o, 64));
+    }
+    double* part = s_lo;  // 4 per wave (the brackets are written later)
+    if (lane == 0) {
+      part[4 * wv] = tn;
+      part[4 * wv + 1] = em;
+      part[4 * wv + 2] = gl;
+      part[4 * wv + 3] = gu;
+    }
+    __syncthreads();
+    for (int q = 0; q < nt / 64; ++q) {
+      tn = fmax(tn, part[4 * q]);
+      em = fmax(em, part[4 * q + 1]);
+      gl = fmin(gl, part[4 * q + 2]);
+      gu = fmax(gu, part[4 * q + 3]);
+    }
+    s_gl = gl;
+    s_gu = gu;
+    if (tid == 0) {
+      s_tnorm = tn;
+      s_pivmin = 2.2250738585072014e-308 * fmax(1.0, em);
+    }
   }
   __syncthreads();
   const double tnorm = s_tnorm, pivmin = s_pivmin;
@@ -828,12 +868,7 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
 
   // ---- 2. multisection for the top mk eigenvalues (+ count of positives)
   {
-    double gl = 0.0, gu = 0.0;
-    for (int i = 0; i < N; ++i) {
-      double rr = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < N ? fabs(e[i]) : 0.0);
-      gl = (i == 0) ? d[i] - rr : fmin(gl, d[i] - rr);
-      gu = (i == 0) ? d[i] + rr : fmax(gu, d[i] + rr);
-    }
+    double gl = s_gl, gu = s_gu;
     const double pad = 2.2e-16 * tnorm * 4.0 * N + 2.0 * pivmin;
     gl -= pad;
     gu += pad;
