@@ -9,8 +9,8 @@
 //      to a few ulps of ||T||;
 //   3. eigenvectors of T by the twisted factorization of T - sigma I (top-down
 //      and bottom-up pivots, twist at the smallest |gamma|), one thread per
-//      vector; modified Gram-Schmidt inside clusters (with inverse iteration
-//      from a fixed start vector when a vector collapses onto its
+//      vector; classical Gram-Schmidt, twice, inside clusters (with inverse
+//      iteration from a fixed start vector when a vector collapses onto its
 //      predecessors, as for exactly repeated eigenvalues); Rayleigh quotients;
 //   4. back-transformation by blocks of 16 reflectors in compact WY form
 //      (wy_back), in the same workgroup (batched engine) or in a separate
@@ -964,8 +964,11 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
   }
   __syncthreads();
   if (tid == 0) t_mgs = wall_clock64();
-  // modified Gram-Schmidt inside clusters (wave 0)
-  if (wv == 0) {
+  // Gram-Schmidt inside clusters, block-wide: classical, applied twice per
+  // vector (every dot product of a pass at once, one wave each), then the
+  // norm by a block reduction; dot products in Tb
+  {
+    double* dots = Tb;
     for (int j = 1; j < mk; ++j) {
       const double mid_j = 0.5 * (s_lo[j] + s_hi[j]);
       const double mid_p = 0.5 * (s_lo[j - 1] + s_hi[j - 1]);
@@ -976,27 +979,37 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
       double* yj = Y + (size_t)j * ldy;
       for (int attempt = 0; attempt < 2; ++attempt) {
         for (int pass = 0; pass < 2; ++pass) {
-          for (int i0 = c0; i0 < j; ++i0) {
+          for (int i0 = c0 + wv; i0 < j; i0 += nt / 64) {
             const double* yi = Y + (size_t)i0 * ldy;
             double dp = 0.0;
             for (int q = lane; q < N; q += 64) dp += yi[q] * yj[q];
             dp = wave_sum(dp);
-            for (int q = lane; q < N; q += 64) yj[q] -= dp * yi[q];
-            __threadfence_block();
+            if (lane == 0) dots[i0 - c0] = dp;
           }
+          __syncthreads();
+          for (int q = tid; q < N; q += nt) {
+            double v = yj[q];
+            for (int i0 = c0; i0 < j; ++i0) v -= dots[i0 - c0] * Y[q + (size_t)i0 * ldy];
+            yj[q] = v;
+          }
+          __syncthreads();
         }
         double nn = 0.0;
-        for (int q = lane; q < N; q += 64) nn += yj[q] * yj[q];
+        for (int q = tid; q < N; q += nt) nn += yj[q] * yj[q];
         nn = wave_sum(nn);
+        if (lane == 0) red[wv] = nn;
+        __syncthreads();
+        nn = 0.0;
+        for (int q = 0; q < nt / 64; ++q) nn += red[q];
         if (nn > 0.25 || attempt == 1) {
           const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-          for (int q = lane; q < N; q += 64) yj[q] *= inv;
-          __threadfence_block();
+          for (int q = tid; q < N; q += nt) yj[q] *= inv;
+          __syncthreads();
           break;
         }
         // the vector collapsed onto its predecessors (repeated eigenvalue):
-        // inverse iteration from a fixed start vector, factors in Tb/Wb
-        if (lane == 0) {
+        // inverse iteration from a fixed start vector, factors in Tb
+        if (tid == 0) {
           for (int i = 0; i < N; ++i) yj[i] = start_entry(i, j);
           double* U0 = Tb;
           tri_solve(d, e, N, mid_j, pfloor, yj, U0, U0 + N, U0 + 2 * N, 1);
@@ -1005,11 +1018,10 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
           const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
           for (int i = 0; i < N; ++i) yj[i] *= sc;
         }
-        __threadfence_block();
+        __syncthreads();
       }
     }
   }
-  __syncthreads();
   if (tid == 0) st->t_sub[7] = wall_clock64() - t_mgs;
   // Rayleigh quotients y^T T y
   for (int j = tid; j < mk; j += nt) {
