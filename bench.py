@@ -59,10 +59,10 @@ FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rrback", "rebuild", "inges
 # kernel and is reported as null.
 TRAFFIC = {
     ("n1000_warm_seq", "rr"): {
-        "bytes": 99.8e3,
+        "bytes": 108.7e3,
         "files": ["paper_1912_02767_amd/csrc/rr_fast.h", "paper_1912_02767_amd/csrc/rr_body.h",
                   "paper_1912_02767_amd/csrc/k_rr_tri.hip", "paper_1912_02767_amd/csrc/common.h"],
-        "sha256": "3ff1ff022d8cb9a3466e3cf455c502a771c6a2fc7787d59d3ff0208efd703669",
+        "sha256": "6d391e6fb84fb1dceaa87e09227b0e8a897e7cc5a3539b6a99b7155e90089a62",
         "profile": "profiles/hbm_traffic_n1000_warm_seq.txt",
     },
 }
