@@ -336,6 +336,14 @@ psdp_status psdp_profile_enable(psdp_handle h, int on);
 psdp_status psdp_profile_get(psdp_handle h, const char *family, long *launches,
                              double *total_ms, double *bytes, double *flops);
 
+/* Restricts the timing of psdp_profile_enable to the comma-separated kernel
+ * families in `families` (e.g. "rr"); NULL or "" times every family.  Each
+ * timed family adds two hipEvent records per launch group to the stream,
+ * and every record costs the stream a few microseconds, so a throughput
+ * measurement times only the family it reports.  The filter is kept by the
+ * handle until changed; PSDP_ERR_INVALID_ARG for a null handle. */
+psdp_status psdp_profile_filter(psdp_handle h, const char *families);
+
 /* Library version string. */
 const char *psdp_version(void);
 

@@ -262,6 +262,10 @@ class Projector:
     def profile_enable(self, on: bool = True):
         self.lib.psdp_profile_enable(self._h, 1 if on else 0)
 
+    def profile_filter(self, families: str = ""):
+        """Time only these comma-separated kernel families ("" = all)."""
+        self.lib.psdp_profile_filter(self._h, families.encode())
+
     def full_eig_batched(self, Xs: Sequence, m_caps=None, V_bufs=None, Pi_outs=None):
         """Exact projections of many small cones (n <= 256) in zero-padded
         buckets (psdp_full_eig_project_batched).  With m_caps, also the

@@ -30,6 +30,7 @@ EXPORTED = [
     "psdp_server_open_session", "psdp_server_close_session", "psdp_server_submit",
     "psdp_server_wait", "psdp_server_drain", "psdp_server_session_block",
     "psdp_server_stats_get", "psdp_server_stats_reset", "psdp_full_eig_project_batched",
+    "psdp_profile_filter",
 ]
 
 
@@ -180,6 +181,8 @@ def load():
     lib.psdp_batched_tuning.restype = ctypes.c_int
     lib.psdp_profile_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_long), dp, dp, dp]
     lib.psdp_profile_get.restype = ctypes.c_int
+    lib.psdp_profile_filter.argtypes = [vp, ctypes.c_char_p]
+    lib.psdp_profile_filter.restype = ctypes.c_int
     llp = ctypes.POINTER(ctypes.c_longlong)
     lib.psdp_full_eig_project_batched.restype = ctypes.c_int
     lib.psdp_server_default_config.argtypes = [ctypes.POINTER(ServerConfig)]

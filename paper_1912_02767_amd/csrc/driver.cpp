@@ -24,6 +24,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -122,6 +123,7 @@ struct psdp_handle_s {
                       // 1: Jacobi, 2: first tridiagonal design (inverse iteration)
   int trace = 0;      // PSDP_TRACE=1: one line per iteration on stderr (2: RR stages)
   bool prof = false;
+  std::set<std::string> prof_only;  // families timed while prof is on (empty: all)
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> event_pool;
@@ -158,14 +160,14 @@ struct ProfScope {
   double bytes, flops;
   ProfScope(psdp_handle h_, const char* f, double by = 0, double fl = 0)
       : h(h_), fam(f), bytes(by), flops(fl) {
-    if (h->prof) {
+    if (h->prof && (h->prof_only.empty() || h->prof_only.count(f))) {
       a = get_event(h);
       b = get_event(h);
       if (a) (void)hipEventRecord(a, h->stream);
     }
   }
   ~ProfScope() {
-    if (h->prof && a && b) {
+    if (a && b) {
       (void)hipEventRecord(b, h->stream);
       h->pending.push_back({fam, a, b, bytes, flops});
     }
@@ -655,6 +657,25 @@ psdp_status psdp_profile_enable(psdp_handle h, int on) {
   prof_collect(h);
   h->prof_tab.clear();
   h->prof = on != 0;
+  return PSDP_OK;
+}
+
+psdp_status psdp_profile_filter(psdp_handle h, const char* families) {
+  if (!h) return PSDP_ERR_INVALID_ARG;
+  prof_collect(h);
+  h->prof_only.clear();
+  if (families) {
+    std::string cur;
+    for (const char* c = families;; ++c) {
+      if (*c == ',' || *c == '\0') {
+        if (!cur.empty()) h->prof_only.insert(cur);
+        cur.clear();
+        if (*c == '\0') break;
+      } else if (*c != ' ') {
+        cur += *c;
+      }
+    }
+  }
   return PSDP_OK;
 }
 
