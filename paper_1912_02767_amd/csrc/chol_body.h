@@ -82,6 +82,21 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   State* st = a.st;
   const int tid = threadIdx.x;
   const int m = a.m;
+  if (a.spec_m > 0) {
+    // queued before the previous iteration was read back: a no-op unless that
+    // iteration kept running with the assumed block size.  One thread reads
+    // the state and the workgroup takes its verdict, before any thread can
+    // change the state.
+    if (tid == 0) {
+      const int stop0 = st->stop;
+      s_stop = (stop0 != kRunning) ? 1 : (st->mk != a.spec_m ? 2 : 0);
+      if (s_stop == 2) st->stop = kSpecAbort;
+    }
+    __syncthreads();
+    const int verdict = s_stop;
+    __syncthreads();
+    if (verdict != 0) return;
+  }
   if (tid == 0 && a.mode != -1) st->t_phase[5] = wall_clock64();
 
   if (a.mode == kModeFull || a.mode == kModeXR || a.mode == kModeEval) {

@@ -22,6 +22,7 @@ enum StopReason : int {
   kNonFinite = 4,
   kBreakdown = 5,  // trial basis lost rank beyond recovery
   kEvaluated = 6,  // evaluation pass only (statistics of the current block)
+  kSpecAbort = 7,  // a speculatively queued iteration found the block size changed
 };
 
 // Composition of the trial basis of one iteration.
@@ -190,6 +191,8 @@ struct DecideArgs {
   int nz;               // expansion columns (mode XZ)
   int has_p;
   int phase_lowprec;    // product precision of the phase: 0 FP64, 1 FP32, 2 BF16
+  int spec_m;           // > 0: queued before the previous iteration was read back,
+                        // assuming it kept running with block size spec_m
   double tau;           // dropping threshold on the scaled pivot
   const double* bases[5];  // X, R, P, Z, S1 column bases
   int ld;               // leading dim of the bases
@@ -272,5 +275,7 @@ hipError_t launch_fill_normal(double* B, int ld, int n, int col0, int cols, uint
                               uint64_t stream_id, hipStream_t st);
 hipError_t launch_copy_cols(const double* src, int lds, double* dst, int ldd, int n, int cols,
                             hipStream_t st);
+// st->stop = v (one thread)
+hipError_t launch_set_stop(State* st, int v, hipStream_t s);
 
 }  // namespace psdp

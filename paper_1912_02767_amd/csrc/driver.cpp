@@ -127,6 +127,9 @@ struct psdp_handle_s {
   std::map<std::string, ProfEntry> prof_tab;
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> event_pool;
+  hipEvent_t sync_ev = nullptr;  // polled by spin_wait
+  State* h_snap = nullptr;         // two pinned state snapshots of queued iterations
+  hipEvent_t snap_ev[2] = {nullptr, nullptr};
   psdp::BatchEngine* batch = nullptr;
   char* beig = nullptr;  // batched exact path scratch
   size_t beig_bytes = 0;
@@ -142,14 +145,39 @@ namespace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Waits for the work queued on s by polling an event: the host sees the end
+// of a short iteration within microseconds, where a blocking wait can sleep
+// for tens of them before the next launches are queued.
+hipError_t spin_wait(psdp_handle h, hipStream_t s) {
+  if (!h->sync_ev && hipEventCreateWithFlags(&h->sync_ev, hipEventDisableTiming) != hipSuccess) {
+    h->sync_ev = nullptr;
+    return hipStreamSynchronize(s);
+  }
+  hipError_t e = hipEventRecord(h->sync_ev, s);
+  if (e != hipSuccess) return e;
+  while ((e = hipEventQuery(h->sync_ev)) == hipErrorNotReady) {
+  }
+  return e;
+}
+
+// Polls an already recorded event.
+hipError_t spin_event(hipEvent_t ev) {
+  hipError_t e;
+  while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+  }
+  return e;
+}
+
 hipEvent_t get_event(psdp_handle h) {
   if (!h->event_pool.empty()) {
     hipEvent_t e = h->event_pool.back();
     h->event_pool.pop_back();
     return e;
   }
+  // timing only: no system-scope fence (cache write-back and invalidation)
+  // when the event is recorded, which would stall the following launches
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -311,18 +339,18 @@ struct Solver {
 
   psdp_status read_state() {
     HIP_TRY(hipMemcpyAsync(hs, w.st, sizeof(State), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(spin_wait(h, s));
     return PSDP_OK;
   }
 
   // Algorithmic bytes / flops of this iteration's launches, attributed once
   // the device-side widths are known (after the state readback).
-  void attribute(size_t first, int Ng, int pprec) {
+  void attribute(size_t first, size_t last, int Ng, int pprec) {
     if (!h->prof) return;
     const State& st = *hs;
     const double nn = n, N = st.N > 0 ? st.N : Ng, N1 = st.Np1, N2 = st.Np, mk = st.mk;
     int gram_i = 0, chol_i = 0, tsmm_i = 0;
-    for (size_t i = first; i < h->pending.size(); ++i) {
+    for (size_t i = first; i < last && i < h->pending.size(); ++i) {
       PendingEvent& p = h->pending[i];
       if (p.family == "gram") {
         double c = (gram_i == 0) ? Ng : (gram_i == 1 ? N1 : N2);
@@ -358,11 +386,46 @@ struct Solver {
     }
   }
 
-  // one Rayleigh-Ritz iteration on the trial basis given by `mode`
+  // An iteration whose launches are queued and whose state snapshot is not
+  // read yet.  spec_m > 0: queued before the previous iteration was read back,
+  // assuming it kept running with block size spec_m; its decision kernel
+  // turns it into no-ops otherwise.
+  struct Queued {
+    int mode = 0, pprec = 0, Ng = 0, want_p = 0, spec_m = 0, slot = 0;
+    size_t ev_begin = 0, ev_end = 0;
+  };
+  int next_slot = 0;
+
+  psdp_status ensure_snapshots() {
+    if (!h->h_snap) {
+      if (hipHostMalloc((void**)&h->h_snap, 2 * sizeof(State), hipHostMallocDefault) != hipSuccess) {
+        h->h_snap = nullptr;
+        return PSDP_ERR_OUT_OF_MEMORY;
+      }
+    }
+    for (auto& e : h->snap_ev)
+      if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return PSDP_OK;
+  }
+
+  // one Rayleigh-Ritz iteration on the trial basis given by `mode`, queued
+  // and read back
   psdp_status iterate(int mode, int pprec, int mtarget, int nz) {
+    Queued q;
+    psdp_status r = enqueue(mode, pprec, mtarget, nz, 0, q);
+    if (r != PSDP_OK) return r;
+    return complete(q);
+  }
+
+  // the launches of one iteration, then the state snapshot into a pinned slot
+  psdp_status enqueue(int mode, int pprec, int mtarget, int nz, int spec_m, Queued& q) {
+    psdp_status pr = ensure_snapshots();
+    if (pr != PSDP_OK) return pr;
     const int L = w.L, NC = w.NC;
     const size_t first_ev = h->pending.size();
     const int* stop = &w.st->stop;
+    const int* stop_first = spec_m > 0 ? stop : nullptr;  // a speculative Gram skips when stopped
+    const int hp = (mode == kModeFull) ? 1 : (mode == kModeXR ? 0 : has_p);
     // ---- Gram of the candidate columns (gives residual norms too)
     ColMap cand;
     int Ng;
@@ -373,21 +436,21 @@ struct Solver {
       cand = colmap_seg(w.X, m, L, w.Z, nz);
       Ng = m + nz;
     } else {
-      cand = colmap_seg(w.X, m, L, w.R, m, has_p ? w.P : nullptr, has_p ? m : 0);
-      Ng = has_p ? 3 * m : 2 * m;
+      cand = colmap_seg(w.X, m, L, w.R, m, hp ? w.P : nullptr, hp ? m : 0);
+      Ng = hp ? 3 * m : 2 * m;
     }
     int nblk = 0;
     {
       ProfScope ps(h, "gram");
       HIP_TRY(launch_gram_partial(cand, nullptr, nullptr, Ng, nullptr, Ng, n, w.Gpart, NC,
-                                  (size_t)NC * NC, &nblk, nullptr, s));
+                                  (size_t)NC * NC, &nblk, stop_first, s));
       HIP_TRY(launch_reduce_partials(w.Gpart, nblk, (size_t)NC * NC, NC, nullptr, Ng, nullptr, Ng,
-                                     w.G, NC, nullptr, s));
+                                     w.G, NC, stop_first, s));
     }
     // ---- decisions + first Cholesky-QR pass
     DecideArgs da{};
     da.G = w.G; da.ldg = NC; da.Ng = Ng; da.mode = mode; da.m = m; da.nz = nz;
-    da.has_p = has_p; da.phase_lowprec = pprec; da.tau = 1e-10;
+    da.has_p = hp; da.phase_lowprec = pprec; da.tau = 1e-10; da.spec_m = spec_m;
     da.bases[0] = w.X; da.bases[1] = w.R; da.bases[2] = w.P; da.bases[3] = w.Z; da.bases[4] = w.S1;
     da.ld = L; da.T = w.T; da.ldt = NC; da.colptr = w.colptr; da.st = w.st;
     int Nmax = Ng;  // upper bound on the trial width
@@ -410,6 +473,7 @@ struct Solver {
                                      &w.st->Np, Nmax, w.G, NC, stop, s));
     }
     DecideArgs db = da;
+    db.spec_m = 0;
     db.mode = -1;  // second pass: the candidate count is st->Np on the device
     db.Ng = Nmax;
     {
@@ -469,8 +533,33 @@ struct Solver {
       HIP_TRY(launch_update(w.S2, w.AS, L, w.C, NC, w.st, want_p, n, std::min(mtarget, Nmax),
                             w.X, w.AX, w.P, w.R, L, s));
     }
-    psdp_status rs = read_state();
-    if (rs != PSDP_OK) return rs;
+    q.mode = mode; q.pprec = pprec; q.Ng = Ng; q.want_p = want_p; q.spec_m = spec_m;
+    q.slot = next_slot;
+    next_slot ^= 1;
+    q.ev_begin = first_ev;
+    q.ev_end = h->pending.size();
+    HIP_TRY(hipMemcpyAsync(h->h_snap + q.slot, w.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(h->snap_ev[q.slot], s));
+    return PSDP_OK;
+  }
+
+  // drops a queued iteration that will not be read back (its timing events
+  // are not accumulated)
+  void discard(const Queued& q) {
+    for (size_t i = q.ev_begin; i < q.ev_end && i < h->pending.size(); ++i) {
+      h->event_pool.push_back(h->pending[i].a);
+      h->event_pool.push_back(h->pending[i].b);
+    }
+    if (q.ev_end <= h->pending.size() && q.ev_begin < q.ev_end)
+      h->pending.erase(h->pending.begin() + q.ev_begin, h->pending.begin() + q.ev_end);
+  }
+
+  // waits for a queued iteration's snapshot, mirrors it and updates the block
+  psdp_status complete(const Queued& q) {
+    const int mode = q.mode, pprec = q.pprec, Ng = q.Ng, want_p = q.want_p;
+    const size_t first_ev = q.ev_begin;
+    HIP_TRY(spin_event(h->snap_ev[q.slot]));
+    std::memcpy(hs, h->h_snap + q.slot, sizeof(State));
     if (h->trace) {
       double ph[4], pc[5];
       for (int q = 0; q < 4; ++q) ph[q] = (hs->t_phase[q + 1] - hs->t_phase[q]) * 1e-2;  // us
@@ -502,10 +591,10 @@ struct Solver {
       }
     }
     if (hs->stop == kRunning || mode == kModeXOnly || mode == kModeXZ) {
-      attribute(first_ev, Ng, pprec);
+      attribute(first_ev, q.ev_end, Ng, pprec);
     } else if (h->prof) {
       // stopped after the decision pass: only the first Gram and decision ran
-      for (size_t i = first_ev; i < h->pending.size(); ++i) {
+      for (size_t i = first_ev; i < q.ev_end && i < h->pending.size(); ++i) {
         PendingEvent& p = h->pending[i];
         if (p.family == "gram" && p.bytes == 0) { p.bytes = 8.0 * n * Ng; p.flops = (double)n * Ng * Ng; }
         if (p.family == "chol" && p.flops == 0) { p.flops = 2.0 * Ng * Ng * (double)Ng / 3.0; p.bytes = 16.0 * Ng * Ng; }
@@ -634,6 +723,9 @@ psdp_status psdp_destroy(psdp_handle h) {
   (void)hipStreamSynchronize(h->stream);
   prof_collect(h);
   for (auto e : h->event_pool) hipEventDestroy(e);
+  if (h->sync_ev) hipEventDestroy(h->sync_ev);
+  for (auto e : h->snap_ev) if (e) hipEventDestroy(e);
+  if (h->h_snap) hipHostFree(h->h_snap);
   if (h->ws.base) hipFree(h->ws.base);
   if (h->eig_A) hipFree(h->eig_A);
   if (h->h_state) hipHostFree(h->h_state);
@@ -1193,13 +1285,43 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     return PSDP_OK;
   };
   int guard_calls = 0;
+  // The loop keeps one iteration queued ahead: while the host reads back
+  // iteration t, iteration t + 1 (full trial basis, same block size and
+  // product precision) is already on the stream.  Its decision kernel makes
+  // it a no-op when t stopped or changed the block size; the host then drops
+  // it (and after a size change clears the abort flag).
+  Solver::Queued cur, nxt;
+  bool have_cur = false;
+  auto drop_next = [&](bool have, const Solver::Queued& q, bool clear_abort) -> psdp_status {
+    if (!have) return PSDP_OK;
+    sv.discard(q);
+    if (clear_abort) HIP_TRY(launch_set_stop(w.st, kRunning, s));
+    return PSDP_OK;
+  };
   while (!finished) {
     if (++guard_calls > 4 * opt.max_iter + 64) break;  // hard bound on host steps
-    int mode = sv.has_p ? kModeFull : kModeXR;
-    rc = sv.iterate(mode, phase, sv.m, 0);
+    if (!have_cur) {
+      int mode = sv.has_p ? kModeFull : kModeXR;
+      rc = sv.enqueue(mode, phase, sv.m, 0, 0, cur);
+      if (rc != PSDP_OK) { info->status = rc; return rc; }
+    }
+    have_cur = false;
+    // h_state is still the snapshot before `cur`: two more iterations fit
+    bool have_nxt = false;
+    if (h->h_state->iter + 2 <= opt.max_iter) {
+      rc = sv.enqueue(kModeFull, phase, sv.m, 0, sv.m, nxt);
+      if (rc != PSDP_OK) { info->status = rc; return rc; }
+      have_nxt = true;
+    }
+    rc = sv.complete(cur);
     if (rc != PSDP_OK) { info->status = rc; return rc; }
     const State& st = *h->h_state;
     int stop = st.stop;
+    if (stop != kRunning) {
+      // the queued iteration found `stop` set and did nothing
+      drop_next(have_nxt, nxt, false);
+      have_nxt = false;
+    }
     if (stop == kNonFinite) { info->status = PSDP_ERR_NUMERICAL; return PSDP_ERR_NUMERICAL; }
     if (stop == kBreakdown) {
       if (opt.fallback_full) { fell_back = 1; break; }
@@ -1268,8 +1390,17 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       continue;
     }
     if (st.iter >= opt.max_iter) {
+      drop_next(have_nxt, nxt, true);
       finished = true;
       break;
+    }
+    if (have_nxt) {
+      if (sv.m == nxt.spec_m && sv.has_p) {
+        cur = nxt;  // the queued iteration is the next one
+        have_cur = true;
+      } else {
+        drop_next(true, nxt, true);  // it aborted on the block size
+      }
     }
   }
   if (fell_back || (!converged && opt.fallback_full)) {

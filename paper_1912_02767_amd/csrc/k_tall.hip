@@ -549,6 +549,15 @@ hipError_t launch_reduce_partials(const double* part, int nblk, size_t part_stri
   return hipGetLastError();
 }
 
+__global__ void k_set_stop(State* st, int v) {
+  if (threadIdx.x == 0) st->stop = v;
+}
+
+hipError_t launch_set_stop(State* st, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_stop, dim3(1), dim3(64), 0, s, st, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_tsmm(const ColMap& src, const int* kk_dev, int kk_host, const int* q_dev,
                        int q_host, const double* M, int ldm, int n, double* Y, int ldy,
                        const int* stop, hipStream_t st) {
