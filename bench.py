@@ -166,9 +166,11 @@ def run_sequence(args, torch, psdp):
     Xs = [torch.from_numpy(np.asfortranarray(X)).to(dev) for X in mats]
     torch.cuda.synchronize()
     if big:
-        # sqrt(2 m~) tol <= 1e-7 ||Pi||; ||Pi_0||_F from the construction
+        # the metric asks for rel err <= 1e-6: the residual part of the
+        # bound, sqrt(2 m~) tol, is held to args.bound_rel ||Pi|| (default
+        # 5e-7, half the requirement); ||Pi_0||_F from the construction
         nrm_pi0 = float(np.linalg.norm(np.maximum(lam0, 0)))
-        tol = 1e-7 * nrm_pi0 / math.sqrt(2 * p)
+        tol = args.bound_rel * nrm_pi0 / math.sqrt(2 * p)
         m_cap, block = 48, 48
     else:
         tol, m_cap, block = 1e-8, 24, 24
@@ -267,6 +269,7 @@ def run_sequence(args, torch, psdp):
         "value": value, "steps": steps, "warmup": warm, "ms_per_step": 1e3 * wall / steps,
         "dtype": prec,
         "config": {"workload": wl, "n": n, "n_pos": p, "block": block, "tol": tol,
+                   "bound_rel_target": args.bound_rel if big else None,
                    "matrices": len(mats), "products": prec, "ortho_rr_refine": "fp64"},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
@@ -511,6 +514,9 @@ def main():
     ap.add_argument("--full-eig-samples", type=int, default=None)
     ap.add_argument("--oracle-samples", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--bound-rel", type=float, default=5e-7,
+                    help="n = 4000 workloads: residual part of the error bound held below this "
+                         "fraction of ||Pi||_F (the metric's accuracy is 1e-6)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
 
