@@ -130,6 +130,77 @@ __device__ inline void twisted_vector(const double* d, const double* e, const do
   y[r] = 1.0;
 }
 
+// The twisted factorization split over two threads of a vector: the
+// top-down pivots D+ (into y) and the bottom-up pivots D- (into w) run at
+// once; then both threads find the twist and build the two halves of the
+// vector (the same values as twisted_vector).
+__device__ inline void twisted_top(const double* d, const double* e2, int N, double sigma,
+                                   double pfloor, double* y) {
+  double dp = d[0] - sigma;
+  if (fabs(dp) < pfloor) dp = -pfloor;
+  y[0] = dp;
+  int i = 1;
+  for (; i + 3 < N; i += 4) {
+    const double d0 = d[i] - sigma, d1 = d[i + 1] - sigma, d2 = d[i + 2] - sigma, d3 = d[i + 3] - sigma;
+    const double f0 = e2[i - 1], f1 = e2[i], f2 = e2[i + 1], f3 = e2[i + 2];
+    dp = tw_piv(d0, f0, dp, pfloor); y[i] = dp;
+    dp = tw_piv(d1, f1, dp, pfloor); y[i + 1] = dp;
+    dp = tw_piv(d2, f2, dp, pfloor); y[i + 2] = dp;
+    dp = tw_piv(d3, f3, dp, pfloor); y[i + 3] = dp;
+  }
+  for (; i < N; ++i) { dp = tw_piv(d[i] - sigma, e2[i - 1], dp, pfloor); y[i] = dp; }
+}
+
+__device__ inline void twisted_bottom(const double* d, const double* e2, int N, double sigma,
+                                      double pfloor, double* w) {
+  double dm = d[N - 1] - sigma;
+  if (fabs(dm) < pfloor) dm = -pfloor;
+  w[N - 1] = dm;
+  int i = N - 2;
+  for (; i - 3 >= 0; i -= 4) {
+    const double d0 = d[i] - sigma, d1 = d[i - 1] - sigma, d2 = d[i - 2] - sigma, d3 = d[i - 3] - sigma;
+    const double f0 = e2[i], f1 = e2[i - 1], f2 = e2[i - 2], f3 = e2[i - 3];
+    dm = tw_piv(d0, f0, dm, pfloor); w[i] = dm;
+    dm = tw_piv(d1, f1, dm, pfloor); w[i - 1] = dm;
+    dm = tw_piv(d2, f2, dm, pfloor); w[i - 2] = dm;
+    dm = tw_piv(d3, f3, dm, pfloor); w[i - 3] = dm;
+  }
+  for (; i >= 0; --i) { dm = tw_piv(d[i] - sigma, e2[i], dm, pfloor); w[i] = dm; }
+}
+
+// twist index: the smallest |gamma_i| = |D+_i + D-_i - (d_i - sigma)|, the
+// last row first and the larger index kept on ties
+__device__ inline int twisted_index(const double* d, int N, double sigma, const double* y,
+                                   const double* w) {
+  int r = N - 1;
+  double gbest = fabs(y[N - 1]);
+  for (int i = N - 2; i >= 0; --i) {
+    const double di = d[i] - sigma;
+    const double g = fabs(y[i] + w[i] - di);
+    if (g < gbest) { gbest = g; r = i; }
+  }
+  return r;
+}
+
+// z_r = 1; upward through L (D+ in y), written over y
+__device__ inline void twisted_up(const double* e, int r, double* y) {
+  double z = 1.0;
+  for (int i = r - 1; i >= 0; --i) {
+    z = -fast_div(e[i], y[i]) * z;
+    y[i] = z;
+  }
+  y[r] = 1.0;
+}
+
+// downward through U (D- in w), into y below the twist
+__device__ inline void twisted_down(const double* e, int N, int r, const double* w, double* y) {
+  double z = 1.0;
+  for (int i = r + 1; i < N; ++i) {
+    z = -fast_div(e[i - 1], w[i]) * z;
+    y[i] = z;
+  }
+}
+
 // a / b with the reciprocal estimate refined by one Newton step (relative
 // error about 1e-14: the counts below are those of a matrix whose squared
 // off-diagonal entries are perturbed by that much)
@@ -799,6 +870,13 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
 
   // ---- 1. tridiagonalization (matrix in registers)
   tridiag_reg<NBR, NBC, NT>(a, N, P, d, e, tau, tbuf, red);
+  if (EXPORT) {
+    // reflectors and tau to the global scratch for the back-transformation
+    // kernel; the reflector region is free for the vectors' D- afterwards
+    const size_t n2 = (size_t)N * (N + 1) / 2;
+    for (size_t x = tid; x < n2; x += nt) a.scratch[x] = P[x];
+    for (int x = tid; x < N; x += nt) a.scratch[n2 + x] = tau[x];
+  }
   // e^2, and in one parallel pass the row-sum norm ||T||, max e^2 and the
   // Gershgorin interval (max / min reductions: the same values as a serial loop)
   double s_gl, s_gu;
@@ -951,16 +1029,52 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
   // ---- 3. eigenvectors: twisted factorization, one thread per vector
   const double pfloor = fmax(2.2e-16 * tnorm, 1e-300);
   const double ortol = 1e-3 * tnorm;
-  for (int j = tid; j < mk; j += nt) {
+  if (EXPORT && mk <= 64 && nt >= 128 && 2 * mk <= N + 1) {
+    // wave 0 forms the top-down pivots of vector `lane`, wave 1 its
+    // bottom-up pivots (D- in the reflector region, exported already, which
+    // holds N (N + 1) / 2 >= mk N doubles); both
+    // find the twist, then wave 0 builds the part above it and wave 1 the
+    // part below
+    const int j = lane, half = wv;
+    const bool act = wv < 2 && j < mk;
+    const double sigma = act ? 0.5 * (s_lo[j] + s_hi[j]) : 0.0;
+    double* y = Y + (size_t)min(j, mk - 1) * ldy;
+    double* dmv = P + (size_t)min(j, mk - 1) * N;
+    if (act) {
+      if (N == 1) {
+        if (half == 0) y[0] = 1.0;
+      } else if (half == 0) {
+        twisted_top(d, e2, N, sigma, pfloor, y);
+      } else {
+        twisted_bottom(d, e2, N, sigma, pfloor, dmv);
+      }
+    }
+    __syncthreads();
+    const int r = (act && N > 1) ? twisted_index(d, N, sigma, y, dmv) : 0;
+    __syncthreads();  // every twist is known before either part is written
+    if (act && N > 1) {
+      if (half == 0)
+        twisted_up(e, r, y);
+      else
+        twisted_down(e, N, r, dmv, y);
+    }
+  } else {
+    for (int j = tid; j < mk; j += nt)
+      twisted_vector(d, e, e2, N, 0.5 * (s_lo[j] + s_hi[j]), pfloor, Y + (size_t)j * ldy);
+  }
+  __syncthreads();
+  // normalization, one wave per vector: scaled by the largest entry first
+  for (int j = wv; j < mk; j += nt / 64) {
     double* y = Y + (size_t)j * ldy;
-    twisted_vector(d, e, e2, N, 0.5 * (s_lo[j] + s_hi[j]), pfloor, y);
     double mx = 0.0;
-    for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(y[i]));
+    for (int i = lane; i < N; i += 64) mx = fmax(mx, fabs(y[i]));
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
     const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
     double nn = 0.0;
-    for (int i = 0; i < N; ++i) { const double v = y[i] * sc; y[i] = v; nn += v * v; }
+    for (int i = lane; i < N; i += 64) { const double v = y[i] * sc; nn += v * v; }
+    nn = wave_sum(nn);
     const double inv = 1.0 / sqrt(nn);
-    for (int i = 0; i < N; ++i) y[i] *= inv;
+    for (int i = lane; i < N; i += 64) y[i] = (y[i] * sc) * inv;
   }
   __syncthreads();
   if (tid == 0) t_mgs = wall_clock64();
@@ -1023,29 +1137,23 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
     }
   }
   if (tid == 0) st->t_sub[7] = wall_clock64() - t_mgs;
-  // Rayleigh quotients y^T T y
-  for (int j = tid; j < mk; j += nt) {
+  // Rayleigh quotients y^T T y, one wave per vector
+  for (int j = wv; j < mk; j += nt / 64) {
     const double* y = Y + (size_t)j * ldy;
     double rq = 0.0;
-    for (int i = 0; i < N; ++i) {
+    for (int i = lane; i < N; i += 64) {
       double ty = d[i] * y[i];
       if (i > 0) ty += e[i - 1] * y[i - 1];
       if (i + 1 < N) ty += e[i] * y[i + 1];
       rq += y[i] * ty;
     }
-    pv[j] = rq;
+    rq = wave_sum(rq);
+    if (lane == 0) pv[j] = rq;
   }
   __syncthreads();
   if (tid == 0) st->t_phase[3] = wall_clock64();
 
-  if (EXPORT) {
-    // reflectors and tau to the global scratch for the back-transformation kernel
-    const size_t n2 = (size_t)N * (N + 1) / 2;
-    for (size_t x = tid; x < n2; x += nt) a.scratch[x] = P[x];
-    for (int x = tid; x < N; x += nt) a.scratch[n2 + x] = tau[x];
-  } else {
-    wy_back<NT, NBC, 4>(N, P, tau, Y, ldy, mk, Tb, Wb, st);
-  }
+  if (!EXPORT) wy_back<NT, NBC, 4>(N, P, tau, Y, ldy, mk, Tb, Wb, st);
   if (tid == 0) st->t_phase[4] = wall_clock64();
   // ---- outputs: C = Z (N x mk), Ritz values descending
   for (int x = tid; x < N * mk; x += nt) {
