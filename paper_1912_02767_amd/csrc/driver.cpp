@@ -69,7 +69,7 @@ using namespace psdp;
 namespace {
 
 constexpr int kMaxSweeps = 40;
-constexpr int kProductSlices = 8;
+constexpr int kProductSlices = 16;
 
 struct ProfEntry {
   long launches = 0;

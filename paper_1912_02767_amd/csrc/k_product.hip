@@ -281,11 +281,13 @@ hipError_t launch_product(const ProductArgs& a, hipStream_t st) {
                        a.lds % 2 == 0 && a.lds >= a.lda && !g_force_ref;
   if (mfma_ok) {
     const int rt = (a.n + 63) / 64;
-    // K slices: about two workgroups per compute unit, slices a multiple of
-    // the staging chunk (128 covers every precision)
-    int sk = std::max(1, std::min((512 + rt - 1) / rt, a.n / 256));
+    // K slices: up to two resident workgroups per compute unit (512), each
+    // slice at least two staging chunks of the precision and a multiple of
+    // one (small n: more slices fill the device)
+    const int kc = a.prec == 0 ? PCfg<0>::KC : (a.prec == 1 ? PCfg<1>::KC : PCfg<2>::KC);
+    int sk = std::max(1, std::min(512 / rt, a.n / (2 * kc)));
     sk = std::min(sk, a.max_slices);
-    const int kslice = ((a.n + sk - 1) / sk + 127) / 128 * 128;
+    const int kslice = ((a.n + sk - 1) / sk + kc - 1) / kc * kc;
     sk = (a.n + kslice - 1) / kslice;
     const size_t pstride = (size_t)a.lda * a.cols_max;
     const size_t elem = a.prec == 0 ? 8 : 4;
