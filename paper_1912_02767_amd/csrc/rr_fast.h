@@ -549,6 +549,41 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
   __syncthreads();
 }
 
+// tridiag_reg on the smallest thread-grid blocking that covers N: the work
+// of a step is issue-bound (every thread updates its whole block), so a
+// trial basis well below the kernel's largest order takes a smaller block
+// per thread.  The choice is uniform (N from the device state).
+template <int NBR, int NBC, int NT>
+__device__ inline void tridiag_fit(const RRArgs& a, int N, double* P, double* d, double* e,
+                                   double* tau, double* buf, double* red) {
+  constexpr int RG = NT / 16;
+  if constexpr (NBR >= 3 && NBC >= 3 && (NBR > 3 || NBC > 3)) {
+    if (N <= 3 * RG && N <= 48) {
+      tridiag_reg<3, 3, NT>(a, N, P, d, e, tau, buf, red);
+      return;
+    }
+  }
+  if constexpr (NBR >= 4 && NBC >= 4 && (NBR > 4 || NBC > 4)) {
+    if (N <= 4 * RG && N <= 64) {
+      tridiag_reg<4, 4, NT>(a, N, P, d, e, tau, buf, red);
+      return;
+    }
+  }
+  if constexpr (NBR >= 3 && NBC >= 6 && (NBR > 3 || NBC > 6)) {
+    if (N <= 3 * RG && N <= 96) {
+      tridiag_reg<3, 6, NT>(a, N, P, d, e, tau, buf, red);
+      return;
+    }
+  }
+  if constexpr (NBR >= 4 && NBC >= 8 && (NBR > 4 || NBC > 8)) {
+    if (N <= 4 * RG && N <= 128) {
+      tridiag_reg<4, 8, NT>(a, N, P, d, e, tau, buf, red);
+      return;
+    }
+  }
+  tridiag_reg<NBR, NBC, NT>(a, N, P, d, e, tau, buf, red);
+}
+
 // Back-transformation Z = H_0 H_1 ... H_{N-3} Y by blocks of
 // reflectors, last block first, on ncols <= 16 (NTQ - 1) columns of Y:
 // Y <- (I - V T V^T) Y with V the block's reflectors (unit at row k + 1,
@@ -869,7 +904,7 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
   if (tid == 0) st->t_phase[0] = wall_clock64();
 
   // ---- 1. tridiagonalization (matrix in registers)
-  tridiag_reg<NBR, NBC, NT>(a, N, P, d, e, tau, tbuf, red);
+  tridiag_fit<NBR, NBC, NT>(a, N, P, d, e, tau, tbuf, red);
   if (EXPORT) {
     // reflectors and tau to the global scratch for the back-transformation
     // kernel; the reflector region is free for the vectors' D- afterwards
