@@ -1021,31 +1021,42 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
     __syncthreads();
     const int per = max(1, nt / max(mk, 1));  // shifts per eigenvalue per round
     const int j_me = tid / per, s_me = tid % per;
+    // shift s of a bracket [lo, hi]: lo + (hi - lo) (s + 1) rp; the counts
+    // and the bracket update use this same expression
+    const double rp = 1.0 / (double)(per + 1);
     int rounds = 1;
     for (int round = 0; round < 64; ++round) {
-      bool any = false;
-      for (int q = 0; q < nt / 64; ++q) any = any || oflag[q] != 0;
-      if (!any) break;
+      int anyi = 0;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) anyi |= oflag[q];
+      if (anyi == 0) break;
       ++rounds;
       if (j_me < mk) {
         const double lo = s_lo[j_me], hi = s_hi[j_me];
-        const double x = lo + (hi - lo) * (double)(s_me + 1) / (double)(per + 1);
+        const double x = lo + (hi - lo) * ((double)(s_me + 1) * rp);
         cnts[tid] = sturm_count_fast(dsc, e2sc, d, e2, N, x, tsh, pivmin);
       }
       __syncthreads();
-      // new bracket: the first shift whose count exceeds the target (all
-      // counts loaded before the selects, no early exit)
+      // new bracket: the first shift whose count exceeds the target (counts
+      // loaded 16 at a time ahead of the selects, no early exit)
       open = false;
       if (tid < mk) {
         const int j = tid;
         const int target = N - 1 - j;  // ascending index of the j-th largest
         const double lo = s_lo[j], hi = s_hi[j];
         int first = per;
-        for (int s2 = per - 1; s2 >= 0; --s2) first = (cnts[j * per + s2] > target) ? s2 : first;
-        const double nlo =
-            (first > 0) ? lo + (hi - lo) * (double)first / (double)(per + 1) : lo;
-        const double nhi =
-            (first < per) ? lo + (hi - lo) * (double)(first + 1) / (double)(per + 1) : hi;
+        for (int s0 = 0; s0 < per; s0 += 16) {
+          int cv[16];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) cv[u] = cnts[j * per + min(s0 + u, per - 1)];
+#pragma unroll
+          for (int u = 0; u < 16; ++u) {
+            const int s2 = s0 + u;
+            first = (s2 < first && s2 < per && cv[u] > target) ? s2 : first;
+          }
+        }
+        const double nlo = (first > 0) ? lo + (hi - lo) * ((double)first * rp) : lo;
+        const double nhi = (first < per) ? lo + (hi - lo) * ((double)(first + 1) * rp) : hi;
         s_lo[j] = nlo;
         s_hi[j] = nhi;
         open = bracket_open(nlo, nhi, tnorm, pivmin);
