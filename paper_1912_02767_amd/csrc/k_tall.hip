@@ -249,57 +249,74 @@ constexpr int kTR = 64;
 constexpr int kTQ = 16;
 constexpr int kTK = 32;
 
+constexpr int kTGroup = 5;  // chunks whose loads are issued together (kk <= 160 in one group)
+
 __device__ inline void tsmm_tile(const ColMap& src, int kk, int q,
                                  const double* __restrict__ M, int ldm, int n,
                                  double* __restrict__ Y, int ldy, int row0, int col0,
-                                 double (*sS)[kTR + 1], double (*sM)[kTQ + 1]) {
+                                 double (*sS)[kTR + 1], double (*sM)[kTQ + 1],
+                                 const double** sp) {
   // 256 threads: thread -> (row r = tid % 64, col group cg = tid / 64 -> 4 cols)
   const int r = threadIdx.x % kTR;
   const int cg = threadIdx.x / kTR;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   // per chunk: 32 source columns x 64 rows (8 values per thread) and 32 x 16
-  // of M (2 per thread); the next chunk's loads are in flight during the FMAs
+  // of M (2 per thread).  The loads of a whole group of chunks (the full
+  // trial basis in one group) are issued before the first chunk is used:
+  // one global-memory round trip instead of one per chunk.
   constexpr int PS = kTK * kTR / 256, PM = kTK * kTQ / 256;
-  double cs[PS], cm[PM];
-  auto load_chunk = [&](int k0) {
-#pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int rr = e % kTR, kc = e / kTR;
-      const int row = row0 + rr, k = k0 + kc;
-      const double v = src.col(min(k, kk - 1))[min(row, n - 1)];
-      cs[u] = (row < n && k < kk) ? v : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < PM; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int kc = e % kTK, c = e / kTK;
-      const int k = k0 + kc, j = col0 + c;
-      const double v = M[min(k, kk - 1) + (size_t)min(j, q - 1) * ldm];
-      cm[u] = (k < kk && j < q) ? v : 0.0;
-    }
-  };
-  if (kk > 0) load_chunk(0);
-  for (int k0 = 0; k0 < kk; k0 += kTK) {
-#pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      sS[e / kTR][e % kTR] = cs[u];
-    }
-#pragma unroll
-    for (int u = 0; u < PM; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      sM[e % kTK][e / kTK] = cm[u];
-    }
+  double cs[kTGroup][PS], cm[kTGroup][PM];
+  // column pointers of the group in LDS (sp[k - g0]): resolving a column
+  // inside the load loop would put a dependent pointer load and a branch in
+  // front of every element.  Every load of the group is unconditional (indices
+  // clamped); the zero padding is applied when the values reach LDS.
+  typedef const __attribute__((address_space(1))) double* gptr;
+  for (int g0 = 0; g0 < kk; g0 += kTGroup * kTK) {
+    for (int k = g0 + (int)threadIdx.x; k < min(kk, g0 + kTGroup * kTK); k += 256)
+      sp[k - g0] = src.col(k);
     __syncthreads();
-    if (k0 + kTK < kk) load_chunk(k0 + kTK);
+#pragma unroll
+    for (int c = 0; c < kTGroup; ++c) {
+      const int k0 = g0 + c * kTK;
+#pragma unroll
+      for (int u = 0; u < PS; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int rr = e % kTR, kc = e / kTR;
+        const int k = min(k0 + kc, kk - 1);
+        cs[c][u] = ((gptr)sp[k - g0])[min(row0 + rr, n - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < PM; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int kc = e % kTK, cc = e / kTK;
+        cm[c][u] = M[min(k0 + kc, kk - 1) + (size_t)min(col0 + cc, q - 1) * ldm];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kTGroup; ++c) {
+      const int k0 = g0 + c * kTK;
+      if (k0 >= kk) break;  // uniform
+#pragma unroll
+      for (int u = 0; u < PS; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int rr = e % kTR, kc = e / kTR;
+        sS[kc][rr] = (row0 + rr < n && k0 + kc < kk) ? cs[c][u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PM; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int kc = e % kTK, cc = e / kTK;
+        sM[kc][cc] = (k0 + kc < kk && col0 + cc < q) ? cm[c][u] : 0.0;
+      }
+      __syncthreads();
 #pragma unroll 8
-    for (int kc = 0; kc < kTK; ++kc) {
-      double s = sS[kc][r];
+      for (int kc = 0; kc < kTK; ++kc) {
+        double sv = sS[kc][r];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) acc[c] = fma(s, sM[kc][cg * 4 + c], acc[c]);
+        for (int cc = 0; cc < 4; ++cc) acc[cc] = fma(sv, sM[kc][cg * 4 + cc], acc[cc]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   int row = row0 + r;
   if (row < n) {
@@ -319,11 +336,12 @@ __global__ __launch_bounds__(256) void k_tsmm(ColMap src,
   if (stop && *stop) return;
   __shared__ double sS[kTK][kTR + 1];
   __shared__ double sM[kTK][kTQ + 1];
+  __shared__ const double* sp[kTGroup * kTK];
   int kk = kk_dev ? *kk_dev : kk_host;
   int q = q_dev ? *q_dev : q_host;
   int row0 = blockIdx.x * kTR, col0 = blockIdx.y * kTQ;
   if (col0 >= q) return;
-  tsmm_tile(src, kk, q, M, ldm, n, Y, ldy, row0, col0, sS, sM);
+  tsmm_tile(src, kk, q, M, ldm, n, Y, ldy, row0, col0, sS, sM, sp);
 }
 
 // ----------------------------------------------------------- Ritz update ---
