@@ -366,56 +366,62 @@ __global__ __launch_bounds__(256) void k_update(const double* __restrict__ S,
   __shared__ double sC[kTK][kTQ + 1];
   double ax[4] = {0, 0, 0, 0}, xx[4] = {0, 0, 0, 0}, pp[4] = {0, 0, 0, 0};
   constexpr int PS = kTK * kTR / 256, PC = kTK * kTQ / 256;
-  double cs[PS], ca[PS], cc_[PC];
-  auto load_chunk = [&](int k0) {
+  // every chunk of a group (the whole trial basis in one group) is loaded
+  // before the first is used, indices clamped; the zero padding is applied
+  // when the values reach LDS
+  double cs[kTGroup][PS], ca[kTGroup][PS], cc_[kTGroup][PC];
+  for (int g0 = 0; g0 < Np; g0 += kTGroup * kTK) {
 #pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int rr = e % kTR, kc = e / kTR;
-      const int row = row0 + rr, k = k0 + kc;
-      const size_t o = min(row, n - 1) + (size_t)min(k, Np - 1) * lds;
-      const double vs = S[o], va = AS[o];
-      const bool ok = (row < n && k < Np);
-      cs[u] = ok ? vs : 0.0;
-      ca[u] = ok ? va : 0.0;
-    }
+    for (int c = 0; c < kTGroup; ++c) {
+      const int k0 = g0 + c * kTK;
 #pragma unroll
-    for (int u = 0; u < PC; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int kc = e % kTK, c = e / kTK;
-      const int k = k0 + kc, j = col0 + c;
-      const double v = C[min(k, Np - 1) + (size_t)min(j, mk - 1) * ldc];
-      cc_[u] = (k < Np && j < mk) ? v : 0.0;
-    }
-  };
-  if (Np > 0) load_chunk(0);
-  for (int k0 = 0; k0 < Np; k0 += kTK) {
+      for (int u = 0; u < PS; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int rr = e % kTR, kc = e / kTR;
+        const size_t o = min(row0 + rr, n - 1) + (size_t)min(k0 + kc, Np - 1) * lds;
+        cs[c][u] = S[o];
+        ca[c][u] = AS[o];
+      }
 #pragma unroll
-    for (int u = 0; u < PS; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      sS[e / kTR][e % kTR] = cs[u];
-      sA[e / kTR][e % kTR] = ca[u];
-    }
-#pragma unroll
-    for (int u = 0; u < PC; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      sC[e % kTK][e / kTK] = cc_[u];
-    }
-    __syncthreads();
-    if (k0 + kTK < Np) load_chunk(k0 + kTK);
-#pragma unroll 8
-    for (int kc = 0; kc < kTK; ++kc) {
-      double s = sS[kc][r], a = sA[kc][r];
-      bool isp = (k0 + kc) >= nx;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        double cc = sC[kc][cg * 4 + c];
-        xx[c] = fma(s, cc, xx[c]);
-        ax[c] = fma(a, cc, ax[c]);
-        if (isp) pp[c] = fma(s, cc, pp[c]);
+      for (int u = 0; u < PC; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int kc = e % kTK, cc = e / kTK;
+        cc_[c][u] = C[min(k0 + kc, Np - 1) + (size_t)min(col0 + cc, mk - 1) * ldc];
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kTGroup; ++c) {
+      const int k0 = g0 + c * kTK;
+      if (k0 >= Np) break;  // uniform
+#pragma unroll
+      for (int u = 0; u < PS; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int rr = e % kTR, kc = e / kTR;
+        const bool ok = (row0 + rr < n && k0 + kc < Np);
+        sS[kc][rr] = ok ? cs[c][u] : 0.0;
+        sA[kc][rr] = ok ? ca[c][u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < PC; ++u) {
+        const int e = threadIdx.x + 256 * u;
+        const int kc = e % kTK, cc = e / kTK;
+        sC[kc][cc] = (k0 + kc < Np && col0 + cc < mk) ? cc_[c][u] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int kc = 0; kc < kTK; ++kc) {
+        double sv = sS[kc][r], a = sA[kc][r];
+        bool isp = (k0 + kc) >= nx;
+#pragma unroll
+        for (int c2 = 0; c2 < 4; ++c2) {
+          double cv = sC[kc][cg * 4 + c2];
+          xx[c2] = fma(sv, cv, xx[c2]);
+          ax[c2] = fma(a, cv, ax[c2]);
+          if (isp) pp[c2] = fma(sv, cv, pp[c2]);
+        }
+      }
+      __syncthreads();
+    }
   }
   int row = row0 + r;
   if (row < n) {
