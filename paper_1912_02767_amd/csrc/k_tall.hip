@@ -166,15 +166,17 @@ __global__ __launch_bounds__(256) void k_gram_partial(ColMap bptr, ColMap yptr, 
   // the next stage's loads are in flight while this stage is multiplied
   constexpr int PER = kGR * kGT / 256;
   double cb[PER], cy[PER];
+  // unconditional loads (rows clamped, global address space), the zero
+  // padding applied at the LDS store: no wait between the loads of a stage
+  typedef const __attribute__((address_space(1))) double* gptr;
   auto load_stage = [&](int rr) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + 256 * u;
       const int r = e % kGR, c = e / kGR;
-      const int row = rr + r, rowc = min(row, r1 - 1);
-      const double vb = pb[c][rowc], vy = py[c][rowc];
-      cb[u] = (row < r1 && okb[c]) ? vb : 0.0;
-      cy[u] = (row < r1 && oky[c]) ? vy : 0.0;
+      const int rowc = min(rr + r, r1 - 1);
+      cb[u] = ((gptr)pb[c])[rowc];
+      cy[u] = ((gptr)py[c])[rowc];
     }
   };
   load_stage(r0);
@@ -182,8 +184,10 @@ __global__ __launch_bounds__(256) void k_gram_partial(ColMap bptr, ColMap yptr, 
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + 256 * u;
-      sb[e % kGR][e / kGR] = cb[u];
-      sy[e % kGR][e / kGR] = cy[u];
+      const int r = e % kGR, c = e / kGR;
+      const bool rowok = rr + r < r1;
+      sb[r][c] = (rowok && okb[c]) ? cb[u] : 0.0;
+      sy[r][c] = (rowok && oky[c]) ? cy[u] : 0.0;
     }
     __syncthreads();
     if (rr + kGR < r1) load_stage(rr + kGR);
