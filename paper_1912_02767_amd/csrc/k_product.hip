@@ -264,8 +264,17 @@ __global__ __launch_bounds__(256) void k_product_reduce(const part_t* __restrict
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   const int i = (int)(e % (size_t)n), j = (int)(e / (size_t)n);
   if (j >= cols) return;
+  // the slices' loads issued 16 at a time before they are added (in slice order)
+  const part_t* p = part + i + (size_t)j * ldp;
   double s = 0.0;
-  for (int q = 0; q < nsl; ++q) s += (double)part[(size_t)q * part_stride + i + (size_t)j * ldp];
+  for (int q0 = 0; q0 < nsl; q0 += 16) {
+    part_t v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = p[(size_t)min(q0 + u, nsl - 1) * part_stride];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (q0 + u < nsl) s += (double)v[u];
+  }
   Y[i + (size_t)j * ldy] = s;
 }
 

@@ -232,16 +232,25 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double* __restric
   int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= rows * cols) return;
   int i = e % rows, j = e / rows;
-  // eight loads in flight; the partial sums are combined in a fixed order
+  // 32 loads in flight (all of a group issued before any is added); the
+  // partial sums are combined in a fixed order
   const double* p = part + i + (size_t)j * ldp;
-  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int b = 0;
-  for (; b + 8 <= nblk; b += 8) {
+  constexpr int W = 32;
+  double s[W];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += p[(size_t)(b + u) * part_stride];
+  for (int u = 0; u < W; ++u) s[u] = 0.0;
+  for (int b = 0; b < nblk; b += W) {
+    double v[W];
+#pragma unroll
+    for (int u = 0; u < W; ++u) v[u] = p[(size_t)min(b + u, nblk - 1) * part_stride];
+#pragma unroll
+    for (int u = 0; u < W; ++u) s[u] += (b + u < nblk) ? v[u] : 0.0;
   }
-  for (int u = 0; b < nblk; ++b, ++u) s[u] += p[(size_t)b * part_stride];
-  out[i + (size_t)j * ldo] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+#pragma unroll
+  for (int h = W / 2; h > 0; h /= 2)
+#pragma unroll
+    for (int u = 0; u < h; ++u) s[u] += s[u + h];
+  out[i + (size_t)j * ldo] = s[0];
 }
 
 // --------------------------------------------------------------- tsmm ---
