@@ -72,10 +72,32 @@ __global__ __launch_bounds__(kBackThreads) void k_rr_back(RRArgs a) {
   double* Tb = Y + (size_t)ldy * kBackCols;
   double* Wb = Tb + kWYBlock * kWYBlock;
   double* Vb = Wb + kWYLd * kBackCols;
-  for (size_t x = threadIdx.x; x < n2 + N; x += kBackThreads) P[x] = a.scratch[x];  // P, tau
-  for (int x = threadIdx.x; x < ldy * kBackCols; x += kBackThreads) {
-    const int i = x % ldy, j = x / ldy;
-    Y[x] = (i < N && j < nc) ? a.C[i + (size_t)(j0 + j) * a.ldc] : 0.0;
+  // P and tau, then the 16 columns of C: eight loads in flight per thread
+  const size_t np = n2 + N;
+  for (size_t x0 = 0; x0 < np; x0 += 8 * kBackThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = a.scratch[min(x0 + threadIdx.x + (size_t)u * kBackThreads, np - 1)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const size_t x = x0 + threadIdx.x + (size_t)u * kBackThreads;
+      if (x < np) P[x] = v[u];
+    }
+  }
+  for (int x0 = 0; x0 < ldy * kBackCols; x0 += 8 * kBackThreads) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int x = x0 + threadIdx.x + u * kBackThreads;
+      const int i = min(x % ldy, N - 1), j = min(x / ldy, nc - 1);
+      v[u] = a.C[i + (size_t)(j0 + j) * a.ldc];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int x = x0 + threadIdx.x + u * kBackThreads;
+      const int i = x % ldy, j = x / ldy;
+      if (x < ldy * kBackCols) Y[x] = (i < N && j < nc) ? v[u] : 0.0;
+    }
   }
   __syncthreads();
   wy_back_dense<NBC>(N, P, tau, Y, ldy, nc, Tb, Wb, Vb, blockIdx.x == 0 ? st : nullptr);

@@ -375,14 +375,24 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
   double* pf = buf + 3 * LP;
   double* cpre = buf + 4 * LP;
   double A[NBR][NBC];
+  // one row of the block at a time: both triangles' entries loaded
+  // unconditionally (indices clamped) before the selects
 #pragma unroll
-  for (int li = 0; li < NBR; ++li)
+  for (int li = 0; li < NBR; ++li) {
+    double ka[NBC], kb[NBC];
+    const int i = row0 + li, ic = min(i, N - 1);
 #pragma unroll
     for (int lj = 0; lj < NBC; ++lj) {
-      const int i = row0 + li, j = c + 16 * lj;
-      A[li][lj] = (i < N && j < N) ? 0.5 * (a.K[i + (size_t)j * a.ldk] + a.K[j + (size_t)i * a.ldk])
-                                   : 0.0;
+      const int jc = min(c + 16 * lj, N - 1);
+      ka[lj] = a.K[ic + (size_t)jc * a.ldk];
+      kb[lj] = a.K[jc + (size_t)ic * a.ldk];
     }
+#pragma unroll
+    for (int lj = 0; lj < NBC; ++lj) {
+      const int j = c + 16 * lj;
+      A[li][lj] = (i < N && j < N) ? 0.5 * (ka[lj] + kb[lj]) : 0.0;
+    }
+  }
   // column 0 below the diagonal, and d[0]
   for (int i = tid; i < LP; i += NT) {
     buf[i] = (i >= 1 && i < N) ? 0.5 * (a.K[i] + a.K[(size_t)i * a.ldk]) : 0.0;
