@@ -276,7 +276,10 @@ __device__ inline int sturm_count_poly(const double* ds, const double* e2s, int 
     a = __builtin_amdgcn_ldexp(a, -ex);
     b = __builtin_amdgcn_ldexp(b, -ex);
   }
-  for (; i < N; ++i) sturm_poly_step(ds[i], e2s[i - 1], xs, a, b, sb, cnt);
+  // the last partial block from the values already prefetched (rows i .. N - 1)
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (i + u < N) sturm_poly_step(dn[u], en[u], xs, a, b, sb, cnt);
   const double m = fmax(fabs(a), fabs(b));
   emin = min(emin, __builtin_amdgcn_frexp_exp(m));
   const bool bad = !(m > 0.0) || !(m < 1e300) || emin < -900;
