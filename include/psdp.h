@@ -83,7 +83,9 @@ typedef struct {
     int ladder;             /* on a stalled low-precision residual move BF16 ->   */
                             /* FP32 -> FP64 products (default 1); 0 = raw path    */
     int certify;            /* reserved, must be 0                                */
-    unsigned long long seed;/* counter-based RNG seed (cold start, expansion)     */
+    unsigned long long seed;/* counter-based RNG seed (cold start, expansion);    */
+                            /* the stream also takes the handle's call count, so */
+                            /* repeated cold starts draw different columns       */
     double side_threshold;  /* AUTO side rule threshold, default 1/3 (paper §6)   */
     int expand_cols;        /* columns added per expansion, 0 = ceil(n/50)        */
                             /* (paper §5.1 expansion rule)                        */

@@ -189,3 +189,53 @@ def test_precision_ladder_warm(proj, prec):
         iters[p] = res.info["iters"]
     print("iters", iters)
     assert iters[prec] <= iters["fp32"] + 10
+
+
+@pytest.mark.parametrize("max_iter", [1, 2, 3, 5])
+def test_iteration_cap_with_queued_iteration(proj, max_iter):
+    """One iteration is queued ahead of the state readback; the cap still
+    holds exactly, and a repeat from the same warm start gives the same
+    bytes (a dropped speculative iteration leaves no trace)."""
+    from gpu_util import to_dev, to_host
+    X = random_spectrum_matrix(300, 30, rng_for(41, 300)).X
+    V0 = rng_for(41, 1).standard_normal((300, 36))
+    Xd = to_dev(X)
+    r1, r2 = (proj.project(Xd, V=to_dev(V0), m_cap=40, side="pos", tol=1e-14,
+                           max_iter=max_iter, raise_on_error=False) for _ in range(2))
+    assert r1.info["iters"] <= max_iter, r1.info
+    assert r1.info["iters"] == r2.info["iters"]
+    P1, P2 = to_host(r1.Pi), to_host(r2.Pi)
+    assert np.isfinite(P1).all()
+    assert np.array_equal(P1, P2)
+
+
+def test_repeat_is_bitwise_identical(proj):
+    """The pipelined loop is deterministic: the same warm-started call twice
+    gives the same projection bytes."""
+    from gpu_util import to_dev, to_host
+    X = random_spectrum_matrix(500, 40, rng_for(42, 500)).X
+    V0 = rng_for(42, 1).standard_normal((500, 46))
+    Xd = to_dev(X)
+    res = [proj.project(Xd, V=to_dev(V0), m_cap=48, side="pos", tol=1e-10)
+           for _ in range(2)]
+    assert res[0].info["iters"] == res[1].info["iters"]
+    assert np.array_equal(to_host(res[0].Pi), to_host(res[1].Pi))
+    _check(res[0], X)
+
+
+def test_profile_filter_times_only_named_families(proj):
+    from gpu_util import to_dev
+    X = to_dev(random_spectrum_matrix(300, 20, rng_for(43, 300)).X)
+    proj.profile_filter("rr")
+    proj.profile_enable(True)
+    proj.project(X, m_cap=32, side="pos", tol=1e-10)
+    rr, gram = proj.profile_get("rr"), proj.profile_get("gram")
+    proj.profile_enable(False)
+    proj.profile_filter("")
+    assert rr["launches"] > 0 and rr["ms"] > 0
+    assert gram["launches"] == 0
+    proj.profile_enable(True)
+    proj.project(X, m_cap=32, side="pos", tol=1e-10)
+    gram = proj.profile_get("gram")
+    proj.profile_enable(False)
+    assert gram["launches"] > 0
