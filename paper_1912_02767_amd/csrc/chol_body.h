@@ -297,63 +297,105 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   //   (1) one wave factors the diagonal block column by column;
   //   (2) rows below the block solve against it, one row per thread;
   //   (3) the trailing triangle takes the rank-bs update in 4 x 4 tiles.
+  // Lookahead: in (3) wave 0 takes the tiles of the next diagonal block and
+  // goes on to factor it (1) while the other waves update the rest, so the
+  // sequential factorization of a block is off the critical path.  What the
+  // other waves read meanwhile that (1) may change (row L[k, :o] of a column
+  // k dropped in the next block) only enters entries of column k, which the
+  // solve (2) multiplies by a zero inverse pivot.
   {
     double* pinv = row;  // 16 inverse pivots of the panel (0: dropped)
     const int lane = tid & 63;
     long long tc = wall_clock64(), tca[3] = {0, 0, 0};
-    for (int o = 0; o < N; o += 16) {
+    // (1) for the block at o, by wave 0: lane l < bs holds row o + l of the
+    // diagonal block; pivots by reciprocal square root (two Newton steps),
+    // the block column by lane reads, the rank-1 updates in registers
+    auto factor_diag = [&](int o) {
       const int bs = min(16, N - o);
-      if (tid < 64) {
-        // lane l < bs holds row o + l of the diagonal block; pivots by
-        // reciprocal square root (two Newton steps), the block column by
-        // lane reads, the rank-1 updates in registers
-        const int l = lane;
-        double rw[16];
+      const int l = lane;
+      double rw[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) rw[k] = (l < bs && k <= l) ? Lp[plo(o + min(l, bs - 1), o + min(k, l))] : 0.0;
-        const double dsl = dsc[o + min(l, bs - 1)];
-        unsigned long long dropm = 0ull;
+      for (int k = 0; k < 16; ++k) rw[k] = (l < bs && k <= l) ? Lp[plo(o + min(l, bs - 1), o + min(k, l))] : 0.0;
+      const double dsl = dsc[o + min(l, bs - 1)];
+      unsigned long long dropm = 0ull;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-          if (j < bs) {
-            const double d = bcast_d(rw[j], j);
-            const double dsj = bcast_d(dsl, j);
-            const bool drop = !(d > a.tau) || dsj == 0.0;
-            double r = 0.0;
-            if (!drop) {
-              r = __builtin_amdgcn_rsq(d);
-              r = r * fma(-0.5 * d * r, r, 1.5);
-              r = r * fma(-0.5 * d * r, r, 1.5);
-            }
-            if (drop) dropm |= 1ull << j;
-            if (l == j) rw[j] = drop ? 0.0 : d * r;  // L(j, j) = sqrt(d)
-            if (l > j) rw[j] = drop ? 0.0 : rw[j] * r;
-            if (l == 0) pinv[j] = r;
-            if (!drop) {
+      for (int j = 0; j < 16; ++j) {
+        if (j < bs) {
+          const double d = bcast_d(rw[j], j);
+          const double dsj = bcast_d(dsl, j);
+          const bool drop = !(d > a.tau) || dsj == 0.0;
+          double r = 0.0;
+          if (!drop) {
+            r = __builtin_amdgcn_rsq(d);
+            r = r * fma(-0.5 * d * r, r, 1.5);
+            r = r * fma(-0.5 * d * r, r, 1.5);
+          }
+          if (drop) dropm |= 1ull << j;
+          if (l == j) rw[j] = drop ? 0.0 : d * r;  // L(j, j) = sqrt(d)
+          if (l > j) rw[j] = drop ? 0.0 : rw[j] * r;
+          if (l == 0) pinv[j] = r;
+          if (!drop) {
 #pragma unroll
-              for (int k = j + 1; k < 16; ++k) {
-                const double lkj = bcast_d(rw[j], k);  // L(k, j)
-                if (k <= l) rw[k] = fma(-rw[j], lkj, rw[k]);
-              }
+            for (int k = j + 1; k < 16; ++k) {
+              const double lkj = bcast_d(rw[j], k);  // L(k, j)
+              if (k <= l) rw[k] = fma(-rw[j], lkj, rw[k]);
             }
           }
         }
-        // rows of dropped columns are zero (in this block and to its left)
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (l == j && ((dropm >> j) & 1ull)) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) rw[k] = 0.0;
-          }
-        if (l < bs)
-#pragma unroll
-          for (int k = 0; k < 16; ++k)
-            if (k <= l) Lp[plo(o + l, o + k)] = rw[k];
-        for (int j = 0; j < bs; ++j)
-          if ((dropm >> j) & 1ull)
-            for (int k = lane; k < o; k += 64) Lp[plo(o + j, k)] = 0.0;
       }
-      __syncthreads();
+      // rows of dropped columns are zero (in this block and to its left)
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if (l == j && ((dropm >> j) & 1ull)) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) rw[k] = 0.0;
+        }
+      if (l < bs)
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+          if (k <= l) Lp[plo(o + l, o + k)] = rw[k];
+      for (int j = 0; j < bs; ++j)
+        if ((dropm >> j) & 1ull)
+          for (int k = lane; k < o; k += 64) Lp[plo(o + j, k)] = 0.0;
+    };
+    // one 4 x 4 tile of the rank-16 update from panel o (rows i0.., columns k0..)
+    auto update_tile = [&](int o, int i0, int k0) {
+      double acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+#pragma unroll 1
+      for (int j0 = 0; j0 < 16; j0 += 4) {
+        double x[4][4], y[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = min(i0 + r, N - 1), k = min(k0 + r, N - 1);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {  // bs = 16 whenever a trailing block exists
+            x[r][q] = Lp[plo(i, o + j0 + q)];
+            y[r][q] = Lp[plo(k, o + j0 + q)];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[r][c] = fma(x[r][q], y[c][q], acc[r][c]);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = i0 + r, k = k0 + c;
+          if (i < N && k <= i) Lp[plo(i, k)] -= acc[r][c];
+        }
+    };
+    if (tid < 64) factor_diag(0);
+    __syncthreads();
+    for (int o = 0; o < N; o += 16) {
+      const int bs = min(16, N - o);
       if (mark) { const long long tn = wall_clock64(); tca[0] += tn - tc; tc = tn; }
       // (2) L[i, o:o+bs] = S[i, o:o+bs] L_D^-T, dropped columns zero
       // (rows below the block exist only when the block is full: bs = 16)
@@ -374,45 +416,27 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       }
       __syncthreads();
       if (mark) { const long long tn = wall_clock64(); tca[1] += tn - tc; tc = tn; }
-      // (3) S[i, k] -= sum_j L[i, o + j] L[k, o + j] for o + bs <= k <= i
+      // (3) S[i, k] -= sum_j L[i, o + j] L[k, o + j] for o + bs <= k <= i;
+      // tiles 0 .. 9 (rows and columns below b0 + 16) form the next diagonal
+      // block: wave 0 updates them and factors that block, the other waves
+      // take tiles 10 ..
       const int b0 = o + bs;
       const int t = N - b0;
       if (t > 0) {
         const int nt = (t + 3) / 4;
-        for (int tile = tid; tile < nt * (nt + 1) / 2; tile += blockDim.x) {
-          const int ti = tri_row(tile), tj = tile - ti * (ti + 1) / 2;
-          const int i0 = b0 + 4 * ti, k0 = b0 + 4 * tj;
-          double acc[4][4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
-#pragma unroll 1
-          for (int j0 = 0; j0 < 16; j0 += 4) {
-            double x[4][4], y[4][4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = min(i0 + r, N - 1), k = min(k0 + r, N - 1);
-#pragma unroll
-              for (int q = 0; q < 4; ++q) {  // bs = 16 whenever a trailing block exists
-                x[r][q] = Lp[plo(i, o + j0 + q)];
-                y[r][q] = Lp[plo(k, o + j0 + q)];
-              }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-              for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[r][c] = fma(x[r][q], y[c][q], acc[r][c]);
+        const int ntile = nt * (nt + 1) / 2;
+        if (tid < 64) {
+          if (tid < min(10, ntile)) {
+            const int ti = tri_row(tid), tj = tid - ti * (ti + 1) / 2;
+            update_tile(o, b0 + 4 * ti, b0 + 4 * tj);
           }
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              const int i = i0 + r, k = k0 + c;
-              if (i < N && k <= i) Lp[plo(i, k)] -= acc[r][c];
-            }
+          __threadfence_block();  // the wave's tile updates precede its reads of the block
+          factor_diag(b0);
+        } else {
+          for (int tile = 10 + tid - 64; tile < ntile; tile += blockDim.x - 64) {
+            const int ti = tri_row(tile), tj = tile - ti * (ti + 1) / 2;
+            update_tile(o, b0 + 4 * ti, b0 + 4 * tj);
+          }
         }
       }
       __syncthreads();
