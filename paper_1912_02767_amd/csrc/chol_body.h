@@ -231,19 +231,42 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
     // max|E| <= 1e-6 the Cholesky factor is I + F + O(E^2) with F the strict
     // lower part of E plus half its diagonal, so T = L^-T = I - F^T up to
     // O(E^2) <= 1e-12: no sequential factorization is needed.
+    // both sweeps over G issue kU unconditional loads (indices clamped)
+    // before using any: one global-memory round trip per kU elements
+    constexpr int kU = 16;
+    const int NN = N * N, nb = (int)blockDim.x;
     double em = 0.0;
-    for (int x = tid; x < N * N; x += blockDim.x) {
-      int i = x % N, j = x / N;
-      em = fmax(em, fabs(a.G[i + (size_t)j * a.ldg] - (i == j ? 1.0 : 0.0)));
+    for (int x0 = tid; x0 < NN; x0 += kU * nb) {
+      double g[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int x = min(x0 + u * nb, NN - 1);
+        g[u] = a.G[x % N + (size_t)(x / N) * a.ldg];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int x = x0 + u * nb;
+        const int i = x % N, j = x / N;
+        const double dv = fabs(g[u] - (i == j ? 1.0 : 0.0));
+        em = fmax(em, (x < NN) ? dv : 0.0);
+      }
     }
     em = block_max(em, red);
     if (em <= 1e-6) {
-      for (int x = tid; x < N * N; x += blockDim.x) {
-        int t = x % N, c = x / N;
-        double v = 0.0;
-        if (c == t) v = 1.0 - 0.5 * (a.G[t + (size_t)t * a.ldg] - 1.0);
-        else if (c > t) v = -a.G[c + (size_t)t * a.ldg];
-        a.T[t + (size_t)c * a.ldt] = v;
+      for (int x0 = tid; x0 < NN; x0 += kU * nb) {
+        double g[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int x = min(x0 + u * nb, NN - 1);
+          g[u] = a.G[x / N + (size_t)(x % N) * a.ldg];  // G[c, t]
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int x = x0 + u * nb;
+          const int t = x % N, c = x / N;
+          const double v = (c == t) ? 1.0 - 0.5 * (g[u] - 1.0) : ((c > t) ? -g[u] : 0.0);
+          if (x < NN) a.T[t + (size_t)c * a.ldt] = v;
+        }
       }
       for (int t = tid; t < N; t += blockDim.x) {
         a.colptr[t] = a.bases[4] + (size_t)t * a.ld;
@@ -267,20 +290,22 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   }
   __syncthreads();
   {
-    // four independent loads in flight per thread
-    const int n2 = N * (N + 1) / 2, nt4 = 4 * blockDim.x;
-    for (int e0 = tid; e0 < n2; e0 += nt4) {
-      double g[4];
-      int ii[4], jj[4];
+    // sixteen independent loads in flight per thread (indices clamped)
+    constexpr int kU = 16;
+    const int n2 = N * (N + 1) / 2, ntu = kU * blockDim.x;
+    for (int e0 = tid; e0 < n2; e0 += ntu) {
+      double g[kU];
+      int ii[kU], jj[kU];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kU; ++u) {
         const int e = min(e0 + u * (int)blockDim.x, n2 - 1);
         ii[u] = tri_row(e);
         jj[u] = e - ii[u] * (ii[u] + 1) / 2;
-        g[u] = a.G[s_list[ii[u]] + (size_t)s_list[jj[u]] * a.ldg];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kU; ++u) g[u] = a.G[s_list[ii[u]] + (size_t)s_list[jj[u]] * a.ldg];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * (int)blockDim.x;
         if (e < n2) Lp[e] = g[u] * dsc[ii[u]] * dsc[jj[u]];
       }
@@ -306,7 +331,8 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
   {
     double* pinv = row;  // 16 inverse pivots of the panel (0: dropped)
     const int lane = tid & 63;
-    long long tc = wall_clock64(), tca[3] = {0, 0, 0};
+    const bool tr = mark && a.trace != 0;  // per-panel clock totals (tracing only)
+    long long tc = tr ? wall_clock64() : 0, tca[3] = {0, 0, 0};
     // (1) for the block at o, by wave 0: lane l < bs holds row o + l of the
     // diagonal block; pivots by reciprocal square root (two Newton steps),
     // the block column by lane reads, the rank-1 updates in registers
@@ -396,7 +422,7 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
     __syncthreads();
     for (int o = 0; o < N; o += 16) {
       const int bs = min(16, N - o);
-      if (mark) { const long long tn = wall_clock64(); tca[0] += tn - tc; tc = tn; }
+      if (tr) { const long long tn = wall_clock64(); tca[0] += tn - tc; tc = tn; }
       // (2) L[i, o:o+bs] = S[i, o:o+bs] L_D^-T, dropped columns zero
       // (rows below the block exist only when the block is full: bs = 16)
       for (int i = o + bs + tid; i < N; i += blockDim.x) {
@@ -415,7 +441,7 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
         for (int j = 0; j < 16; ++j) Li[j] = v[j];
       }
       __syncthreads();
-      if (mark) { const long long tn = wall_clock64(); tca[1] += tn - tc; tc = tn; }
+      if (tr) { const long long tn = wall_clock64(); tca[1] += tn - tc; tc = tn; }
       // (3) S[i, k] -= sum_j L[i, o + j] L[k, o + j] for o + bs <= k <= i;
       // tiles 0 .. 9 (rows and columns below b0 + 16) form the next diagonal
       // block: wave 0 updates them and factors that block, the other waves
@@ -440,7 +466,7 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
         }
       }
       __syncthreads();
-      if (mark) { const long long tn = wall_clock64(); tca[2] += tn - tc; tc = tn; }
+      if (tr) { const long long tn = wall_clock64(); tca[2] += tn - tc; tc = tn; }
     }
     if (mark)
       for (int q = 0; q < 3; ++q) st->t_sub[8 + q] = tca[q];

@@ -199,6 +199,7 @@ struct DecideArgs {
   double* T;            // out: N x Np (ldt)
   int ldt;
   const double** colptr;  // out: N column pointers of the logical trial basis
+  int trace;            // 1: per-panel clock totals into st->t_sub
   State* st;
 };
 
@@ -215,6 +216,7 @@ struct RRArgs {
   double off_tol;    // Jacobi stops when off(H) <= off_tol * ||H||_F
   size_t lds_cap;    // dynamic LDS doubles of the launch (set by launch_rr)
   double* scratch;   // global scratch, >= 5 * Np * mk doubles (tridiagonal path)
+  int trace;         // 1: per-step clock totals into st->t_sub
   State* st;
 };
 

@@ -453,6 +453,7 @@ struct Solver {
     da.has_p = hp; da.phase_lowprec = pprec; da.tau = 1e-10; da.spec_m = spec_m;
     da.bases[0] = w.X; da.bases[1] = w.R; da.bases[2] = w.P; da.bases[3] = w.Z; da.bases[4] = w.S1;
     da.ld = L; da.T = w.T; da.ldt = NC; da.colptr = w.colptr; da.st = w.st;
+    da.trace = h->trace > 1 ? 1 : 0;
     int Nmax = Ng;  // upper bound on the trial width
     {
       ProfScope ps(h, "chol");
@@ -511,6 +512,7 @@ struct Solver {
     ra.count_iter = (mode == kModeFull || mode == kModeXR) ? 1 : 0;
     ra.off_tol = 1e-14;
     ra.scratch = w.rrs;
+    ra.trace = h->trace > 1 ? 1 : 0;
     ra.st = w.st;
     {
       ProfScope ps(h, "rr");
@@ -625,6 +627,7 @@ struct Solver {
     da.has_p = has_p; da.tau = 1e-10;
     da.bases[0] = w.X; da.bases[1] = w.R; da.bases[2] = w.P; da.bases[3] = w.Z; da.bases[4] = w.S1;
     da.ld = L; da.T = w.T; da.ldt = NC; da.colptr = w.colptr; da.st = w.st;
+    da.trace = h->trace > 1 ? 1 : 0;
     {
       ProfScope ps(h, "chol");
       HIP_TRY(launch_decide_chol(da, Ng, s));

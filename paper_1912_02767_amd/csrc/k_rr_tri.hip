@@ -100,7 +100,8 @@ __global__ __launch_bounds__(kBackThreads) void k_rr_back(RRArgs a) {
     }
   }
   __syncthreads();
-  wy_back_dense<NBC>(N, P, tau, Y, ldy, nc, Tb, Wb, Vb, blockIdx.x == 0 ? st : nullptr);
+  wy_back_dense<NBC>(N, P, tau, Y, ldy, nc, Tb, Wb, Vb,
+                     (blockIdx.x == 0 && a.trace) ? st : nullptr);
   for (int x = threadIdx.x; x < N * nc; x += kBackThreads) {
     const int i = x % N, j = x / N;
     a.C[i + (size_t)(j0 + j) * a.ldc] = Y[i + (size_t)j * ldy];

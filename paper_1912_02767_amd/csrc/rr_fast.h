@@ -406,7 +406,8 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
   }
   if (tid == 0) d[0] = a.K[0];
   __syncthreads();
-  long long tl = wall_clock64(), tacc0 = 0, tacc1 = 0;
+  const bool tr = a.trace != 0 && tid == 0;  // per-step clock totals (tracing only)
+  long long tl = tr ? wall_clock64() : 0, tacc0 = 0, tacc1 = 0;
   for (int k = 0; k + 2 < N; ++k) {
     const double* col = buf + (k & 1) * LP;
     double* coln = buf + ((k + 1) & 1) * LP;
@@ -480,7 +481,7 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
       scale = refl ? copysign(q, alpha) : 0.0;
     }
     __syncthreads();
-    if (tid == 0) { const long long tn = wall_clock64(); tacc0 += tn - tl; tl = tn; }
+    if (tr) { const long long tn = wall_clock64(); tacc0 += tn - tl; tl = tn; }
     // ---- (b) v and w, the reflector kept in P, the next column
     // (threads past the last trailing row skip the phase)
     if (k + 1 + tid < N) {
@@ -521,7 +522,7 @@ __device__ inline void tridiag_reg(const RRArgs& a, int N, double* P, double* d,
       }
     }
     __syncthreads();
-    if (tid == 0) { const long long tn = wall_clock64(); tacc1 += tn - tl; tl = tn; }
+    if (tr) { const long long tn = wall_clock64(); tacc1 += tn - tl; tl = tn; }
     // ---- (c) rank-2 update of this thread's block; v comes from x in the
     // registers (v = scale x below row k + 1, v_{k+1} = 1, the same products
     // as in (b)), w from LDS
@@ -620,7 +621,7 @@ __device__ inline void wy_back(int N, const double* P, const double* tau, double
     constexpr int NCW = NTQ - 1;           // column tiles of Y (ncols <= 16 NCW)
     const int g = tid >> 4, s16 = tid & 15, r = tid >> 4, c = tid & 15;
     const int nref = N - 2;  // reflectors 0 .. N - 3
-    long long tw = wall_clock64(), twa[4] = {0, 0, 0, 0};
+    long long tw = st ? wall_clock64() : 0, twa[4] = {0, 0, 0, 0};
     for (int b0 = nref > 0 ? ((nref - 1) / kWYBlock) * kWYBlock : -1; b0 >= 0; b0 -= kWYBlock) {
       const int bs = min(kWYBlock, nref - b0);
       {
@@ -680,7 +681,7 @@ __device__ inline void wy_back(int N, const double* P, const double* tau, double
         }
       }
       __syncthreads();
-      if (tid == 0) { const long long tn = wall_clock64(); twa[0] += tn - tw; tw = tn; }
+      if (tid == 0 && st) { const long long tn = wall_clock64(); twa[0] += tn - tw; tw = tn; }
       // W <- T W with T = U^{-1}, U = diag(1 / tau) + strictly upper part of
       // V^T V: back substitution U W' = W, one thread per column of W,
       // W'(l) = tau_l (W(l) - sum_{m > l} G(l, m) W'(m)) (zero when tau_l = 0)
@@ -704,7 +705,7 @@ __device__ inline void wy_back(int N, const double* P, const double* tau, double
         for (int l = 0; l < kWYBlock; ++l) Wb[l + kWYLd * j] = w[l];
       }
       __syncthreads();
-      if (tid == 0) {
+      if (tid == 0 && st) {
         const long long tn = wall_clock64();
         twa[1] += tn - tw;
         tw = tn;
@@ -742,7 +743,7 @@ __device__ inline void wy_back(int N, const double* P, const double* tau, double
         }
       }
       __syncthreads();
-      if (tid == 0) { const long long tn = wall_clock64(); twa[3] += tn - tw; tw = tn; }
+      if (tid == 0 && st) { const long long tn = wall_clock64(); twa[3] += tn - tw; tw = tn; }
     }
     if (tid == 0 && st)
       for (int q = 0; q < 4; ++q) st->t_sub[2 + q] = twa[q];
@@ -769,7 +770,7 @@ __device__ inline void wy_back_dense(int N, const double* P, const double* tau, 
   const int tid = threadIdx.x;
   const int g = tid >> 4, s16 = tid & 15;
   const int nref = N - 2;  // reflectors 0 .. N - 3
-  long long tw = wall_clock64(), twa[4] = {0, 0, 0, 0};
+  long long tw = st ? wall_clock64() : 0, twa[4] = {0, 0, 0, 0};
   for (int b0 = nref > 0 ? ((nref - 1) / kWYBlock) * kWYBlock : -1; b0 >= 0; b0 -= kWYBlock) {
     const int bs = min(kWYBlock, nref - b0);
     const int nrow = N - 1 - b0;          // rows b0 + 1 .. N - 1
@@ -836,7 +837,7 @@ __device__ inline void wy_back_dense(int N, const double* P, const double* tau, 
       }
     }
     __syncthreads();
-    if (tid == 0) { const long long tn = wall_clock64(); twa[0] += tn - tw; tw = tn; }
+    if (tid == 0 && st) { const long long tn = wall_clock64(); twa[0] += tn - tw; tw = tn; }
     // (ii) W <- T W by back substitution with U = T^{-1}, one thread per
     // column: W'(l) = tau_l (W(l) - sum_{m > l} G(l, m) W'(m)); rows l >= bs
     // of G and W are zero, and tau_l = 0 there
@@ -861,7 +862,7 @@ __device__ inline void wy_back_dense(int N, const double* P, const double* tau, 
       for (int l = 0; l < kWYBlock; ++l) Wb[l + kWYLd * j] = w[l];
     }
     __syncthreads();
-    if (tid == 0) { const long long tn = wall_clock64(); twa[1] += tn - tw; tw = tn; }
+    if (tid == 0 && st) { const long long tn = wall_clock64(); twa[1] += tn - tw; tw = tn; }
     // (iii) Y -= V W: thread (r, c) on rows b0 + 1 + r + 16 li of column c
     {
       const int r = tid >> 4, c = tid & 15, jc = min(c, ncols - 1);
@@ -881,7 +882,7 @@ __device__ inline void wy_back_dense(int N, const double* P, const double* tau, 
       }
     }
     __syncthreads();
-    if (tid == 0) { const long long tn = wall_clock64(); twa[3] += tn - tw; tw = tn; }
+    if (tid == 0 && st) { const long long tn = wall_clock64(); twa[3] += tn - tw; tw = tn; }
   }
   if (tid == 0 && st)
     for (int q = 0; q < 4; ++q) st->t_sub[2 + q] = twa[q];
@@ -1212,7 +1213,7 @@ __device__ inline void rr_fast_body(const RRArgs& a, double* lds, const RRShared
   __syncthreads();
   if (tid == 0) st->t_phase[3] = wall_clock64();
 
-  if (!EXPORT) wy_back<NT, NBC, 4>(N, P, tau, Y, ldy, mk, Tb, Wb, st);
+  if (!EXPORT) wy_back<NT, NBC, 4>(N, P, tau, Y, ldy, mk, Tb, Wb, a.trace ? st : nullptr);
   if (tid == 0) st->t_phase[4] = wall_clock64();
   // ---- outputs: C = Z (N x mk), Ritz values descending
   for (int x = tid; x < N * mk; x += nt) {
