@@ -61,10 +61,10 @@ KERNEL_TABLE_STEPS = 10   # untimed steps that time every family
 # kernel and is reported as null.
 TRAFFIC = {
     ("n1000_warm_seq", "rr"): {
-        "bytes": 103.4e3,
+        "bytes": 110.0e3,
         "files": ["paper_1912_02767_amd/csrc/rr_fast.h", "paper_1912_02767_amd/csrc/rr_body.h",
                   "paper_1912_02767_amd/csrc/k_rr_tri.hip", "paper_1912_02767_amd/csrc/common.h"],
-        "sha256": "b61f7054813410eb244b013d0588343a7bc09d1e0ad2e8d3987c3353bfb69bd2",
+        "sha256": "229773ac0459cb4650254c02fbf64280cfb5174a955ea979d9ac9e36a6250188",
         "profile": "profiles/hbm_traffic_n1000_warm_seq.txt",
     },
 }
