@@ -80,6 +80,7 @@ struct PendingEvent {
   std::string family;
   hipEvent_t a, b;
   double bytes, flops;
+  int prec = -1;  // block products: 0 FP64, 1 FP32, 2 BF16 (also tallied per precision)
 };
 
 struct Workspace {
@@ -197,7 +198,7 @@ struct ProfScope {
   ~ProfScope() {
     if (a && b) {
       (void)hipEventRecord(b, h->stream);
-      h->pending.push_back({fam, a, b, bytes, flops});
+      h->pending.push_back({fam, a, b, bytes, flops, -1});
     }
   }
 };
@@ -213,6 +214,14 @@ void prof_collect(psdp_handle h) {
     e.ms += ms;
     e.bytes += p.bytes;
     e.flops += p.flops;
+    if (p.prec >= 0 && p.prec <= 2) {
+      static const char* const kPrecName[3] = {"product_fp64", "product_fp32", "product_bf16"};
+      auto& q = h->prof_tab[kPrecName[p.prec]];
+      q.launches += 1;
+      q.ms += ms;
+      q.bytes += p.bytes;
+      q.flops += p.flops;
+    }
     h->event_pool.push_back(p.a);
     h->event_pool.push_back(p.b);
   }
@@ -382,6 +391,7 @@ struct Solver {
       } else if (p.family == "product") {
         p.flops = 2.0 * nn * nn * N2;
         p.bytes = (double)product_elem_bytes(pprec) * nn * nn + 16.0 * nn * N2;
+        p.prec = pprec;
       }
     }
   }

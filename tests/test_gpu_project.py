@@ -239,3 +239,18 @@ def test_profile_filter_times_only_named_families(proj):
     gram = proj.profile_get("gram")
     proj.profile_enable(False)
     assert gram["launches"] > 0
+
+
+def test_product_tallies_split_by_precision(proj):
+    """Block-product launches are also tallied per product precision; the
+    split never exceeds the family total."""
+    from gpu_util import to_dev
+    X = to_dev(random_spectrum_matrix(600, 20, rng_for(44, 600)).X)
+    proj.profile_enable(True)
+    proj.project(X, m_cap=32, side="pos", prec="fp32", tol=1e-9)
+    tot = proj.profile_get("product")
+    parts = {p: proj.profile_get("product_" + p) for p in ("fp64", "fp32", "bf16")}
+    proj.profile_enable(False)
+    assert parts["fp32"]["launches"] > 0 and parts["fp32"]["flops"] > 0
+    assert sum(v["launches"] for v in parts.values()) <= tot["launches"]
+    assert sum(v["ms"] for v in parts.values()) <= tot["ms"] * (1 + 1e-9)
