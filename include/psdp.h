@@ -100,6 +100,11 @@ typedef struct {
     int batch_graph;        /* psdp_project_batched: 1 = replay the launch        */
                             /* sequence from a captured hipGraph (default),       */
                             /* 0 = plain launches                                 */
+    double bound_rel_max;   /* > 0 with fallback_full = 1 (psdp_project): a       */
+                            /* converged result whose a-posteriori bound (paper   */
+                            /* §5.2, residual and tail terms) exceeds             */
+                            /* bound_rel_max * ||Pi||_F is replaced by the full   */
+                            /* eig (PSDP_FELL_BACK_FULL_EIG); 0 = off (default)   */
 } psdp_options;
 
 typedef struct {

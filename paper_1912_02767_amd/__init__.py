@@ -71,7 +71,7 @@ class Result:
 
 def _opts(lib, side="pos", prec="fp64", tol=0.0, max_iter=300, refine=True,
           ladder=True, seed=None, side_threshold=1.0 / 3.0, expand_cols=0,
-          pos_hint=-1, fallback_full=False, block_guard=4):
+          pos_hint=-1, fallback_full=False, block_guard=4, bound_rel_max=0.0):
     o = _abi.Options()
     lib.psdp_default_options(ctypes.byref(o))
     o.side = SIDE[side] if isinstance(side, str) else int(side)
@@ -87,6 +87,7 @@ def _opts(lib, side="pos", prec="fp64", tol=0.0, max_iter=300, refine=True,
     o.pos_hint = int(pos_hint)
     o.fallback_full = 1 if fallback_full else 0
     o.block_guard = int(block_guard)
+    o.bound_rel_max = float(bound_rel_max)
     return o
 
 
@@ -136,7 +137,8 @@ class Projector:
                 tol: float = 0.0, max_iter: int = 300, refine: bool = True, ladder: bool = True,
                 seed=None, pos_hint: int = -1, expand_cols: int = 0, fallback_full: bool = False,
                 side_threshold: float = 1.0 / 3.0, block_guard: int = 4, V_buf=None,
-                Pi_out=None, lam_buf=None, raise_on_error: bool = True) -> Result:
+                Pi_out=None, lam_buf=None, raise_on_error: bool = True,
+                bound_rel_max: float = 0.0) -> Result:
         """Pi(X) with LOBPCG on one spectral side (psdp_project).
 
         V: optional warm start (n x k).  V_buf: optional column-major
@@ -162,7 +164,7 @@ class Projector:
         Pi = Pi_out if Pi_out is not None else _empty_f(n, n, Xf.device)
         m_io = ctypes.c_int(k)
         opt = _opts(self.lib, side, prec, tol, max_iter, refine, ladder, seed, side_threshold,
-                    expand_cols, pos_hint, fallback_full, block_guard)
+                    expand_cols, pos_hint, fallback_full, block_guard, bound_rel_max)
         info = _abi.Info()
         rc = self.lib.psdp_project(self._h, n, ctypes.c_void_p(Xf.data_ptr()), Xf.stride(1),
                                    ctypes.c_void_p(V_buf.data_ptr()), V_buf.stride(1), cap,

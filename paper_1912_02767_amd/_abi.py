@@ -51,6 +51,7 @@ class Options(ctypes.Structure):
         ("block_guard", ctypes.c_int),
         ("batch_variant", ctypes.c_int),
         ("batch_graph", ctypes.c_int),
+        ("bound_rel_max", ctypes.c_double),
     ]
 
 

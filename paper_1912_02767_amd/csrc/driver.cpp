@@ -686,6 +686,7 @@ void psdp_default_options(psdp_options* o) {
   o->block_guard = 4;
   o->batch_variant = -1;
   o->batch_graph = 1;
+  o->bound_rel_max = 0.0;
 }
 
 psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t* bytes) {
@@ -1416,7 +1417,8 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       }
     }
   }
-  if (fell_back || (!converged && opt.fallback_full)) {
+  // the exact path in place of the LOBPCG result
+  auto full_instead = [&]() -> psdp_status {
     int mo = 0, npos = 0;
     psdp_status st2 = full_eig_core(h, n, X, ldx, nullptr, Pi, ldpi, V, ldv, m_cap, &mo, lambda, &npos);
     if (st2 != PSDP_OK) { info->status = st2; return st2; }
@@ -1430,7 +1432,8 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     info->expansions = expansions;
     info->status = PSDP_FELL_BACK_FULL_EIG;
     return PSDP_FELL_BACK_FULL_EIG;
-  }
+  };
+  if (fell_back || (!converged && opt.fallback_full)) return full_instead();
   if (!converged && phase != 0 && opt.refine_fp64) {
     // not converged at a low precision: still finish with exact FP64 pairs
     phase = 0;
@@ -1463,6 +1466,10 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   double sum_pos2 = 0.0;
   for (int i = 0; i < npos; ++i) sum_pos2 += st.theta[i] * st.theta[i];
   double pi_fro = (side == PSDP_SIDE_POS) ? std::sqrt(sum_pos2) : std::sqrt(std::max(fro2 - sum_pos2, 0.0));
+  // a bound above the caller's target: the exact path instead (not-a-number
+  // bounds included)
+  if (opt.fallback_full && opt.bound_rel_max > 0.0 && !(bound <= opt.bound_rel_max * pi_fro))
+    return full_instead();
   // ---- rebuild Pi
   {
     ProfScope pscope(h, "rebuild", 8.0 * n * (double)n * (side == PSDP_SIDE_NEG ? 2 : 1),

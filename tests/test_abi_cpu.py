@@ -83,6 +83,7 @@ def test_defaults_and_strings(lib):
     assert o.side == 0 and o.prec == 0 and o.max_iter > 0 and o.refine_fp64 == 1
     assert abs(o.side_threshold - 1.0 / 3.0) < 1e-15 and o.pos_hint == -1
     assert o.batch_variant == -1 and o.batch_graph == 1
+    assert o.bound_rel_max == 0.0
     lib.psdp_status_str.restype = ctypes.c_char_p
     for code, name in [(0, b"PSDP_OK"), (1, b"PSDP_NOT_CONVERGED"), (-1, b"PSDP_ERR_INVALID_ARG"),
                        (-5, b"PSDP_ERR_CAPACITY")]:

@@ -254,3 +254,21 @@ def test_product_tallies_split_by_precision(proj):
     assert parts["fp32"]["launches"] > 0 and parts["fp32"]["flops"] > 0
     assert sum(v["launches"] for v in parts.values()) <= tot["launches"]
     assert sum(v["ms"] for v in parts.values()) <= tot["ms"] * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("limit,fell_back", [(0.0, False), (1.0, False), (1e-30, True)])
+def test_bound_target_fallback(proj, limit, fell_back):
+    """With fallback_full, a converged result whose a-posteriori bound is above
+    bound_rel_max * ||Pi||_F takes the exact path; 0 disables the check."""
+    from gpu_util import to_dev
+    c = random_spectrum_matrix(200, 10, rng_for(45, 200))
+    res = proj.project(to_dev(c.X), m_cap=24, side="pos", tol=1e-10, fallback_full=True,
+                       bound_rel_max=limit, raise_on_error=False)
+    if fell_back:
+        assert res.status == 2 and res.info["side_used"] == 3, res.info  # fell back; full side
+        assert res.info["n_pos_full"] == 10
+        _check(res, c.X, rel=1e-12, bound=False)
+    else:
+        assert res.status == 0 and res.info["side_used"] == 1, res.info
+        assert res.info["err_bound"] <= 1.0 * res.info["pi_fro"]
+        _check(res, c.X)
