@@ -3,20 +3,20 @@
 full eigendecomposition path at relative Frobenius error <= 1e-6.
 
 Workloads (one step = one pass of the whole projection path):
-  n1000_warm_seq  (default) n = 1000, X_0 = Q diag(lam) Q^T with 20 eigenvalues
-                  in [0.5, 5] and 980 in [-5, -0.01], X_{k+1} = X_k + E_k with
-                  ||E_k||_F = 1e-3 * 0.98^k * ||X_k||_F, 200 matrices, block 24,
-                  tolerance 1e-8, FP64 products; a step is one warm-started
-                  projection of the next matrix.
-  n4000_mixed     n = 4000, Householder basis, 40 positive eigenvalues, 50
-                  warm-started steps X_{k+1} = X_k + E_k, ||E_k||_F = 1e-4 ||X_k||_F,
-                  FP32 (or --prec bf16) products, FP64 orthogonalization /
-                  Rayleigh-Ritz / refinement.  The random walk moves hundreds of
-                  eigenvalues of the -1e-3 cluster across zero within a few steps;
-                  once the positive count outgrows the 48-column block the side
-                  rule sends the step to the exact full eigendecomposition.
+  n4000_mixed     (default) n = 4000, Householder basis, 40 positive
+                  eigenvalues, 50 warm-started steps X_{k+1} = X_k + E_k,
+                  ||E_k||_F = 1e-4 ||X_k||_F, FP32 (or --prec bf16) products,
+                  FP64 orthogonalization / Rayleigh-Ritz / refinement, the tail
+                  of the bound certified.  The random walk moves eigenvalues of
+                  the -1e-3 cluster across zero (75 positive at step 2, 370 at
+                  step 49): the block solver cannot certify those steps and the
+                  side rule sends them to the exact full eigendecomposition.
   n4000_mixed_iid the same cone with X_k = X_0 + E_k (independent perturbations
                   of size 1e-4 ||X_0||_F): the positive count stays 40.
+  n1000_warm_seq  n = 1000, X_0 = Q diag(lam) Q^T with 20 eigenvalues in
+                  [0.5, 5] and 980 in [-5, -0.01], X_{k+1} = X_k + E_k with
+                  ||E_k||_F = 1e-3 * 0.98^k * ||X_k||_F, 200 matrices, block 24,
+                  tolerance 1e-8, FP64 products.
   batched512      512 cones, n_i uniform in [16, 256], 10% positive spectrum;
                   a step is one persistent launch projecting all 512 (FP32
                   products, FP64 Rayleigh-Ritz).
@@ -27,8 +27,11 @@ Workloads (one step = one pass of the whole projection path):
                   the plain path (one projection at a time, same arrivals).
 
 Prints ONE JSON line.  Inputs are generated on the host (seeded) and
-uploaded before the timed region.  The cpu_baseline leg times the FP64
-Jacobi oracle on a bounded sample of the same matrices.
+uploaded before the timed region.  Every timed step of a sequence is checked
+against the full eigendecomposition of the same matrix; `value` counts only
+the steps within 1e-6.  The cpu_baseline leg times the FP64 Jacobi oracle on
+a sample of the same matrices at full size (one n = 4000 matrix takes about
+two minutes on 16 threads).
 
 --copy-probe B runs only a plain device copy of B MiB (ten times) and
 exits: the reference kernel for scaling the HBM byte counters of a profile.
@@ -50,8 +53,9 @@ import numpy as np  # noqa: E402
 PEAKS = {  # MI355X published dense peaks
     "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
 }
-FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rrback", "rebuild", "ingest", "batched", "fulleig"]
-TIMED_FAMILY = "rr"       # the dominant family of the sequence workloads
+FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rrback", "rebuild", "ingest", "cert",
+            "batched", "fulleig"]
+LIBRARY_FAMILIES = {"fulleig"}  # rocSOLVER calls, not hand-written kernels
 KERNEL_TABLE_STEPS = 10   # untimed steps that time every family
 
 # HBM bytes per launch measured with rocprofv3 PMC counters (FETCH_SIZE x 2.0
@@ -167,6 +171,16 @@ def make_sequence(workload, steps_total):
     return 4000, 40, [X0] + list(seq), lam
 
 
+def closed_form_step0(workload, n, lam0):
+    """Pi(X_0) from the construction X_0 = Q diag(lam) Q^T: Q diag(lam_+) Q^T."""
+    from workloads import large_cone, warm_sequence
+    if workload == "n1000_warm_seq":
+        c0 = next(warm_sequence(n=1000, n_pos=20, steps=1))
+        return c0.sandwich(np.maximum(c0.lam, 0.0))
+    _, lam, basis = large_cone(n=n, n_pos=40)
+    return basis.sandwich(np.maximum(lam, 0.0))
+
+
 def run_sequence(args, torch, psdp):
     wl = args.workload
     big = wl.startswith("n4000")
@@ -192,121 +206,136 @@ def run_sequence(args, torch, psdp):
         tol, m_cap, block = 1e-8, 24, 24
 
     proj = psdp.Projector(0)
-    # AUTO side with the block cost rule; a block that outgrows the cap falls
-    # back to the exact path and the next step starts from its inertia.  At
-    # n = 4000 a result whose whole bound (residual and tail terms) is above
-    # the metric's 1e-6 ||Pi||_F also takes the exact path.
-    sess = psdp.Session(proj, n, m_cap=m_cap, tol=tol, side="auto", pos_hint=p, prec=prec,
-                        block_guard=block - p, fallback_full=True,
-                        bound_rel_max=(1e-6 if big else 0.0))
+
+    def session():
+        # AUTO side (paper §6) from the previous call's inertia; the tail of
+        # the bound is certified; a step the block solver cannot certify, or
+        # whose bound is above 1e-6 ||Pi||_F at n = 4000, takes the exact path
+        return psdp.Session(proj, n, m_cap=m_cap, tol=tol, side="auto", pos_hint=p, prec=prec,
+                            block_guard=block - p, fallback_full=True,
+                            bound_rel_max=(1e-6 if big else 0.0))
+
+    # untimed pass over every kernel family (the kernel table; it also names
+    # the dominant hand-written family that the timed region times)
+    sess = session()
     Pis = [psdp._empty_f(n, n, dev) for _ in range(2)]
-    for k in range(warm):  # untimed: the first matrices of the sequence
+    proj.profile_enable(True)
+    kt_steps = min(warm + steps, KERNEL_TABLE_STEPS)
+    for k in range(kt_steps):
         sess.project(Xs[k], Pi_out=Pis[k % 2])
     torch.cuda.synchronize()
+    fams_all = {f: proj.profile_get(f) for f in FAMILIES + ["product_fp64", "product_fp32", "product_bf16"]}
+    proj.profile_enable(False)
+    ours = [f for f in FAMILIES if f not in LIBRARY_FAMILIES and fams_all[f]["launches"]]
+    timed_family = max(ours, key=lambda f: fams_all[f]["ms"]) if ours else "rr"
 
-    # the timed region times only the dominant kernel family live (each timed
-    # family costs the stream two event records per launch group)
-    proj.profile_filter(TIMED_FAMILY)
+    # timed sequence from a fresh session (warm-up steps untimed)
+    sess = session()
+    Pi0 = None
+    for k in range(warm):
+        r = sess.project(Xs[k], Pi_out=Pis[k % 2])
+        if k == 0:
+            Pi0 = r.Pi.clone()
+    torch.cuda.synchronize()
+    proj.profile_filter(timed_family)
     proj.profile_enable(True)
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(steps)]
-    infos, keep = [], {}
-    sample_at = {warm, warm + steps // 2, warm + steps - 1}
+    infos = []
+    outs = [psdp._empty_f(n, n, dev) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         k = warm + i
         ev[i][0].record(stream)
-        res = sess.project(Xs[k], Pi_out=Pis[i % 2])
+        res = sess.project(Xs[k], Pi_out=outs[i])
         ev[i][1].record(stream)
         infos.append(res.info)
-        if k in sample_at:
-            keep[k] = res.Pi.clone()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     fams = {f: proj.profile_get(f) for f in FAMILIES}
     proj.profile_enable(False)
     proj.profile_filter("")
-    value = steps / wall
-    # every family, on an untimed pass over the first matrices of the timed
-    # region: the kernel table and the block product's roofline
-    proj.profile_enable(True)
-    for i in range(min(steps, KERNEL_TABLE_STEPS)):
-        sess.project(Xs[warm + i], Pi_out=Pis[i % 2])
-    torch.cuda.synchronize()
-    fams_all = {f: proj.profile_get(f) for f in FAMILIES + ["product_fp64", "product_fp32", "product_bf16"]}
-    proj.profile_enable(False)
 
-    # on-GPU full eigendecomposition of the same matrices
-    n_fe = args.full_eig_samples if args.full_eig_samples is not None else (3 if big else 10)
-    fe_idx = [warm + int(i * max(1, steps - 1) / max(1, n_fe - 1)) for i in range(n_fe)] if n_fe else []
-    fe_idx = sorted(set(min(k, warm + steps - 1) for k in fe_idx) | set(keep))
-    fe_Pi = {}
-    proj.full_eig(Xs[fe_idx[0]])
+    # every timed step against the on-GPU full eigendecomposition of the same
+    # matrix (untimed as a check; the same calls time the baseline)
+    proj.full_eig(Xs[warm])
     torch.cuda.synchronize()
-    t_fe = 0.0
-    for k in fe_idx:
+    t_fe, rel_vs_fe = 0.0, []
+    Pi_f = psdp._empty_f(n, n, dev)
+    for i in range(steps):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        Pi_f, _ = proj.full_eig(Xs[k])
+        proj.full_eig(Xs[warm + i], Pi_out=Pi_f)
         torch.cuda.synchronize()
         t_fe += time.perf_counter() - t
-        if k in keep:
-            fe_Pi[k] = Pi_f.clone()
-    fe_rate = len(fe_idx) / t_fe
-    rel_vs_fe = {k: float(torch.linalg.norm(keep[k] - fe_Pi[k]) / torch.linalg.norm(fe_Pi[k]))
-                 for k in keep}
+        rel_vs_fe.append(float(torch.linalg.norm(outs[i] - Pi_f) / torch.linalg.norm(Pi_f)))
+    fe_rate = steps / t_fe
+    bad = [warm + i for i, r in enumerate(rel_vs_fe) if not r <= 1e-6]
+    ok_steps = steps - len(bad)
+
+    # step 0 against the construction closed form
+    rel_step0 = None
+    if Pi0 is not None:
+        exact0 = closed_form_step0(wl, n, lam0)
+        rel_step0 = float(np.linalg.norm(Pi0.cpu().numpy() - exact0) / np.linalg.norm(exact0))
 
     cpu, rel_oracle = None, {}
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        if not big:
-            n_or = args.oracle_samples if args.oracle_samples is not None else 3
-            ks = sorted(keep)[:n_or]
-            t = time.perf_counter()
-            for k in ks:
-                Pi_ref, _ = oracle.project(mats[k])
-                rel_oracle[k] = oracle.rel_error(keep[k].cpu().numpy(), Pi_ref)
-            dt = time.perf_counter() - t
-            cpu = {"value": len(ks) / dt, "unit": "projections/s", "cores": oracle.num_threads(),
-                   "kind": "oracle",
-                   "sample": f"{len(ks)} of the timed matrices (steps {ks}), FP64 cyclic Jacobi + clip"}
-        else:
-            sub = np.asfortranarray(mats[0][:1000, :1000])
-            t = time.perf_counter()
-            oracle.project(sub)
-            dt = time.perf_counter() - t
-            scale = (n / 1000.0) ** 3
-            cpu = {"value": 1.0 / (dt * scale), "unit": "projections/s",
-                   "cores": oracle.num_threads(), "kind": "oracle",
-                   "sample": "oracle on the leading 1000x1000 block of X_0, time scaled by (4000/1000)^3"}
+        n_or = args.oracle_samples if args.oracle_samples is not None else (1 if big else 3)
+        ks = [warm + int(i * max(1, steps - 1) / max(1, n_or - 1)) for i in range(n_or)][:n_or]
+        ks = sorted(set(ks))
+        log(f"oracle (FP64 Jacobi on {oracle.num_threads()} threads) on step(s) {ks} ...")
+        t = time.perf_counter()
+        for k in ks:
+            Pi_ref, _ = oracle.project(mats[k])
+            rel_oracle[k] = oracle.rel_error(outs[k - warm].cpu().numpy(), Pi_ref)
+            log(f"oracle step {k}: rel {rel_oracle[k]:.2e} ({time.perf_counter() - t:.1f}s)")
+        dt = time.perf_counter() - t
+        cpu = {"value": len(ks) / dt, "unit": "projections/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{len(ks)} of the timed matrices (steps {ks}) at full size n={n}, "
+                         f"FP64 cyclic Jacobi + clip"}
     iters = np.array([inf["iters"] for inf in infos])
+    lob = [inf for inf in infos if inf["side_used"] != 3]
+    cert = fams_all.get("cert", {"launches": 0, "ms": 0.0})
     out = {
-        "value": value, "steps": steps, "warmup": warm, "ms_per_step": 1e3 * wall / steps,
+        "value": ok_steps / wall, "steps": steps, "warmup": warm, "ms_per_step": 1e3 * wall / steps,
         "dtype": prec,
         "config": {"workload": wl, "n": n, "n_pos": p, "block": block, "tol": tol,
                    "bound_rel_target": args.bound_rel if big else None,
-                   "matrices": len(mats), "products": prec, "ortho_rr_refine": "fp64"},
+                   "matrices": len(mats), "products": prec, "ortho_rr_refine": "fp64",
+                   "tail": "certified (FP64 Cholesky certificate)"},
+        "value_note": "projections/s counting only steps within 1e-6 of the full eig "
+                      "(every timed step is checked)",
+        "accuracy_ok": not bad, "steps_over_1e-6": bad,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
         "status_ok": int(sum(1 for inf in infos if inf["status"] == 0)),
+        "steps_block_solver": len(lob),
         "steps_full_eig": int(sum(1 for inf in infos if inf["side_used"] == 3)),
-        "n_pos_last": int(infos[-1]["n_pos_full"] if infos[-1]["side_used"] == 3
-                          else infos[-1]["n_pos"]),
+        "steps_certified": int(sum(1 for inf in lob if inf["certified"] == 1)),
+        "n_pos_last": int(infos[-1]["pos_est"]),
         "full_eig": {"value": fe_rate, "unit": "projections/s", "method": "rocsolver_dsyevd",
-                     "samples": len(fe_idx)},
-        "speedup_vs_full_eig": value / fe_rate,
-        "rel_err_vs_full_eig_max": max(rel_vs_fe.values()) if rel_vs_fe else None,
+                     "samples": steps},
+        "speedup_vs_full_eig": (ok_steps / wall) / fe_rate,
+        "rel_err_vs_full_eig_max": max(rel_vs_fe),
+        "rel_err_step0_vs_closed_form": rel_step0,
         "rel_err_vs_oracle_max": max(rel_oracle.values()) if rel_oracle else None,
-        "err_bound_rel_max": max(inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in infos
-                                 if inf["side_used"] != 3) if any(inf["side_used"] != 3 for inf in infos) else 0.0,
+        "err_bound_rel_max": max((inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in lob),
+                                 default=0.0),
+        "certificate": {"launch_groups": cert["launches"],
+                        "ms_per_projection": cert["ms"] / max(1, kt_steps),
+                        "ms_per_certificate": cert["ms"] / max(1, cert["launches"])},
         "roofline": roofline(fams, prec, wl), "product_roofline": product_roofline(fams_all, prec),
         "cpu_baseline": cpu, "kernels": kernels_table(fams_all),
-        "kernels_note": f"every family timed on an untimed pass over {min(steps, KERNEL_TABLE_STEPS)} "
-                        f"of the timed matrices; the timed region times only '{TIMED_FAMILY}'",
+        "kernels_note": f"every family timed on an untimed pass over the first {kt_steps} "
+                        f"matrices; the timed region times only '{timed_family}', the "
+                        f"hand-written family with the most time in that pass",
         "dominant_family_untimed_pass": max(FAMILIES, key=lambda f: fams_all[f]["ms"]),
     }
     proj.close()
@@ -524,7 +553,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="n1000_warm_seq",
+    ap.add_argument("--workload", default="n4000_mixed",
                     choices=["n1000_warm_seq", "n4000_mixed", "n4000_mixed_iid", "batched512",
                              "serving_mix"])
     ap.add_argument("--serve-seconds", type=float, default=0.25,

@@ -11,8 +11,16 @@
  *     ||Vt Lt Vt^T - Pi(A)||_F^2 <= 2 ||R||_F^2 + ||Pi(Vt_perp^T A Vt_perp)||_F^2
  *
  * where (Vt, Lt) are the positive Ritz pairs with Lt = Vt^T A Vt and
- * R = A Vt - Vt Lt.  The last term is reported as an estimate (tail_est,
- * certified = 0); §5.2 and §6 treat it the same way.
+ * R = A Vt - Vt Lt.  The last term (the tail) is certified by default: an
+ * FP64 Cholesky factorization of (delta - eta) I - P A P + c Vt Vt^T,
+ * P = I - Vt Vt^T, completes only if every eigenvalue of Vt_perp^T A Vt_perp
+ * is below delta (eta bounds the rounding of forming and factoring the
+ * matrix), and then tail <= sqrt(n - m~) delta (certified = 1).  §5.2 leaves
+ * this term out of its experiments.  A certificate that fails leaves the
+ * tail unbounded (tail_est = err_bound = +inf, PSDP_NOT_CONVERGED, or the
+ * exact path with fallback_full).  Without the certificate (certify = 0) the
+ * tail is estimated from the largest non-positive Ritz pair (theta_g, r_g)
+ * as sqrt(n - m~) max(theta_g + r_g, 0) (certified = 0).
  *
  * Conventions for every entry point:
  *   - matrices are column-major (Fortran order) with a leading dimension;
@@ -82,7 +90,11 @@ typedef struct {
                             /* correction sweep (default 1)                       */
     int ladder;             /* on a stalled low-precision residual move BF16 ->   */
                             /* FP32 -> FP64 products (default 1); 0 = raw path    */
-    int certify;            /* reserved, must be 0                                */
+    int certify;            /* 1 (default): certify the tail term (FP64 Cholesky */
+                            /* of (delta - eta) I - P A P + c Vt Vt^T); a failed */
+                            /* certificate makes the result PSDP_NOT_CONVERGED,  */
+                            /* or the full eig when fallback_full is set; 0: the */
+                            /* tail is the estimate from the guard Ritz pair     */
     unsigned long long seed;/* counter-based RNG seed (cold start, expansion);    */
                             /* the stream also takes the handle's call count, so */
                             /* repeated cold starts draw different columns       */
@@ -105,12 +117,24 @@ typedef struct {
                             /* §5.2, residual and tail terms) exceeds             */
                             /* bound_rel_max * ||Pi||_F is replaced by the full   */
                             /* eig (PSDP_FELL_BACK_FULL_EIG); 0 = off (default)   */
+    double certify_delta;   /* certificate threshold delta (> 0); 0 (default) =   */
+                            /* sqrt(2 max(m~, 1)) tol / sqrt(n), so that the      */
+                            /* certified tail is at most the residual part the    */
+                            /* stopping rule allows; raised to 4 eta when the     */
+                            /* rounding margin eta is larger                      */
+    int warm_side;          /* side the warm-start block V belongs to, PSDP_SIDE_ */
+                            /* POS or _NEG (the previous call's info.block_side); */
+                            /* a call that resolves to the other side starts      */
+                            /* cold; PSDP_SIDE_AUTO (default): the side this call */
+                            /* uses                                               */
 } psdp_options;
 
 typedef struct {
     double err_bound;   /* sqrt(2 ||R||_F^2 + tail_est^2), absolute Frobenius     */
     double res_fro;     /* ||R||_F of the final positive Ritz pairs (FP64)        */
-    double tail_est;    /* estimate of ||Pi(Vt_perp^T A Vt_perp)||_F (uncertified) */
+    double tail_est;    /* bound on ||Pi(Vt_perp^T A Vt_perp)||_F: sqrt(n - m~)   */
+                        /* cert_delta when certified, +inf when the certificate  */
+                        /* failed, the guard estimate when certify = 0           */
     double pi_fro;      /* ||Pi||_F of the returned projection (host estimate     */
                         /* sqrt(sum lt^2) for the positive side)                  */
     double theta_guard; /* largest non-positive Ritz value kept in the block      */
@@ -119,11 +143,22 @@ typedef struct {
     int m_out;          /* columns returned in V                                  */
     int iters;          /* LOBPCG iterations (all phases)                         */
     int side_used;      /* PSDP_SIDE_POS, _NEG or _FULL                           */
-    int certified;      /* 1 if the tail term is proven zero (not implemented: 0) */
+    int certified;      /* 1: the tail term is certified (the Cholesky            */
+                        /* certificate succeeded, or m~ = n, or the exact path   */
+                        /* was used); 0: tail_est is an estimate                 */
     int status;         /* same as the return value                               */
     int expansions;     /* block expansions performed                             */
     int prec_final;     /* product precision in the last LOBPCG phase             */
     int n_pos_full;     /* eigenvalue count of X above 0 (full eig path) or -1    */
+    int pos_est;        /* estimated count of positive eigenvalues of X, the      */
+                        /* pos_hint for the next call on a nearby matrix (paper   */
+                        /* §6 side rule): n_pos (positive side), n - n_pos        */
+                        /* (negative side) or n_pos_full (exact path)             */
+    int block_side;     /* side the returned V belongs to (PSDP_SIDE_POS or _NEG; */
+                        /* the exact path returns leading pairs of X: POS), the   */
+                        /* warm_side of the next call                             */
+    double cert_delta;  /* threshold the certificate proved (NaN when not run)    */
+    double cert_eta;    /* its rounding margin eta (NaN when not run)             */
 } psdp_info;
 
 /* Fill *opt with the defaults documented above. */
@@ -237,6 +272,23 @@ psdp_status psdp_full_eig_project(psdp_handle h, int n, const double *X, int ldx
 psdp_status psdp_block_product(psdp_handle h, int n, const double *X, int ldx,
                                const double *S, int lds, int k, int prec,
                                double *Y, int ldy);
+
+/* The tail certificate on its own (paper §5.2, Thm `bound`, second term
+ * ||Pi(V_perp^T A V_perp)||_F with A = sym(X)): proves that every eigenvalue
+ * of V_perp^T A V_perp is below delta through an FP64 Cholesky factorization
+ * of (delta - eta) I - P A P + c V V^T, P = I - V V^T, c = ||A||_F / sqrt(n).
+ *   X, ldx     n x n symmetric, lower triangle read (device)
+ *   V, ldv     n x m with orthonormal columns (device), 0 <= m <= 48
+ *   delta      > 0
+ *   certified  (host) 1: proven; 0: a pivot was not positive (some eigenvalue
+ *              of V_perp^T A V_perp is at least about delta)
+ *   delta_eff  (host, may be NULL) threshold proven: max(delta, 4 eta)
+ *   eta        (host, may be NULL) bound on the rounding of forming and
+ *              factoring the matrix
+ * PSDP_ERR_NUMERICAL for non-finite X.  Synchronises the handle's stream. */
+psdp_status psdp_certify_tail(psdp_handle h, int n, const double *X, int ldx, const double *V,
+                              int ldv, int m, double delta, int *certified, double *delta_eff,
+                              double *eta);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop for many concurrent ADMM solves (paper §6: every

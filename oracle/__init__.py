@@ -169,5 +169,27 @@ def tail_exact(X, Vt) -> float:
     return float(np.sqrt(np.sum(pos * pos)))
 
 
+def complement_spectrum(X, Vt) -> np.ndarray:
+    """Eigenvalues (ascending) of Vt_perp^T X Vt_perp, the matrix whose
+    positive part is the last term of Thm `bound` (§5.2), for orthonormal
+    columns Vt (n x m).
+
+    With P = I - Vt Vt^T and s = 2 ||X||_F + 1, the matrix P X P - s Vt Vt^T
+    has spectrum eig(Vt_perp^T X Vt_perp) plus m copies of -s (range(Vt) is
+    invariant with eigenvalue -s, its complement carries the compression),
+    and -s lies below every eigenvalue of the compression; the m smallest
+    eigenvalues are dropped.
+    """
+    X = symmetrize_lower(X)
+    Vt = np.asarray(Vt, dtype=np.float64).reshape(X.shape[0], -1)
+    n, m = X.shape[0], Vt.shape[1]
+    s = 2.0 * float(np.linalg.norm(X)) + 1.0
+    P = np.eye(n) - Vt @ Vt.T
+    M = P @ X @ P - s * (Vt @ Vt.T)
+    M = 0.5 * (M + M.T)
+    lam, _ = eigh(M)
+    return lam[m:]
+
+
 __all__ = ["build", "eigh", "project", "true_error", "rel_error", "tail_exact",
-           "symmetrize_lower", "num_threads", "OracleError"]
+           "complement_spectrum", "symmetrize_lower", "num_threads", "OracleError"]

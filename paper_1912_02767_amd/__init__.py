@@ -27,7 +27,7 @@ from ._abi import (PREC_BF16, PREC_FP32, PREC_FP64, PSDP_ERR_CAPACITY,
                    SIDE_POS, LibraryMissing, load, status_str)
 
 __all__ = ["Projector", "Session", "Server", "Result", "ServedResult", "PsdpError", "load",
-           "status_str", "fortran", "auto_side", "PREC", "SIDE", "LibraryMissing"]
+           "status_str", "fortran", "PREC", "SIDE", "LibraryMissing"]
 
 PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 SIDE = {"auto": SIDE_AUTO, "pos": SIDE_POS, "neg": SIDE_NEG, "full": SIDE_FULL}
@@ -71,7 +71,8 @@ class Result:
 
 def _opts(lib, side="pos", prec="fp64", tol=0.0, max_iter=300, refine=True,
           ladder=True, seed=None, side_threshold=1.0 / 3.0, expand_cols=0,
-          pos_hint=-1, fallback_full=False, block_guard=4, bound_rel_max=0.0):
+          pos_hint=-1, fallback_full=False, block_guard=4, bound_rel_max=0.0,
+          certify=True, certify_delta=0.0, warm_side="auto"):
     o = _abi.Options()
     lib.psdp_default_options(ctypes.byref(o))
     o.side = SIDE[side] if isinstance(side, str) else int(side)
@@ -88,6 +89,9 @@ def _opts(lib, side="pos", prec="fp64", tol=0.0, max_iter=300, refine=True,
     o.fallback_full = 1 if fallback_full else 0
     o.block_guard = int(block_guard)
     o.bound_rel_max = float(bound_rel_max)
+    o.certify = 1 if certify else 0
+    o.certify_delta = float(certify_delta)
+    o.warm_side = SIDE[warm_side] if isinstance(warm_side, str) else int(warm_side)
     return o
 
 
@@ -138,7 +142,8 @@ class Projector:
                 seed=None, pos_hint: int = -1, expand_cols: int = 0, fallback_full: bool = False,
                 side_threshold: float = 1.0 / 3.0, block_guard: int = 4, V_buf=None,
                 Pi_out=None, lam_buf=None, raise_on_error: bool = True,
-                bound_rel_max: float = 0.0) -> Result:
+                bound_rel_max: float = 0.0, certify: bool = True, certify_delta: float = 0.0,
+                warm_side="auto") -> Result:
         """Pi(X) with LOBPCG on one spectral side (psdp_project).
 
         V: optional warm start (n x k).  V_buf: optional column-major
@@ -164,7 +169,8 @@ class Projector:
         Pi = Pi_out if Pi_out is not None else _empty_f(n, n, Xf.device)
         m_io = ctypes.c_int(k)
         opt = _opts(self.lib, side, prec, tol, max_iter, refine, ladder, seed, side_threshold,
-                    expand_cols, pos_hint, fallback_full, block_guard, bound_rel_max)
+                    expand_cols, pos_hint, fallback_full, block_guard, bound_rel_max, certify,
+                    certify_delta, warm_side)
         info = _abi.Info()
         rc = self.lib.psdp_project(self._h, n, ctypes.c_void_p(Xf.data_ptr()), Xf.stride(1),
                                    ctypes.c_void_p(V_buf.data_ptr()), V_buf.stride(1), cap,
@@ -260,6 +266,25 @@ class Projector:
             raise PsdpError(rc, "psdp_block_product")
         return Y
 
+    def certify_tail(self, X, V, delta: float):
+        """(certified, delta_eff, eta) of the tail certificate alone
+        (psdp_certify_tail): every eigenvalue of V_perp^T sym(X) V_perp is
+        below delta_eff when certified."""
+        Xf = self._check_matrix(X)
+        n = Xf.shape[0]
+        self._sync_stream()
+        m = 0 if V is None else V.shape[1]
+        Vf = fortran(V) if m else None
+        ok = ctypes.c_int(0)
+        de, eta = ctypes.c_double(), ctypes.c_double()
+        rc = self.lib.psdp_certify_tail(self._h, n, ctypes.c_void_p(Xf.data_ptr()), Xf.stride(1),
+                                        ctypes.c_void_p(Vf.data_ptr() if m else 0),
+                                        Vf.stride(1) if m else n, m, float(delta),
+                                        ctypes.byref(ok), ctypes.byref(de), ctypes.byref(eta))
+        if rc < 0:
+            raise PsdpError(rc, "psdp_certify_tail")
+        return bool(ok.value), de.value, eta.value
+
     # ------------------------------------------------------------ profiling
     def profile_enable(self, on: bool = True):
         self.lib.psdp_profile_enable(self._h, 1 if on else 0)
@@ -324,29 +349,13 @@ class Projector:
         return {"launches": n.value, "ms": ms.value, "bytes": by.value, "flops": fl.value}
 
 
-def auto_side(n: int, pos_hint: int, m_cap: int, block_guard: int = 4,
-              threshold: float = 1.0 / 3.0, max_block: int = 48) -> str:
-    """The AUTO side rule of psdp_project (paper §6 plus the block cost rule):
-    the side with fewer than threshold * n eigenvalues, if the block it needs
-    fits min(m_cap, 48) columns and 6 * block < n; else the full eig."""
-    if pos_hint < 0:
-        return "full"
-    if pos_hint < threshold * n:
-        side, est = "pos", pos_hint
-    elif n - pos_hint < threshold * n:
-        side, est = "neg", n - pos_hint
-    else:
-        return "full"
-    need = est + max(block_guard, math.ceil(0.2 * est))
-    if need > min(m_cap, max_block) or 6 * need >= n:
-        return "full"
-    return side
-
-
 class Session:
     """Warm-start memory of one matrix sequence (one PSD variable of an ADMM
-    solve): the Ritz block stays on the device between calls and the side is
-    chosen from the previous call's inertia (paper §6)."""
+    solve): the Ritz block stays on the device between calls (paper §5.1:
+    LOBPCG allows warm starting).  The side is chosen by the library's AUTO
+    rule (paper §6) from the previous call's inertia estimate; this class
+    only carries the library's own outputs (info.pos_est, info.block_side)
+    into the next call."""
 
     def __init__(self, projector: Projector, n: int, m_cap: int = 64, prec="fp64",
                  tol: float = 0.0, side="auto", pos_hint: int = -1, **kw):
@@ -361,33 +370,19 @@ class Session:
         self.V_buf = _empty_f(n, m_cap, torch.device("cuda", projector.device))
         self.lam_buf = torch.empty(m_cap, dtype=torch.float64, device=self.V_buf.device)
         self.m = 0
-        self.last_side = None
+        self.block_side = SIDE_AUTO
         self.pos_hint = pos_hint
         self.calls = 0
 
     def project(self, X, Pi_out=None) -> Result:
-        side = self.side_mode
-        hint = self.pos_hint
-        if side == "auto":
-            # resolve here (same rule as the library's AUTO side) so that a
-            # side switch drops the other side's block
-            side = auto_side(self.n, hint, self.m_cap, self.kw.get("block_guard", 4))
-        warm = self.m if (self.last_side == side and side != "full") else 0
-        res = self.p.project(X, V=warm, side=side, prec=self.prec, tol=self.tol,
-                             pos_hint=hint, V_buf=self.V_buf, lam_buf=self.lam_buf,
-                             Pi_out=Pi_out, **self.kw)
+        res = self.p.project(X, V=self.m, side=self.side_mode, prec=self.prec, tol=self.tol,
+                             pos_hint=self.pos_hint, V_buf=self.V_buf, lam_buf=self.lam_buf,
+                             Pi_out=Pi_out, warm_side=self.block_side, **self.kw)
         info = res.info
-        if info["side_used"] == SIDE_FULL:
-            # the full path returns the positive eigenpairs (up to m_cap):
-            # they warm-start a later positive-side call
-            self.pos_hint = info["n_pos_full"]
+        if res.status >= 0:
             self.m = info["m_out"]
-            self.last_side = "pos"
-        else:
-            self.m = info["m_out"]
-            self.last_side = "pos" if info["side_used"] == SIDE_POS else "neg"
-            np_side = info["n_pos"]
-            self.pos_hint = np_side if self.last_side == "pos" else self.n - np_side
+            self.block_side = info["block_side"]
+            self.pos_hint = info["pos_est"]
         self.calls += 1
         return res
 

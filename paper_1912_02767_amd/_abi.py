@@ -30,7 +30,7 @@ EXPORTED = [
     "psdp_server_open_session", "psdp_server_close_session", "psdp_server_submit",
     "psdp_server_wait", "psdp_server_drain", "psdp_server_session_block",
     "psdp_server_stats_get", "psdp_server_stats_reset", "psdp_full_eig_project_batched",
-    "psdp_profile_filter",
+    "psdp_profile_filter", "psdp_certify_tail",
 ]
 
 
@@ -52,6 +52,8 @@ class Options(ctypes.Structure):
         ("batch_variant", ctypes.c_int),
         ("batch_graph", ctypes.c_int),
         ("bound_rel_max", ctypes.c_double),
+        ("certify_delta", ctypes.c_double),
+        ("warm_side", ctypes.c_int),
     ]
 
 
@@ -72,6 +74,10 @@ class Info(ctypes.Structure):
         ("expansions", ctypes.c_int),
         ("prec_final", ctypes.c_int),
         ("n_pos_full", ctypes.c_int),
+        ("pos_est", ctypes.c_int),
+        ("block_side", ctypes.c_int),
+        ("cert_delta", ctypes.c_double),
+        ("cert_eta", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -174,6 +180,9 @@ def load():
     lib.psdp_block_product.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, vp, ctypes.c_int]
     lib.psdp_block_product.restype = ctypes.c_int
+    lib.psdp_certify_tail.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
+                                      ctypes.c_int, ctypes.c_double, ip, dp, dp]
+    lib.psdp_certify_tail.restype = ctypes.c_int
     lib.psdp_status_str.argtypes = [ctypes.c_int]
     lib.psdp_status_str.restype = ctypes.c_char_p
     lib.psdp_profile_enable.argtypes = [vp, ctypes.c_int]

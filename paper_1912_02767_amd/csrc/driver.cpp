@@ -30,6 +30,7 @@
 
 #include "../../include/psdp.h"
 #include "batched.h"
+#include "cert.h"
 #include "common.h"
 #include "internal.h"
 
@@ -134,6 +135,13 @@ struct psdp_handle_s {
   psdp::BatchEngine* batch = nullptr;
   char* beig = nullptr;  // batched exact path scratch
   size_t beig_bytes = 0;
+  // tail certificate: M (L x L FP64), partial sums, device state
+  char* cert_base = nullptr;
+  int cert_L = 0;
+  double* cert_M = nullptr;
+  double* cert_part = nullptr;
+  psdp::CertState* cert_dev = nullptr;
+  psdp::CertState* cert_host = nullptr;  // pinned
 };
 
 namespace {
@@ -646,6 +654,99 @@ struct Solver {
   }
 };
 
+
+psdp_status ensure_cert(psdp_handle h, int L) {
+  if (h->cert_base && h->cert_L >= L) return PSDP_OK;
+  if (!h->cert_host &&
+      hipHostMalloc((void**)&h->cert_host, sizeof(CertState), hipHostMallocDefault) != hipSuccess) {
+    h->cert_host = nullptr;
+    return PSDP_ERR_OUT_OF_MEMORY;
+  }
+  if (h->cert_base) {
+    (void)hipStreamSynchronize(h->stream);
+    hipFree(h->cert_base);
+    h->cert_base = nullptr;
+    h->cert_L = 0;
+  }
+  const int T = L / kCertTile;
+  const size_t oM = 0;
+  const size_t oP = align_up(oM + sizeof(double) * (size_t)L * L, 256);
+  const size_t oS = align_up(oP + sizeof(double) * (size_t)(3 * T + 8), 256);
+  const size_t total = align_up(oS + sizeof(CertState), 256);
+  char* base = nullptr;
+  if (hipMalloc(&base, total) != hipSuccess) return PSDP_ERR_OUT_OF_MEMORY;
+  h->cert_base = base;
+  h->cert_L = L;
+  h->cert_M = (double*)(base + oM);
+  h->cert_part = (double*)(base + oP);
+  h->cert_dev = (CertState*)(base + oS);
+  return PSDP_OK;
+}
+
+// Tail certificate (paper §5.2, Thm `bound`: the term ||Pi(Vt_perp^T A
+// Vt_perp)||_F) for the first mt columns of the block X, the positive Ritz
+// vectors of A = s sym(X) held in A64: an FP64 Cholesky factorization of
+// (delta - eta) I - P A P + c Vt Vt^T, P = I - Vt Vt^T.  On success every
+// eigenvalue of Vt_perp^T A Vt_perp is below out->delta_eff.  Clobbers the
+// work columns AS (W = A Vt), S1 (U), G and T (Vt^T W, Vt^T Vt) and the
+// split-K partials; X and A64 are only read.
+psdp_status run_certificate(psdp_handle h, int n, int mt, double fro2, double delta, int* certified,
+                            CertState* out) {
+  Workspace& w = h->ws;
+  hipStream_t s = h->stream;
+  const int L = w.L, NC = w.NC;
+  if (mt < 0 || mt > w.MC) return PSDP_ERR_INVALID_ARG;
+  psdp_status ps = ensure_cert(h, L);
+  if (ps != PSDP_OK) return ps;
+  const double nn = n;
+  CertState* hc = h->cert_host;
+  std::memset(hc, 0, sizeof(CertState));
+  hc->delta = delta;
+  hc->fro_a = std::sqrt(std::max(fro2, 0.0));
+  hc->c = fro2 > 0.0 ? std::sqrt(fro2 / nn) : 1.0;
+  hc->n = n;
+  hc->L = L;
+  hc->mt = mt;
+  {
+    // algorithmic work: W = A Vt (2 n^2 mt), the rank-2 mt formation of the
+    // lower triangle (2 n^2 mt), the factorization (n^3 / 3); bytes: A read
+    // twice (full, then its lower triangle), M written and read (lower)
+    ProfScope pscope(h, "cert", 20.0 * nn * nn, 4.0 * nn * nn * mt + nn * nn * nn / 3.0);
+    if (mt > 0) {
+      ProductArgs pa{};
+      pa.A = w.A64; pa.lda = L; pa.n = n; pa.prec = 0;
+      pa.S = w.X; pa.lds = L; pa.Y = w.AS; pa.ldy = L;
+      pa.cols_dev = nullptr; pa.cols_max = mt; pa.stop = nullptr;
+      pa.partial = w.ppart; pa.partial_bytes = w.ppart_bytes; pa.max_slices = kProductSlices;
+      HIP_TRY(launch_product(pa, s));
+      int nblk = 0;
+      const ColMap vx = colmap_seg(w.X, mt, L), wa = colmap_seg(w.AS, mt, L);
+      HIP_TRY(launch_gram_partial(vx, &wa, nullptr, mt, nullptr, mt, n, w.Gpart, NC, (size_t)NC * NC,
+                                  &nblk, nullptr, s));
+      HIP_TRY(launch_reduce_partials(w.Gpart, nblk, (size_t)NC * NC, NC, nullptr, mt, nullptr, mt,
+                                     w.G, NC, nullptr, s));
+      HIP_TRY(launch_gram_partial(vx, nullptr, nullptr, mt, nullptr, mt, n, w.Gpart, NC,
+                                  (size_t)NC * NC, &nblk, nullptr, s));
+      HIP_TRY(launch_reduce_partials(w.Gpart, nblk, (size_t)NC * NC, NC, nullptr, mt, nullptr, mt,
+                                     w.T, NC, nullptr, s));
+  }
+    HIP_TRY(hipMemcpyAsync(h->cert_dev, hc, sizeof(CertState), hipMemcpyHostToDevice, s));
+    const int T = L / kCertTile;
+    double* prep_part = h->cert_part;
+    double* diag_part = h->cert_part + 2 * T;
+    HIP_TRY(launch_cert_prep(w.X, w.AS, L, w.G, NC, mt, n, L, hc->c, w.S1, prep_part, s));
+    HIP_TRY(launch_cert_form(w.A64, L, w.X, w.S1, L, mt, n, L, h->cert_M, diag_part, s));
+    HIP_TRY(launch_cert_shift(w.T, NC, prep_part, mt > 0 ? T : 0, diag_part, h->cert_M, h->cert_dev,
+                              s));
+    HIP_TRY(launch_cert_chol(h->cert_M, L, h->cert_dev, s));
+  }
+  HIP_TRY(hipMemcpyAsync(hc, h->cert_dev, sizeof(CertState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = *hc;
+  *certified = (hc->fail == 0) ? 1 : 0;
+  return PSDP_OK;
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -677,7 +778,7 @@ void psdp_default_options(psdp_options* o) {
   o->max_iter = 300;
   o->refine_fp64 = 1;
   o->ladder = 1;
-  o->certify = 0;
+  o->certify = 1;
   o->seed = 0x1912276700000000ull;
   o->side_threshold = 1.0 / 3.0;
   o->expand_cols = 0;
@@ -687,6 +788,8 @@ void psdp_default_options(psdp_options* o) {
   o->batch_variant = -1;
   o->batch_graph = 1;
   o->bound_rel_max = 0.0;
+  o->certify_delta = 0.0;
+  o->warm_side = PSDP_SIDE_AUTO;
 }
 
 psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t* bytes) {
@@ -747,6 +850,8 @@ psdp_status psdp_destroy(psdp_handle h) {
   if (h->rb) rocblas_destroy_handle(h->rb);
   batch_engine_free(h->batch);
   if (h->beig) hipFree(h->beig);
+  if (h->cert_base) hipFree(h->cert_base);
+  if (h->cert_host) hipHostFree(h->cert_host);
   delete h;
   return PSDP_OK;
 }
@@ -914,6 +1019,42 @@ extern "C" psdp_status psdp_block_product(psdp_handle h, int n, const double* X,
   return PSDP_OK;
 }
 
+// ------------------------------------------------------ tail certificate ---
+extern "C" psdp_status psdp_certify_tail(psdp_handle h, int n, const double* X, int ldx,
+                                         const double* V, int ldv, int m, double delta,
+                                         int* certified, double* delta_eff, double* eta) {
+  if (!h || n < 1 || !X || ldx < n || m < 0 || m > kMaxM || m > n || (m > 0 && (!V || ldv < n)) ||
+      !(delta > 0.0) || !(delta < INFINITY) || !certified)
+    return PSDP_ERR_INVALID_ARG;
+  if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
+  psdp_status ps = ensure_workspace(h, n, std::max(m, 1), 0);
+  if (ps != PSDP_OK) return ps;
+  ps = ensure_pinned(h, 64);
+  if (ps != PSDP_OK) return ps;
+  Workspace& w = h->ws;
+  hipStream_t s = h->stream;
+  HIP_TRY(hipMemsetAsync(w.nonfinite, 0, sizeof(int), s));
+  int nb = 0;
+  HIP_TRY(launch_ingest(X, ldx, n, 1.0, w.A64, w.L, w.L, w.Alp, 0, w.fro_part, w.nonfinite, s, &nb));
+  HIP_TRY(launch_reduce_sum(w.fro_part, nb, w.scal, s));
+  HIP_TRY(hipMemcpyAsync(h->h_pin, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h->h_pin + 1, w.nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const double fro2 = h->h_pin[0];
+  int nonfin = 0;
+  std::memcpy(&nonfin, h->h_pin + 1, sizeof(int));
+  if (nonfin || !std::isfinite(fro2)) return PSDP_ERR_NUMERICAL;
+  if (m > 0) HIP_TRY(launch_copy_cols(V, ldv, w.X, w.L, n, m, s));
+  CertState cs{};
+  int ok = 0;
+  ps = run_certificate(h, n, m, fro2, delta, &ok, &cs);
+  if (ps != PSDP_OK) return ps;
+  *certified = ok;
+  if (delta_eff) *delta_eff = cs.delta_eff;
+  if (eta) *eta = cs.eta;
+  return PSDP_OK;
+}
+
 // ---------------------------------------------------------- single cone ---
 static void fill_info_defaults(psdp_info* info) {
   std::memset(info, 0, sizeof(*info));
@@ -923,6 +1064,10 @@ static void fill_info_defaults(psdp_info* info) {
   info->pi_fro = NAN;
   info->theta_guard = NAN;
   info->n_pos_full = -1;
+  info->pos_est = -1;
+  info->block_side = PSDP_SIDE_POS;
+  info->cert_delta = NAN;
+  info->cert_eta = NAN;
 }
 
 // Exact projection of many cones (n <= 256) through zero-padded buckets of
@@ -1065,7 +1210,8 @@ extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int*
   if (count == 0) return PSDP_OK;
   if (!n || !X || !V || !m_cap || !m_inout || !lambda || !Pi || !info) return PSDP_ERR_INVALID_ARG;
   if (opt.side < 0 || opt.side > 2 || opt.prec < 0 || opt.prec > 2) return PSDP_ERR_INVALID_ARG;
-  if (opt.max_iter < 1 || opt.certify != 0 || opt.expand_cols < 0 || opt.batch_variant < -1)
+  if (opt.max_iter < 1 || opt.certify < 0 || opt.certify > 1 || opt.expand_cols < 0 ||
+      opt.batch_variant < -1)
     return PSDP_ERR_INVALID_ARG;
   if (opt.prec == PSDP_PREC_BF16) opt.prec = PSDP_PREC_FP32;
   for (int i = 0; i < count; ++i) {
@@ -1179,8 +1325,9 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   if (ldx < n || ldv < n || ldpi < n || m_cap < 1) return PSDP_ERR_INVALID_ARG;
   if (*m_inout < 0 || *m_inout > m_cap) return PSDP_ERR_INVALID_ARG;
   if (opt.side < 0 || opt.side > 3 || opt.prec < 0 || opt.prec > 2) return PSDP_ERR_INVALID_ARG;
-  if (opt.max_iter < 1 || opt.certify != 0 || !(opt.side_threshold > 0.0) ||
-      opt.side_threshold > 0.5 || opt.expand_cols < 0 || opt.pos_hint > n)
+  if (opt.max_iter < 1 || opt.certify < 0 || opt.certify > 1 || !(opt.side_threshold > 0.0) ||
+      opt.side_threshold > 0.5 || opt.expand_cols < 0 || opt.pos_hint > n ||
+      !(opt.certify_delta >= 0.0) || opt.warm_side < 0 || opt.warm_side > 2)
     return PSDP_ERR_INVALID_ARG;
   if ((const void*)Pi == (const void*)X) return PSDP_ERR_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
@@ -1198,16 +1345,20 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     info->side_used = PSDP_SIDE_FULL;
     info->n_pos = npos;
     info->n_pos_full = npos;
+    info->pos_est = npos;
+    info->block_side = PSDP_SIDE_POS;
     info->m_out = mo;
     info->err_bound = 0.0;
     info->res_fro = 0.0;
     info->tail_est = 0.0;
+    info->certified = 1;
     info->status = PSDP_FELL_BACK_FULL_EIG;
     return PSDP_FELL_BACK_FULL_EIG;
   }
   const double sign = (side == PSDP_SIDE_NEG) ? -1.0 : 1.0;
-  // ---- block size
+  // ---- block size; a warm block of the other side is not used
   int m_in = *m_inout;
+  if (opt.warm_side != PSDP_SIDE_AUTO && opt.warm_side != side) m_in = 0;
   int m0 = m_in;
   if (m0 == 0) {
     int est = -1;
@@ -1426,8 +1577,11 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     info->side_used = PSDP_SIDE_FULL;
     info->n_pos = npos;
     info->n_pos_full = npos;
+    info->pos_est = npos;
+    info->block_side = PSDP_SIDE_POS;
     info->m_out = mo;
     info->err_bound = 0.0; info->res_fro = 0.0; info->tail_est = 0.0;
+    info->certified = 1;
     info->iters = h->h_state->iter;
     info->expansions = expansions;
     info->status = PSDP_FELL_BACK_FULL_EIG;
@@ -1453,14 +1607,39 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   const int m = sv.m;
   int npos = st.npos_blk;
   double rfro = st.res_fro_pos;
+  // tail term ||Pi(Vt_perp^T A Vt_perp)||_F
   double tail = 0.0;
-  if (npos < m) {
-    double th_g = st.guard_theta, r_g = st.guard_res;
-    double delta = npos > 0 ? (st.theta_min_pos - th_g) : std::fabs(th_g);
-    double est = (delta > 0.0) ? th_g + r_g * r_g / delta : th_g + r_g;
-    tail = std::sqrt((double)(n - npos)) * std::max(est, 0.0);
-  } else if (m < n) {
-    tail = INFINITY;  // no non-positive pair in the block: nothing to estimate from
+  int certified = 0;
+  double cert_delta = NAN, cert_eta = NAN;
+  if (npos >= n) {
+    certified = 1;  // Vt spans the whole space: no complement
+  } else if (opt.certify) {
+    const double delta = opt.certify_delta > 0.0
+                             ? opt.certify_delta
+                             : std::sqrt(2.0 * std::max(npos, 1)) * tol / std::sqrt((double)n);
+    CertState cs{};
+    rc = run_certificate(h, n, npos, fro2, delta, &certified, &cs);
+    if (rc != PSDP_OK) { info->status = rc; return rc; }
+    cert_delta = cs.delta_eff;
+    cert_eta = cs.eta;
+    if (certified) tail = std::sqrt((double)(n - npos)) * cert_delta;
+  }
+  if (!certified && npos < n) {
+    if (opt.certify) {
+      tail = INFINITY;  // the certificate failed: the tail term is not bounded
+    } else if (npos < m) {
+      // estimate from the largest non-positive Ritz pair: its value plus its
+      // residual norm (an eigenvalue lies within r_g of theta_g)
+      tail = std::sqrt((double)(n - npos)) * std::max(st.guard_theta + st.guard_res, 0.0);
+    } else {
+      tail = INFINITY;  // no non-positive pair in the block to estimate from
+    }
+  }
+  // a certificate that was asked for and failed: positive eigenvalues of the
+  // complement may exceed the threshold, so the result is not converged
+  if (opt.certify && !certified) {
+    converged = false;
+    if (opt.fallback_full) return full_instead();
   }
   double bound = std::sqrt(2.0 * rfro * rfro + tail * tail);
   double sum_pos2 = 0.0;
@@ -1495,7 +1674,11 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   info->m_out = m;
   info->iters = st.iter;
   info->side_used = side;
-  info->certified = 0;
+  info->certified = certified;
+  info->cert_delta = cert_delta;
+  info->cert_eta = cert_eta;
+  info->pos_est = (side == PSDP_SIDE_POS) ? npos : n - npos;
+  info->block_side = side;
   info->expansions = expansions;
   info->prec_final = phase;
   info->status = converged ? PSDP_OK : PSDP_NOT_CONVERGED;

@@ -1,0 +1,445 @@
+// Certificate of the tail term of the a-posteriori bound (paper §5.2,
+// Thm `bound`): forming M = s I - P A P + c Vt Vt^T and its FP64 Cholesky
+// factorization on 64 x 64 tiles (see cert.h for what success proves).
+//
+// Rounding (Higham, Accuracy and Stability of Numerical Algorithms, Thm 10.3
+// and §3.5): a Cholesky factorization that completes with positive pivots
+// gives L L^T = M + dM with |dM| <= gamma_{L+1} |L| |L^T|, hence
+// ||dM||_2 <= gamma_{L+1} tr(M) / (1 - gamma_{L+1}); the factorization here
+// divides through a rounded reciprocal, one more rounding per entry, which
+// gamma_{L+3} covers.  The formation of M is bounded the same way from the
+// norms the kernels measure; eta is twice the sum of these terms.
+#include "cert.h"
+#include "common.h"
+
+namespace psdp {
+
+namespace {
+
+constexpr int kT = kCertTile;  // 64
+constexpr int kLd = kT + 1;     // LDS row stride of a row-major 64 x 64 tile
+
+__device__ inline bool cert_failed(const CertState* cs) {
+  return *(const volatile int*)&cs->fail != 0;
+}
+
+// lower-triangular tile index b -> (ii, jj), ii >= jj
+__device__ inline void tri_index(int b, int& ii, int& jj) {
+  int i = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= b) ++i;
+  while (i * (i + 1) / 2 > b) --i;
+  ii = i;
+  jj = b - i * (i + 1) / 2;
+}
+
+// Right-looking Cholesky of the lower triangle of the 64 x 64 tile held
+// row-major (stride 65) in LDS.  256 threads.  Returns false, on every
+// thread, when a pivot is not positive and finite.  On success the lower
+// triangle holds the factor (the strict upper triangle is left as it was).
+__device__ bool chol_tile_lds(double* a, double* dg) {
+  const int t = threadIdx.x, c = t & 63, i0 = t >> 6;
+  for (int j = 0; j < kT; ++j) {
+    __syncthreads();  // the previous step's update is visible
+    const double d = a[j * kLd + j];
+    if (!(d > 0.0) || !(d < INFINITY)) return false;  // same value on every thread
+    const double ljj = sqrt(d);
+    const double inv = 1.0 / ljj;
+    if (t > j && t < kT) a[t * kLd + j] *= inv;
+    if (t == 0) dg[j] = ljj;
+    __syncthreads();
+    if (c > j) {
+      const double lcj = a[c * kLd + j];
+#pragma unroll 4
+      for (int s = 0; s < kT / 4; ++s) {
+        const int i = i0 + 4 * s;
+        if (i >= c) a[i * kLd + c] = fma(-a[i * kLd + j], lcj, a[i * kLd + c]);
+      }
+    }
+  }
+  __syncthreads();
+  if (t < kT) a[t * kLd + t] = dg[t];
+  __syncthreads();
+  return true;
+}
+
+// tile (row block bi, column block bj) of column-major M <-> row-major LDS
+__device__ inline void load_tile(const double* M, int L, int bi, int bj, double* a) {
+  const int t = threadIdx.x;
+#pragma unroll 4
+  for (int u = 0; u < kT * kT / 256; ++u) {
+    const int e = t + 256 * u, r = e & 63, c = e >> 6;
+    a[r * kLd + c] = M[(size_t)(bi * kT + r) + (size_t)(bj * kT + c) * L];
+  }
+}
+
+__device__ inline void store_tile(double* M, int L, int bi, int bj, const double* a) {
+  const int t = threadIdx.x;
+#pragma unroll 4
+  for (int u = 0; u < kT * kT / 256; ++u) {
+    const int e = t + 256 * u, r = e & 63, c = e >> 6;
+    M[(size_t)(bi * kT + r) + (size_t)(bj * kT + c) * L] = a[r * kLd + c];
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ formation --
+// One workgroup per 64 rows; thread (r = t % 64, g = t / 64) computes the
+// columns q = g, g + 4, ... of row r:  U = W + (c/2) Vt - Vt H / 2.
+constexpr int kCertMaxM = kMaxM;
+
+__global__ __launch_bounds__(256) void k_cert_prep(const double* __restrict__ V,
+                                                   const double* __restrict__ W, int ld,
+                                                   const double* __restrict__ H, int ldh, int mt,
+                                                   int n, double c, double* __restrict__ U,
+                                                   double* __restrict__ part) {
+  __shared__ double hs[kCertMaxM * (kCertMaxM + 1)];
+  __shared__ double vs[kCertMaxM * kT];  // vs[p * 64 + r]
+  __shared__ double red[2 * 256];
+  const int t = threadIdx.x, r = t & 63, g = t >> 6;
+  const int row = blockIdx.x * kT + r;
+  const bool ok = row < n;
+  for (int e = t; e < mt * mt; e += 256) {
+    const int p = e % mt, q = e / mt;
+    hs[p * (kCertMaxM + 1) + q] = H[p + (size_t)q * ldh];
+  }
+  for (int e = t; e < mt * kT; e += 256) {
+    const int rr = e & 63, p = e >> 6;
+    const int rw = blockIdx.x * kT + rr;
+    vs[p * kT + rr] = (rw < n) ? V[rw + (size_t)p * ld] : 0.0;
+  }
+  __syncthreads();
+  double su = 0.0, sw = 0.0;
+  for (int q = g; q < mt; q += 4) {
+    const double w = ok ? W[row + (size_t)q * ld] : 0.0;
+    double s = 0.0;
+    for (int p = 0; p < mt; ++p) s = fma(vs[p * kT + r], hs[p * (kCertMaxM + 1) + q], s);
+    const double u = ok ? (w + 0.5 * c * vs[q * kT + r]) - 0.5 * s : 0.0;
+    U[row + (size_t)q * ld] = u;
+    su = fma(u, u, su);
+    sw = fma(w, w, sw);
+  }
+  red[t] = su;
+  red[256 + t] = sw;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      red[t] += red[t + s];
+      red[256 + t] += red[256 + t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part[2 * blockIdx.x] = red[0];
+    part[2 * blockIdx.x + 1] = red[256];
+  }
+}
+
+// M0 = -A + [Vt U] [U Vt]^T on lower tiles; thread (tr = t % 16, tc = t / 16)
+// owns rows 4 tr .. 4 tr + 3 and columns 4 tc .. 4 tc + 3 of the tile.  The
+// rank-2m~ inner dimension is staged in LDS in chunks of 32, k-major.
+constexpr int kFK = 32;
+
+__global__ __launch_bounds__(256) void k_cert_form(const double* __restrict__ A, int lda,
+                                                   const double* __restrict__ V,
+                                                   const double* __restrict__ U, int ld, int mt,
+                                                   int n, int L, double* __restrict__ M,
+                                                   double* __restrict__ diag_part) {
+  __shared__ __align__(16) double pt[kFK * kT];
+  __shared__ __align__(16) double qt[kFK * kT];
+  __shared__ double red[256];
+  int bi, bj;
+  tri_index(blockIdx.x, bi, bj);
+  const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
+  const int i0 = bi * kT, j0 = bj * kT;
+  double acc[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a][b] = -A[(size_t)(i0 + 4 * tr + a) + (size_t)(j0 + 4 * tc + b) * lda];
+  const int K = 2 * mt;
+  for (int k0 = 0; k0 < K; k0 += kFK) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kFK * kT / 256; ++u) {
+      const int e = t + 256 * u, r = e & 63, kk = e >> 6, k = k0 + kk;
+      double pv = 0.0, qv = 0.0;
+      if (k < mt) {
+        pv = V[(size_t)(i0 + r) + (size_t)k * ld];
+        qv = U[(size_t)(j0 + r) + (size_t)k * ld];
+      } else if (k < K) {
+        pv = U[(size_t)(i0 + r) + (size_t)(k - mt) * ld];
+        qv = V[(size_t)(j0 + r) + (size_t)(k - mt) * ld];
+      }
+      pt[kk * kT + r] = pv;
+      qt[kk * kT + r] = qv;
+    }
+    __syncthreads();
+    const int kn = min(kFK, K - k0);
+    for (int kk = 0; kk < kn; ++kk) {
+      const double2 p01 = *(const double2*)&pt[kk * kT + 4 * tr];
+      const double2 p23 = *(const double2*)&pt[kk * kT + 4 * tr + 2];
+      const double2 q01 = *(const double2*)&qt[kk * kT + 4 * tc];
+      const double2 q23 = *(const double2*)&qt[kk * kT + 4 * tc + 2];
+      const double p[4] = {p01.x, p01.y, p23.x, p23.y};
+      const double q[4] = {q01.x, q01.y, q23.x, q23.y};
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a][b] = fma(p[a], q[b], acc[a][b]);
+    }
+  }
+  double dsum = 0.0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = i0 + 4 * tr + a, j = j0 + 4 * tc + b;
+      double v = acc[a][b];
+      if (i >= n || j >= n) v = (i == j) ? 1.0 : 0.0;
+      else if (i == j) dsum += v;
+      M[(size_t)i + (size_t)j * L] = v;
+    }
+  if (bi == bj) {
+    red[t] = dsum;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    if (t == 0) diag_part[bi] = red[0];
+  }
+}
+
+// ------------------------------------------------------------- margins ---
+__device__ inline double gam(double k) {
+  const double u = 1.1102230246251565e-16;  // 2^-53
+  return k * u / (1.0 - k * u);
+}
+
+__global__ __launch_bounds__(256) void k_cert_shift(const double* __restrict__ G, int ldg,
+                                                    const double* __restrict__ prep_part, int nprep,
+                                                    const double* __restrict__ diag_part,
+                                                    double* __restrict__ M, CertState* cs) {
+  __shared__ double red[4 * 256];
+  __shared__ double s_shift;
+  const int t = threadIdx.x;
+  const int n = cs->n, L = cs->L, mt = cs->mt, T = L / kT;
+  double tr = 0.0, su = 0.0, sw = 0.0, sv = 0.0, sp = 0.0;
+  for (int b = t; b < T; b += 256) tr += diag_part[b];
+  for (int b = t; b < nprep; b += 256) {
+    su += prep_part[2 * b];
+    sw += prep_part[2 * b + 1];
+  }
+  for (int e = t; e < mt * mt; e += 256) {
+    const int p = e % mt, q = e / mt;
+    const double gv = G[p + (size_t)q * ldg];
+    if (p == q) sv += gv;
+    const double d = gv - (p == q ? 1.0 : 0.0);
+    sp = fma(d, d, sp);
+  }
+  red[t] = tr;
+  red[256 + t] = su;
+  red[512 + t] = sw;
+  red[768 + t] = sv;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      red[t] += red[t + s];
+      red[256 + t] += red[256 + t + s];
+      red[512 + t] += red[512 + t + s];
+      red[768 + t] += red[768 + t + s];
+    }
+    __syncthreads();
+  }
+  const double trace = red[0], ufro2 = red[256], wfro2 = red[512], vfro2 = red[768];
+  __syncthreads();
+  red[t] = sp;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double phi = sqrt(red[0]);
+    const double fa = cs->fro_a, c = cs->c;
+    const double vn = sqrt(fmax(vfro2, 0.0)), wn = sqrt(fmax(wfro2, 0.0));
+    const double f = (1.0 + phi) * (1.0 + phi);
+    // every term but the factorization's does not depend on delta
+    const double e_form = gam(2.0 * mt + 1.0) * (fa + vfro2 + ufro2);
+    const double e_w = 3.0 * gam((double)n) * fa * vn * f + gam((double)n) * vn * wn * f +
+                       2.0 * (1.0 + phi) * gam(mt + 2.0) * (wn + 0.5 * vn * wn * (1.0 + phi) + 0.5 * c * vn);
+    const double e_orth = (2.0 * phi + phi * phi) * fa + c * phi;
+    const double gl = gam(L + 3.0);
+    double delta = cs->delta, eta = 0.0;
+    for (int it = 0; it < 3; ++it) {
+      const double tr_m = fmax(trace + n * delta + (double)(L - n), 0.0);
+      const double e_chol = gl * tr_m / (1.0 - gl);
+      const double e_diag = 1.1102230246251565e-16 * (fa + c + delta);
+      eta = 2.0 * (e_chol + e_form + e_w + e_orth + e_diag);
+      if (delta < 4.0 * eta) delta = 4.0 * eta;
+    }
+    cs->trace = trace;
+    cs->ufro2 = ufro2;
+    cs->wfro2 = wfro2;
+    cs->vfro2 = vfro2;
+    cs->phi = phi;
+    cs->eta = eta;
+    cs->delta_eff = delta;
+    cs->shift = delta - eta;
+    s_shift = delta - eta;
+    if (!(trace + n * delta + (double)(L - n) > 0.0)) cs->fail = -2;
+  }
+  __syncthreads();
+  const double sh = s_shift;
+  for (int i = t; i < n; i += 256) M[(size_t)i + (size_t)i * L] += sh;
+}
+
+// ----------------------------------------------------------- Cholesky ----
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int L, int k,
+                                                   CertState* cs) {
+  if (cert_failed(cs)) return;
+  __shared__ double a[kT * kLd];
+  __shared__ double dg[kT];
+  load_tile(M, L, k, k, a);
+  if (!chol_tile_lds(a, dg)) {
+    if (threadIdx.x == 0) cs->fail = 1 + k;
+    return;
+  }
+  store_tile(M, L, k, k, a);
+}
+
+// L_ik = A_ik L_kk^{-T} for the row blocks i > k: row r of the block is
+// solved by the four lanes 4r .. 4r + 3 (lane g owns the columns g + 4s)
+// in column order, the reciprocal of each pivot applied once.
+__global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int L, int k,
+                                                   CertState* cs) {
+  if (cert_failed(cs)) return;
+  __shared__ double lk[kT * kLd];
+  __shared__ double rinv[kT];
+  const int t = threadIdx.x;
+  const int bi = k + 1 + blockIdx.x;
+  load_tile(M, L, k, k, lk);
+  __syncthreads();
+  if (t < kT) rinv[t] = 1.0 / lk[t * kLd + t];
+  __syncthreads();
+  const int r = t >> 2, g = t & 3, lane = t & 63;
+  double* rowp = M + (size_t)(bi * kT + r) + (size_t)(k * kT + g) * L;
+  double x[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) x[s] = rowp[(size_t)(4 * s) * L];
+#pragma unroll
+  for (int c = 0; c < kT; ++c) {
+    double v = x[c >> 2] * rinv[c];
+    v = __shfl(v, (lane & ~3) | (c & 3), 64);
+    if (g == (c & 3)) x[c >> 2] = v;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int q = g + 4 * s;
+      if (q > c) x[s] = fma(-v, lk[q * kLd + c], x[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 16; ++s) rowp[(size_t)(4 * s) * L] = x[s];
+}
+
+// Trailing update A_ij -= L_ik L_jk^T for k < j <= i; workgroup 0 takes the
+// tile (k + 1, k + 1) and then factors it (one-panel lookahead).
+__global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ M, int L, int k,
+                                                   CertState* cs) {
+  if (cert_failed(cs)) return;
+  __shared__ __align__(16) double sm[2 * kT * kT];
+  double* dg = sm + kT * kLd;  // pivots during the lookahead factorization
+  double* pt = sm;            // pt[q * 64 + r] = L_ik(r, q)
+  double* qt = sm + kT * kT;  // qt[q * 64 + c] = L_jk(c, q)
+  int ii, jj;
+  tri_index(blockIdx.x, ii, jj);
+  const int bi = k + 1 + ii, bj = k + 1 + jj;
+  const int i0 = bi * kT, j0 = bj * kT, k0 = k * kT;
+  const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
+#pragma unroll 4
+  for (int u = 0; u < kT * kT / 256; ++u) {
+    const int e = t + 256 * u, r = e & 63, q = e >> 6;
+    pt[q * kT + r] = M[(size_t)(i0 + r) + (size_t)(k0 + q) * L];
+    qt[q * kT + r] = M[(size_t)(j0 + r) + (size_t)(k0 + q) * L];
+  }
+  double acc[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc[a][b] = M[(size_t)(i0 + 4 * tr + a) + (size_t)(j0 + 4 * tc + b) * L];
+  __syncthreads();
+#pragma unroll 4
+  for (int q = 0; q < kT; ++q) {
+    const double2 p01 = *(const double2*)&pt[q * kT + 4 * tr];
+    const double2 p23 = *(const double2*)&pt[q * kT + 4 * tr + 2];
+    const double2 q01 = *(const double2*)&qt[q * kT + 4 * tc];
+    const double2 q23 = *(const double2*)&qt[q * kT + 4 * tc + 2];
+    const double p[4] = {p01.x, p01.y, p23.x, p23.y};
+    const double w[4] = {q01.x, q01.y, q23.x, q23.y};
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc[a][b] = fma(-p[a], w[b], acc[a][b]);
+  }
+  if (blockIdx.x != 0) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) M[(size_t)(i0 + 4 * tr + a) + (size_t)(j0 + 4 * tc + b) * L] = acc[a][b];
+    return;
+  }
+  // lookahead: the updated diagonal tile (k + 1, k + 1) is factored here
+  double* a = sm;  // 64 x 65 row-major, over pt (no longer read)
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[(4 * tr + q) * kLd + 4 * tc + b] = acc[q][b];
+  if (!chol_tile_lds(a, dg)) {
+    if (t == 0) cs->fail = 1 + bi;
+    return;
+  }
+  store_tile(M, L, bi, bi, a);
+}
+
+// ------------------------------------------------------------- launch ----
+hipError_t launch_cert_prep(const double* V, const double* W, int ld, const double* H, int ldh,
+                            int mt, int n, int L, double c, double* U, double* part,
+                            hipStream_t st) {
+  if (mt <= 0) return hipSuccess;
+  if (mt > kCertMaxM) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cert_prep, dim3(L / kT), dim3(256), 0, st, V, W, ld, H, ldh, mt, n, c, U,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t launch_cert_form(const double* A, int lda, const double* V, const double* U, int ld,
+                            int mt, int n, int L, double* M, double* diag_part, hipStream_t st) {
+  if (L % kT != 0 || mt < 0) return hipErrorInvalidValue;
+  const int T = L / kT;
+  hipLaunchKernelGGL(k_cert_form, dim3(T * (T + 1) / 2), dim3(256), 0, st, A, lda, V, U, ld, mt,
+                     n, L, M, diag_part);
+  return hipGetLastError();
+}
+
+hipError_t launch_cert_shift(const double* G, int ldg, const double* prep_part, int nprep,
+                             const double* diag_part, double* M, CertState* cs, hipStream_t st) {
+  hipLaunchKernelGGL(k_cert_shift, dim3(1), dim3(256), 0, st, G, ldg, prep_part, nprep, diag_part,
+                     M, cs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cert_chol(double* M, int L, CertState* cs, hipStream_t st) {
+  if (L % kT != 0 || L <= 0) return hipErrorInvalidValue;
+  const int T = L / kT;
+  hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, M, L, 0, cs);
+  for (int k = 0; k + 1 < T; ++k) {
+    const int R = T - k - 1;
+    hipLaunchKernelGGL(k_chol_trsm, dim3(R), dim3(256), 0, st, M, L, k, cs);
+    hipLaunchKernelGGL(k_chol_syrk, dim3(R * (R + 1) / 2), dim3(256), 0, st, M, L, k, cs);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace psdp

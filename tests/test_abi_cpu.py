@@ -84,6 +84,7 @@ def test_defaults_and_strings(lib):
     assert abs(o.side_threshold - 1.0 / 3.0) < 1e-15 and o.pos_hint == -1
     assert o.batch_variant == -1 and o.batch_graph == 1
     assert o.bound_rel_max == 0.0
+    assert o.certify == 1 and o.certify_delta == 0.0 and o.warm_side == 0
     lib.psdp_status_str.restype = ctypes.c_char_p
     for code, name in [(0, b"PSDP_OK"), (1, b"PSDP_NOT_CONVERGED"), (-1, b"PSDP_ERR_INVALID_ARG"),
                        (-5, b"PSDP_ERR_CAPACITY")]:
@@ -115,6 +116,10 @@ def test_validation_before_any_launch(lib):
     assert lib.psdp_destroy(None) == -1
     assert lib.psdp_project_batched(None, 1, None, None, None, None, None, None, None, None,
                                     None) == -1
+    ok = ctypes.c_int(7)
+    assert lib.psdp_certify_tail(None, 10, None, 10, None, 10, 0, 1e-6, ctypes.byref(ok), None,
+                                 None) == -1
+    assert ok.value == 7
 
 
 def test_create_without_gpu_reports_hip_error(lib):

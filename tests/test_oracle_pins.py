@@ -357,6 +357,57 @@ def test_tail_exact_special_cases():
     assert abs(oracle.tail_exact(c.X, Vt) - np.sqrt(np.sum(miss ** 2))) <= 1e-11 * np.linalg.norm(Pi)
 
 
+@pytest.mark.parametrize("n,m", [(12, 3), (40, 7), (33, 0)])
+def test_complement_spectrum_closed_form(n, m):
+    # X = Q diag(lam) Q^T and Vt = m columns of Q: the compression to the
+    # complement has exactly the other prescribed eigenvalues
+    rng = _rng(960 + n)
+    c = random_spectrum_matrix(n, max(1, n // 4), rng, pos=(0.5, 3.0), neg=(-4.0, -0.01))
+    idx = rng.permutation(n)
+    Vt = c.Q[:, idx[:m]]
+    mu = oracle.complement_spectrum(c.X, Vt)
+    rest = np.sort(c.lam[idx[m:]])
+    assert mu.shape == (n - m,)
+    assert np.abs(mu - rest).max() <= 1e-12 * np.abs(c.lam).max() * n
+
+
+def test_complement_spectrum_interlaces():
+    # Cauchy interlacing for an arbitrary orthonormal Vt (n x m):
+    # lam_k(X) <= mu_k <= lam_{k+m}(X), all ascending
+    rng = _rng(970)
+    n, m = 25, 4
+    X = _sym(n, rng)
+    Vt, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    mu = oracle.complement_spectrum(X, Vt)
+    lam = np.linalg.eigvalsh(X)
+    tol = 1e-12 * np.abs(lam).max() * n
+    assert np.all(lam[: n - m] <= mu + tol)
+    assert np.all(mu <= lam[m:] + tol)
+    # the tail term is the norm of the compression's positive part
+    pos = mu[mu > 0]
+    assert abs(oracle.tail_exact(X, Vt) - np.sqrt(np.sum(pos ** 2))) <= tol * n
+
+
+def test_complement_spectrum_catches_planted_mistakes():
+    # the closed-form pin above fails for plausible slips in the shift trick
+    rng = _rng(980)
+    c = random_spectrum_matrix(15, 4, rng, pos=(0.5, 3.0), neg=(-4.0, -0.1))
+    Vt = c.Q[:, :3]
+    rest = np.sort(c.lam[3:])
+    X = oracle.symmetrize_lower(c.X)
+    n = 15
+
+    def variant(shift_sign, drop_first):
+        s = shift_sign * (2.0 * np.linalg.norm(X) + 1.0)
+        P = np.eye(n) - Vt @ Vt.T
+        lam = np.linalg.eigvalsh(P @ X @ P - s * (Vt @ Vt.T))
+        return lam[3:] if drop_first else lam[:-3]
+
+    assert np.abs(variant(+1, True) - rest).max() < 1e-10          # the oracle's form
+    assert np.abs(variant(-1, True) - rest).max() > 1e-3           # wrong shift sign
+    assert np.abs(variant(+1, False) - rest).max() > 1e-3          # wrong end dropped
+
+
 def test_bound_counterexample_needs_positive_ritz_vectors():
     # The theorem is stated for positive Ritz pairs: with X = diag(1,-1) and
     # Vt = I (a negative Ritz pair kept), R = 0 and the tail is 0, yet the
