@@ -95,6 +95,8 @@ def roofline(fams, prec, workload=None):
     by its average launch time (hipEvents on the launching stream)."""
     dom = max(fams, key=lambda f: fams[f]["ms"])
     fd = fams[dom]
+    if not fd["launches"] or fd["ms"] <= 0:
+        return None
     avg_ms = fd["ms"] / max(1, fd["launches"])
     flops_l = fd["flops"] / max(1, fd["launches"])
     bytes_l = fd["bytes"] / max(1, fd["launches"])
@@ -219,9 +221,11 @@ def run_sequence(args, torch, psdp):
     # the dominant hand-written family that the timed region times)
     sess = session()
     Pis = [psdp._empty_f(n, n, dev) for _ in range(2)]
+    for k in range(warm):
+        sess.project(Xs[k], Pi_out=Pis[k % 2])
     proj.profile_enable(True)
-    kt_steps = min(warm + steps, KERNEL_TABLE_STEPS)
-    for k in range(kt_steps):
+    kt_steps = min(steps, KERNEL_TABLE_STEPS)
+    for k in range(warm, warm + kt_steps):
         sess.project(Xs[k], Pi_out=Pis[k % 2])
     torch.cuda.synchronize()
     fams_all = {f: proj.profile_get(f) for f in FAMILIES + ["product_fp64", "product_fp32", "product_bf16"]}
@@ -334,8 +338,8 @@ def run_sequence(args, torch, psdp):
         "roofline": roofline(fams, prec, wl), "product_roofline": product_roofline(fams_all, prec),
         "cpu_baseline": cpu, "kernels": kernels_table(fams_all),
         "kernels_note": f"every family timed on an untimed pass over the first {kt_steps} "
-                        f"matrices; the timed region times only '{timed_family}', the "
-                        f"hand-written family with the most time in that pass",
+                        f"timed matrices (after the same warm-up); the timed region times only "
+                        f"'{timed_family}', the hand-written family with the most time in that pass",
         "dominant_family_untimed_pass": max(FAMILIES, key=lambda f: fams_all[f]["ms"]),
     }
     proj.close()

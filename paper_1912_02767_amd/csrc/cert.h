@@ -41,6 +41,8 @@ struct CertState {
   int fail;       // 0: every pivot so far positive; 1 + p: a pivot of diagonal
                   // tile p was not positive and finite; -2: tr(M) < 0
   int pad1;
+  long long t_diag[4];  // device clock (100 MHz) in the first diagonal tile's
+                        // factorization: start, loaded, factored, stored
 };
 
 // U = W - Vt H / 2 + (c / 2) Vt (rows < n; zero below), per-workgroup

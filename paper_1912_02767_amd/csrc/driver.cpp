@@ -744,6 +744,10 @@ psdp_status run_certificate(psdp_handle h, int n, int mt, double fro2, double de
   HIP_TRY(hipStreamSynchronize(s));
   *out = *hc;
   *certified = (hc->fail == 0) ? 1 : 0;
+  if (h->trace)
+    std::fprintf(stderr, "psdp: cert n %d mt %d fail %d eta %.3e delta %.3e diag_us load %.1f factor %.1f store %.1f\n",
+                 n, mt, hc->fail, hc->eta, hc->delta_eff, (hc->t_diag[1] - hc->t_diag[0]) * 1e-2,
+                 (hc->t_diag[2] - hc->t_diag[1]) * 1e-2, (hc->t_diag[3] - hc->t_diag[2]) * 1e-2);
   return PSDP_OK;
 }
 

@@ -6,8 +6,8 @@
 // and §3.5): a Cholesky factorization that completes with positive pivots
 // gives L L^T = M + dM with |dM| <= gamma_{L+1} |L| |L^T|, hence
 // ||dM||_2 <= gamma_{L+1} tr(M) / (1 - gamma_{L+1}); the factorization here
-// divides through a rounded reciprocal, one more rounding per entry, which
-// gamma_{L+3} covers.  The formation of M is bounded the same way from the
+// scales by a refined reciprocal square root and divides through rounded
+// reciprocals, a few more roundings per entry, which gamma_{L+8} covers.  The formation of M is bounded the same way from the
 // norms the kernels measure; eta is twice the sum of these terms.
 #include "cert.h"
 #include "common.h"
@@ -32,34 +32,82 @@ __device__ inline void tri_index(int b, int& ii, int& jj) {
   jj = b - i * (i + 1) / 2;
 }
 
+// 1 / sqrt(d) for d > 0: the hardware estimate refined by two Newton steps
+// (relative error a few units of roundoff; the margin eta allows for it).
+__device__ inline double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// v of lane `src` (a constant) on every lane
+__device__ inline double bcast_lane(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
 // Right-looking Cholesky of the lower triangle of the 64 x 64 tile held
-// row-major (stride 65) in LDS.  256 threads.  Returns false, on every
-// thread, when a pivot is not positive and finite.  On success the lower
-// triangle holds the factor (the strict upper triangle is left as it was).
-__device__ bool chol_tile_lds(double* a, double* dg) {
-  const int t = threadIdx.x, c = t & 63, i0 = t >> 6;
-  for (int j = 0; j < kT; ++j) {
-    __syncthreads();  // the previous step's update is visible
-    const double d = a[j * kLd + j];
-    if (!(d > 0.0) || !(d < INFINITY)) return false;  // same value on every thread
-    const double ljj = sqrt(d);
-    const double inv = 1.0 / ljj;
-    if (t > j && t < kT) a[t * kLd + j] *= inv;
-    if (t == 0) dg[j] = ljj;
-    __syncthreads();
-    if (c > j) {
-      const double lcj = a[c * kLd + j];
-#pragma unroll 4
-      for (int s = 0; s < kT / 4; ++s) {
-        const int i = i0 + 4 * s;
-        if (i >= c) a[i * kLd + c] = fma(-a[i * kLd + j], lcj, a[i * kLd + c]);
+// row-major (stride 65) in LDS, by the first wave of the workgroup: lane i
+// keeps row i in registers; at column j the pivot comes from lane j by
+// readlane, every lane forms 1 / sqrt(pivot) itself, writes its l_ij to an
+// LDS column buffer and updates its row with the broadcast l_cj, c > j (the
+// entries right of its diagonal take junk updates that are never read).
+// Called by every thread of the workgroup (the other waves wait at the
+// closing barrier).  Returns false, on every thread, when a pivot is not
+// positive and finite; on success the lower triangle holds the factor.
+__device__ __attribute__((always_inline)) inline bool chol_tile_lds(double* a, double* cb, int* flag) {
+  if (threadIdx.x < kT) {
+    const int lane = threadIdx.x;
+    double r[kT];
+#pragma unroll
+    for (int c = 0; c < kT; ++c) r[c] = a[lane * kLd + c];
+    int ok = 1;
+#pragma unroll
+    for (int j = 0; j < kT; ++j) {
+      const double d = bcast_lane(r[j], j);
+      if (!(d > 0.0) || !(d < INFINITY)) {  // the same value on every lane
+        ok = 0;
+        break;
+      }
+      const double inv = rsqrt_nr(d);
+      const double l = r[j] * inv;
+      r[j] = (lane == j) ? d * inv : l;
+      double* b = cb + (j & 1) * kT;
+      b[lane] = l;
+#pragma unroll
+      for (int c0 = (j + 1) & ~1; c0 < kT; c0 += 2) {
+        const double2 w = *(const double2*)(b + c0);
+        if (c0 > j) r[c0] = fma(-l, w.x, r[c0]);
+        r[c0 + 1] = fma(-l, w.y, r[c0 + 1]);
       }
     }
+#pragma unroll
+    for (int c = 0; c < kT; ++c) a[lane * kLd + c] = r[c];
+    if (lane == 0) *flag = ok;
   }
   __syncthreads();
-  if (t < kT) a[t * kLd + t] = dg[t];
-  __syncthreads();
-  return true;
+  return *flag != 0;
+}
+
+// v from the lane (lane & ~3) | K of this lane's quad (DPP quad permute)
+template <int K>
+__device__ inline double quad_bcast(double v) {
+  constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline double quad_bcast_k(double v, int k) {
+  switch (k) {
+    case 0: return quad_bcast<0>(v);
+    case 1: return quad_bcast<1>(v);
+    case 2: return quad_bcast<2>(v);
+    default: return quad_bcast<3>(v);
+  }
 }
 
 // tile (row block bi, column block bj) of column-major M <-> row-major LDS
@@ -270,7 +318,7 @@ __global__ __launch_bounds__(256) void k_cert_shift(const double* __restrict__ G
     const double e_w = 3.0 * gam((double)n) * fa * vn * f + gam((double)n) * vn * wn * f +
                        2.0 * (1.0 + phi) * gam(mt + 2.0) * (wn + 0.5 * vn * wn * (1.0 + phi) + 0.5 * c * vn);
     const double e_orth = (2.0 * phi + phi * phi) * fa + c * phi;
-    const double gl = gam(L + 3.0);
+    const double gl = gam(L + 8.0);
     double delta = cs->delta, eta = 0.0;
     for (int it = 0; it < 3; ++it) {
       const double tr_m = fmax(trace + n * delta + (double)(L - n), 0.0);
@@ -300,47 +348,84 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int L
                                                    CertState* cs) {
   if (cert_failed(cs)) return;
   __shared__ double a[kT * kLd];
-  __shared__ double dg[kT];
+  __shared__ __align__(16) double cb[2 * kT];
+  __shared__ int flag;
+  const long long t0 = wall_clock64();
   load_tile(M, L, k, k, a);
-  if (!chol_tile_lds(a, dg)) {
+  __syncthreads();
+  const long long t1 = wall_clock64();
+  if (!chol_tile_lds(a, cb, &flag)) {
     if (threadIdx.x == 0) cs->fail = 1 + k;
     return;
   }
+  const long long t2 = wall_clock64();
   store_tile(M, L, k, k, a);
+  if (threadIdx.x == 0) {
+    cs->t_diag[0] = t0;
+    cs->t_diag[1] = t1;
+    cs->t_diag[2] = t2;
+    cs->t_diag[3] = wall_clock64();
+  }
+}
+
+// Columns 16 O .. 16 O + 15 of the row solve in k_chol_trsm (their owner is
+// lane O of each quad).  The staged factor is zero on and above its
+// diagonal, so every lane applies every update unconditionally.
+template <int O>
+__device__ inline void trsm_quarter(double (&x)[16], const double* lt, const double* rinv, int g) {
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) {
+    const int c = 16 * O + cc;
+    const double2* lc = (const double2*)(lt + c * kT + 16 * g);
+    double2 w[8];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) w[s2] = lc[s2];
+    const double v = quad_bcast<O>(x[cc] * rinv[c]);
+    x[cc] = (g == O) ? v : x[cc];
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      x[2 * s2] = fma(-v, w[s2].x, x[2 * s2]);
+      x[2 * s2 + 1] = fma(-v, w[s2].y, x[2 * s2 + 1]);
+    }
+  }
 }
 
 // L_ik = A_ik L_kk^{-T} for the row blocks i > k: row r of the block is
-// solved by the four lanes 4r .. 4r + 3 (lane g owns the columns g + 4s)
-// in column order, the reciprocal of each pivot applied once.
+// solved by the four lanes 4r .. 4r + 3 of a quad (lane g owns the columns
+// 16 g .. 16 g + 15) in column order: x_c = a_c / l_cc by the rounded
+// reciprocal, broadcast in the quad by DPP, then a_q -= x_c l_qc for q > c.
+// L_kk is held transposed in LDS so a lane's 16 values of column c are
+// contiguous.
 __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int L, int k,
                                                    CertState* cs) {
   if (cert_failed(cs)) return;
-  __shared__ double lk[kT * kLd];
+  __shared__ __align__(16) double lt[kT * kT];  // lt[c * 64 + q] = L_kk(q, c), q > c
   __shared__ double rinv[kT];
   const int t = threadIdx.x;
   const int bi = k + 1 + blockIdx.x;
-  load_tile(M, L, k, k, lk);
-  __syncthreads();
-  if (t < kT) rinv[t] = 1.0 / lk[t * kLd + t];
-  __syncthreads();
-  const int r = t >> 2, g = t & 3, lane = t & 63;
-  double* rowp = M + (size_t)(bi * kT + r) + (size_t)(k * kT + g) * L;
-  double x[16];
-#pragma unroll
-  for (int s = 0; s < 16; ++s) x[s] = rowp[(size_t)(4 * s) * L];
-#pragma unroll
-  for (int c = 0; c < kT; ++c) {
-    double v = x[c >> 2] * rinv[c];
-    v = __shfl(v, (lane & ~3) | (c & 3), 64);
-    if (g == (c & 3)) x[c >> 2] = v;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int q = g + 4 * s;
-      if (q > c) x[s] = fma(-v, lk[q * kLd + c], x[s]);
+  {
+    const double* src = M + (size_t)(k * kT) + (size_t)(k * kT) * L;
+#pragma unroll 4
+    for (int u = 0; u < kT * kT / 256; ++u) {
+      const int e = t + 256 * u, q = e & 63, c = e >> 6;
+      const double v = src[q + (size_t)c * L];
+      if (q == c) rinv[c] = 1.0 / v;
+      // only q > c updates: the diagonal and the upper triangle are zero here
+      lt[c * kT + q] = (q > c) ? v : 0.0;
     }
   }
+  __syncthreads();
+  const int r = t >> 2, g = t & 3;
+  double* rowp = M + (size_t)(bi * kT + r) + (size_t)(k * kT + 16 * g) * L;
+  double x[16];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) rowp[(size_t)(4 * s) * L] = x[s];
+  for (int s = 0; s < 16; ++s) x[s] = rowp[(size_t)s * L];
+  trsm_quarter<0>(x, lt, rinv, g);
+  trsm_quarter<1>(x, lt, rinv, g);
+  trsm_quarter<2>(x, lt, rinv, g);
+  trsm_quarter<3>(x, lt, rinv, g);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) rowp[(size_t)s * L] = x[s];
 }
 
 // Trailing update A_ij -= L_ik L_jk^T for k < j <= i; workgroup 0 takes the
@@ -349,7 +434,8 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ M, int L
                                                    CertState* cs) {
   if (cert_failed(cs)) return;
   __shared__ __align__(16) double sm[2 * kT * kT];
-  double* dg = sm + kT * kLd;  // pivots during the lookahead factorization
+  double* cb = sm + kT * kLd;  // column buffers of the lookahead factorization (16-byte aligned)
+  int* flag = (int*)(sm + kT * kLd + 2 * kT);
   double* pt = sm;            // pt[q * 64 + r] = L_ik(r, q)
   double* qt = sm + kT * kT;  // qt[q * 64 + c] = L_jk(c, q)
   int ii, jj;
@@ -396,7 +482,8 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ M, int L
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[(4 * tr + q) * kLd + 4 * tc + b] = acc[q][b];
-  if (!chol_tile_lds(a, dg)) {
+  __syncthreads();
+  if (!chol_tile_lds(a, cb, flag)) {
     if (t == 0) cs->fail = 1 + bi;
     return;
   }
