@@ -273,6 +273,22 @@ psdp_status psdp_block_product(psdp_handle h, int n, const double *X, int ldx,
                                const double *S, int lds, int k, int prec,
                                double *Y, int ldy);
 
+/* psdp_block_product for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same product, same kernels and same results, with every
+ * buffer beyond X, S and Y (the copies of A, the staged S, the split-K
+ * partial sums) in a 64 MiB device array the library holds on each GPU it
+ * runs on until the process ends.  No allocation happens in the call (the
+ * handle's own lazily allocated workspace is not used either).  The array
+ * fits n <= 2048 with any k <= 144 in every precision; a larger request
+ * returns PSDP_ERR_CAPACITY before any launch.  All calls on one GPU share
+ * that GPU's array and each call leaves its contents behind: calls that
+ * overlap on one GPU (several handles, streams or threads) race.
+ * Synchronises the handle's stream. */
+psdp_status psdp_block_product_noalloc(psdp_handle h, int n, const double *X, int ldx,
+                                       const double *S, int lds, int k, int prec, double *Y,
+                                       int ldy);
+
 /* The tail certificate on its own (paper §5.2, Thm `bound`, second term
  * ||Pi(V_perp^T A V_perp)||_F with A = sym(X)): proves that every eigenvalue
  * of V_perp^T A V_perp is below delta through an FP64 Cholesky factorization

@@ -30,7 +30,7 @@ EXPORTED = [
     "psdp_server_open_session", "psdp_server_close_session", "psdp_server_submit",
     "psdp_server_wait", "psdp_server_drain", "psdp_server_session_block",
     "psdp_server_stats_get", "psdp_server_stats_reset", "psdp_full_eig_project_batched",
-    "psdp_profile_filter", "psdp_certify_tail",
+    "psdp_profile_filter", "psdp_certify_tail", "psdp_block_product_noalloc",
 ]
 
 
@@ -180,6 +180,10 @@ def load():
     lib.psdp_block_product.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, vp, ctypes.c_int]
     lib.psdp_block_product.restype = ctypes.c_int
+    lib.psdp_block_product_noalloc.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp,
+                                               ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                               ctypes.c_int]
+    lib.psdp_block_product_noalloc.restype = ctypes.c_int
     lib.psdp_certify_tail.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_double, ip, dp, dp]
     lib.psdp_certify_tail.restype = ctypes.c_int

@@ -279,5 +279,7 @@ hipError_t launch_copy_cols(const double* src, int lds, double* dst, int ldd, in
                             hipStream_t st);
 // st->stop = v (one thread)
 hipError_t launch_set_stop(State* st, int v, hipStream_t s);
+// *p = v (one thread)
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
 
 }  // namespace psdp

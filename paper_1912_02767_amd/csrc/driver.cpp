@@ -1288,6 +1288,9 @@ extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int*
 }
 
 namespace psdp {
+int handle_device(psdp_handle h) { return h->device; }
+hipStream_t handle_stream(psdp_handle h) { return h->stream; }
+
 int block_need(int est, const psdp_options& opt) {
   return est + std::max(opt.block_guard, (int)std::ceil(0.2 * est));
 }

@@ -1,6 +1,7 @@
 // Host-side functions shared between the driver, the batched engine and
 // the server (not part of the C-ABI).
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stddef.h>
 
 #include "../../include/psdp.h"
@@ -12,5 +13,8 @@ namespace psdp {
 int auto_side(int n, int pos_hint, int m_cap, const psdp_options& opt);
 // block an estimate of `est` eigenvalues needs: est + max(guard, ceil(0.2 est))
 int block_need(int est, const psdp_options& opt);
+// device and stream a handle enqueues on
+int handle_device(psdp_handle h);
+hipStream_t handle_stream(psdp_handle h);
 
 }  // namespace psdp

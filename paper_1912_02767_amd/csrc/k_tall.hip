@@ -595,6 +595,15 @@ hipError_t launch_set_stop(State* st, int v, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_tsmm(const ColMap& src, const int* kk_dev, int kk_host, const int* q_dev,
                        int q_host, const double* M, int ldm, int n, double* Y, int ldy,
                        const int* stop, hipStream_t st) {
