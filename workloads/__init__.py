@@ -7,3 +7,5 @@ oracle.
 """
 from .generators import *  # noqa: F401,F403
 from .generators import __all__  # noqa: F401
+from .sdp import (Sdp, complete_graph, cycle_graph, dual_infeasible, maxcut,  # noqa: F401
+                  primal_infeasible, random_graph, theta, trace_min)
