@@ -399,6 +399,87 @@ psdp_status psdp_server_session_block(psdp_server srv, int session, double *V, i
 psdp_status psdp_server_stats_get(psdp_server srv, psdp_server_stats *st);
 psdp_status psdp_server_stats_reset(psdp_server srv);
 
+/* ------------------------------------------------------------------------
+ * Approximate ADMM for semidefinite programs (paper §2, Alg. 1; §6: every
+ * PSD projection by the warm-started block eigensolver on the side chosen
+ * from the previous iterate's inertia, stopped at residual
+ * tol_scale / k^tol_power; §6.2: infeasibility from successive differences).
+ *
+ * Problem, standard form:  minimize <C, Y>  s.t.  <A_i, Y> = b_i (i < p),
+ * Y psd (n x n).  In the paper's form (P): x = Y, P = 0, q = C,
+ * A x = (<A_i, Y>)_i stacked over Y itself, cone C = {b} x S_+.  The A_i are
+ * given by their lower-triangle entries and their supports must be
+ * disjoint (diagonal constraints, single off-diagonal entries, a trace, ...),
+ * which makes the linear system of Alg. 1's first line exact in closed form:
+ * A_eq^* A_eq acts on each A_i as ||A_i||_F^2 and as zero on their
+ * orthogonal complement.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int n;                  /* order of Y                                         */
+    int p;                  /* equality constraints                               */
+    const double *C;        /* DEVICE n x n cost, lower triangle read             */
+    int ldc;                /* >= n                                               */
+    int nnz;                /* constraint entries (HOST arrays below, length nnz) */
+    const int *con;         /* constraint of each entry, nondecreasing, 0..p-1;   */
+                            /* every constraint has at least one entry            */
+    const int *row;         /* row >= col, both in 0..n-1; no position twice      */
+    const int *col;
+    const double *val;      /* A_con holds val (finite, nonzero) at (row, col)    */
+                            /* and (col, row)                                     */
+    const double *b;        /* HOST p right-hand sides                            */
+} psdp_sdp;
+
+typedef struct {
+    double rho, sigma, alpha; /* Alg. 1 parameters (0.1, 1e-6, 1.6)               */
+    int max_iter;           /* iteration limit (2500)                             */
+    int check_every;        /* iterations between termination and infeasibility   */
+                            /* checks (40)                                        */
+    double eps_abs, eps_rel; /* termination on the residuals of (P) (1e-5, 1e-5)  */
+    double eps_inf;         /* infeasibility certificates (1e-5)                  */
+    int exact;              /* 1: exact projections (full eig, the baseline);     */
+                            /* 0 (default): psdp_project                          */
+    double tol_scale;       /* projection residual tolerance at iteration k:      */
+    double tol_power;       /* tol_scale / k^tol_power (10, 1.01: paper §6)       */
+    int prec;               /* psdp_prec of the block products (FP64)             */
+    int m_cap;              /* block capacity of the projections (48)             */
+} psdp_admm_options;
+
+enum {
+    PSDP_ADMM_SOLVED = 0,
+    PSDP_ADMM_MAX_ITER = 1,
+    PSDP_ADMM_PRIMAL_INFEASIBLE = 2,  /* certificate: A^T dy ~ 0, b^T dy < 0, its  */
+                                      /* PSD part negative semidefinite          */
+    PSDP_ADMM_DUAL_INFEASIBLE = 3     /* certificate: A_eq dY ~ 0, dY psd,        */
+                                      /* <C, dY> < 0 (the objective is unbounded) */
+};
+
+typedef struct {
+    int status;             /* PSDP_ADMM_*                                        */
+    int iters;              /* iterations run                                     */
+    double obj;             /* <C, Y> at the last check                           */
+    double r_prim, r_dual;  /* residuals of (P) at the last check                 */
+    double proj_ms;         /* wall time of the projections (host clock)          */
+    double total_ms;        /* wall time of the solve                             */
+    int proj_block;         /* projections by the block eigensolver               */
+    int proj_full;          /* projections by the exact path                      */
+    int proj_not_certified; /* of those, block attempts that fell back            */
+} psdp_admm_info;
+
+/* Fill *opt with the defaults documented above. */
+void psdp_admm_default_options(psdp_admm_options *opt);
+
+/* Solve the SDP *prob with approximate ADMM.  Outputs (DEVICE): Y (n x n,
+ * ldy) the primal matrix, y (p) the multipliers of the equality
+ * constraints, W (n x n, ldw) the multiplier of the PSD block (at a solution
+ * -W = C + sum_i y_i A_i is the dual slack, psd, and <W, Y> = 0).  Returns
+ * PSDP_OK with info->status saying how the iteration ended, or an error
+ * (PSDP_ERR_INVALID_ARG for overlapping supports or bad entries, before any
+ * launch).  Allocates its buffers (about 10 n^2 doubles) for the duration of
+ * the call and runs on the handle's stream, synchronising it. */
+psdp_status psdp_admm_solve(psdp_handle h, const psdp_sdp *prob, const psdp_admm_options *opt,
+                            double *Y, int ldy, double *y, double *W, int ldw,
+                            psdp_admm_info *info);
+
 /* Static string for a status code. */
 const char *psdp_status_str(psdp_status s);
 

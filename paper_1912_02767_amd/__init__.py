@@ -285,6 +285,46 @@ class Projector:
             raise PsdpError(rc, "psdp_certify_tail")
         return bool(ok.value), de.value, eta.value
 
+    def admm_solve(self, sdp, exact: bool = False, **opts):
+        """Approximate ADMM (psdp_admm_solve) on a standard-form SDP given as
+        host arrays: sdp.C (n x n), sdp.con/row/col/val (constraint entries,
+        lower triangle), sdp.b.  Keyword options are the fields of
+        psdp_admm_options.  Returns (Y, y, W, info)."""
+        import numpy as np
+        torch = _torch()
+        self._sync_stream()
+        dev = torch.device("cuda", self.device)
+        n = int(sdp.C.shape[0])
+        C = torch.from_numpy(np.asfortranarray(sdp.C, dtype=np.float64)).to(dev)
+        con = np.ascontiguousarray(sdp.con, dtype=np.int32)
+        row = np.ascontiguousarray(sdp.row, dtype=np.int32)
+        col = np.ascontiguousarray(sdp.col, dtype=np.int32)
+        val = np.ascontiguousarray(sdp.val, dtype=np.float64)
+        b = np.ascontiguousarray(sdp.b, dtype=np.float64)
+        ip = ctypes.POINTER(ctypes.c_int)
+        dp = ctypes.POINTER(ctypes.c_double)
+        pr = _abi.Sdp(n, int(b.size), ctypes.c_void_p(C.data_ptr()), C.stride(1), int(val.size),
+                      con.ctypes.data_as(ip), row.ctypes.data_as(ip), col.ctypes.data_as(ip),
+                      val.ctypes.data_as(dp), b.ctypes.data_as(dp))
+        o = _abi.AdmmOptions()
+        self.lib.psdp_admm_default_options(ctypes.byref(o))
+        o.exact = 1 if exact else 0
+        for k, v in opts.items():
+            if k == "prec" and isinstance(v, str):
+                v = PREC[v]
+            setattr(o, k, v)
+        Y = _empty_f(n, n, dev)
+        W = _empty_f(n, n, dev)
+        y = torch.empty(max(int(b.size), 1), dtype=torch.float64, device=dev)
+        info = _abi.AdmmInfo()
+        rc = self.lib.psdp_admm_solve(self._h, ctypes.byref(pr), ctypes.byref(o),
+                                      ctypes.c_void_p(Y.data_ptr()), Y.stride(1),
+                                      ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(W.data_ptr()),
+                                      W.stride(1), ctypes.byref(info))
+        if rc < 0:
+            raise PsdpError(rc, "psdp_admm_solve")
+        return Y, y[:int(b.size)], W, info.as_dict()
+
     # ------------------------------------------------------------ profiling
     def profile_enable(self, on: bool = True):
         self.lib.psdp_profile_enable(self._h, 1 if on else 0)

@@ -31,7 +31,10 @@ EXPORTED = [
     "psdp_server_wait", "psdp_server_drain", "psdp_server_session_block",
     "psdp_server_stats_get", "psdp_server_stats_reset", "psdp_full_eig_project_batched",
     "psdp_profile_filter", "psdp_certify_tail", "psdp_block_product_noalloc",
+    "psdp_admm_default_options", "psdp_admm_solve",
 ]
+
+ADMM_SOLVED, ADMM_MAX_ITER, ADMM_PRIMAL_INFEASIBLE, ADMM_DUAL_INFEASIBLE = 0, 1, 2, 3
 
 
 class Options(ctypes.Structure):
@@ -78,6 +81,57 @@ class Info(ctypes.Structure):
         ("block_side", ctypes.c_int),
         ("cert_delta", ctypes.c_double),
         ("cert_eta", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class Sdp(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int),
+        ("p", ctypes.c_int),
+        ("C", ctypes.c_void_p),
+        ("ldc", ctypes.c_int),
+        ("nnz", ctypes.c_int),
+        ("con", ctypes.POINTER(ctypes.c_int)),
+        ("row", ctypes.POINTER(ctypes.c_int)),
+        ("col", ctypes.POINTER(ctypes.c_int)),
+        ("val", ctypes.POINTER(ctypes.c_double)),
+        ("b", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class AdmmOptions(ctypes.Structure):
+    _fields_ = [
+        ("rho", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("check_every", ctypes.c_int),
+        ("eps_abs", ctypes.c_double),
+        ("eps_rel", ctypes.c_double),
+        ("eps_inf", ctypes.c_double),
+        ("exact", ctypes.c_int),
+        ("tol_scale", ctypes.c_double),
+        ("tol_power", ctypes.c_double),
+        ("prec", ctypes.c_int),
+        ("m_cap", ctypes.c_int),
+    ]
+
+
+class AdmmInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("iters", ctypes.c_int),
+        ("obj", ctypes.c_double),
+        ("r_prim", ctypes.c_double),
+        ("r_dual", ctypes.c_double),
+        ("proj_ms", ctypes.c_double),
+        ("total_ms", ctypes.c_double),
+        ("proj_block", ctypes.c_int),
+        ("proj_full", ctypes.c_int),
+        ("proj_not_certified", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -184,6 +238,11 @@ def load():
                                                ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
                                                ctypes.c_int]
     lib.psdp_block_product_noalloc.restype = ctypes.c_int
+    lib.psdp_admm_default_options.argtypes = [ctypes.POINTER(AdmmOptions)]
+    lib.psdp_admm_default_options.restype = None
+    lib.psdp_admm_solve.argtypes = [vp, ctypes.POINTER(Sdp), ctypes.POINTER(AdmmOptions), vp,
+                                    ctypes.c_int, vp, vp, ctypes.c_int, ctypes.POINTER(AdmmInfo)]
+    lib.psdp_admm_solve.restype = ctypes.c_int
     lib.psdp_certify_tail.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp, ctypes.c_int,
                                       ctypes.c_int, ctypes.c_double, ip, dp, dp]
     lib.psdp_certify_tail.restype = ctypes.c_int

@@ -64,7 +64,9 @@ int main(void) {{ printf("size %zu\\n", sizeof({struct})); {body} return 0; }}
 @pytest.mark.parametrize("name,cls", [("psdp_options", "Options"), ("psdp_info", "Info"),
                                       ("psdp_server_config", "ServerConfig"),
                                       ("psdp_result", "ServerResult"),
-                                      ("psdp_server_stats", "ServerStats")])
+                                      ("psdp_server_stats", "ServerStats"),
+                                      ("psdp_sdp", "Sdp"), ("psdp_admm_options", "AdmmOptions"),
+                                      ("psdp_admm_info", "AdmmInfo")])
 def test_struct_layout_matches_header(tmp_path, name, cls):
     sys.path.insert(0, ROOT)
     from paper_1912_02767_amd import _abi
@@ -120,6 +122,7 @@ def test_validation_before_any_launch(lib):
     assert lib.psdp_certify_tail(None, 10, None, 10, None, 10, 0, 1e-6, ctypes.byref(ok), None,
                                  None) == -1
     assert ok.value == 7
+    assert lib.psdp_admm_solve(None, None, None, None, 1, None, None, 1, None) == -1
 
 
 def test_create_without_gpu_reports_hip_error(lib):
