@@ -191,5 +191,44 @@ def complement_spectrum(X, Vt) -> np.ndarray:
     return lam[m:]
 
 
+def truncated_projection(X, r: int):
+    """sum_{i <= r} max(lam_i, 0) v_i v_i^T over the r largest eigenpairs of
+    X: the truncated projection the paper's §1 describes for solvers that
+    compute a fixed number of leading eigenpairs.  Returns (Pi_r, lam
+    descending)."""
+    lam, V = eigh(X)
+    order = np.argsort(lam)[::-1]
+    lam, V = lam[order], V[:, order]
+    r = max(0, min(int(r), lam.size))
+    w = np.maximum(lam[:r], 0.0)
+    Pi = (V[:, :r] * w) @ V[:, :r].T
+    return 0.5 * (Pi + Pi.T), lam
+
+
+def block_krylov_projection(X, X0, steps: int = 1):
+    """Rayleigh-Ritz on the block Krylov space span(X^k, A X^k) (paper §5,
+    block Lanczos), restarted `steps` times from X^0 (n x m) keeping the m
+    largest Ritz pairs, then the projection from the positive Ritz pairs:
+    returns (Pi~, theta descending, Ritz vectors).  The orthonormal basis
+    comes from a QR factorisation and the small eigenproblem from
+    numpy.linalg.eigh (library primitives)."""
+    A = symmetrize_lower(X)
+    Xk = np.asarray(X0, dtype=np.float64)
+    m = Xk.shape[1]
+    theta = np.zeros(0)
+    Y = Xk
+    for _ in range(max(1, int(steps))):
+        S, _ = np.linalg.qr(np.concatenate([Xk, A @ Xk], axis=1))
+        H = S.T @ A @ S
+        th, W = np.linalg.eigh(0.5 * (H + H.T))
+        order = np.argsort(th)[::-1][:m]
+        theta, Y = th[order], S @ W[:, order]
+        Xk = Y
+    pos = theta > 0
+    Pi = (Y[:, pos] * theta[pos]) @ Y[:, pos].T
+    return 0.5 * (Pi + Pi.T), theta, Y
+
+
 __all__ = ["build", "eigh", "project", "true_error", "rel_error", "tail_exact",
-           "complement_spectrum", "symmetrize_lower", "num_threads", "OracleError"]
+           "complement_spectrum", "truncated_projection", "block_krylov_projection",
+           "symmetrize_lower", "num_threads", "OracleError"]
