@@ -127,7 +127,28 @@ typedef struct {
                             /* a call that resolves to the other side starts      */
                             /* cold; PSDP_SIDE_AUTO (default): the side this call */
                             /* uses                                               */
+    int method;             /* psdp_method (default PSDP_METHOD_LOBPCG)           */
+    int method_param;       /* BLOCK_KRYLOV: block iterations (0 = 1);            */
+                            /* TOP_R: r, the block width (>= 1)                   */
 } psdp_options;
+
+/* Eigensolvers behind psdp_project (paper §5, the block Krylov discussion,
+ * and §1 on truncated projections). */
+typedef enum {
+    PSDP_METHOD_LOBPCG = 0,       /* Alg. 3 until every positive Ritz pair meets */
+                                  /* tol (the paper's method)                    */
+    PSDP_METHOD_BLOCK_KRYLOV = 1, /* Rayleigh-Ritz on span(X, AX) from the warm  */
+                                  /* start, method_param times (one block        */
+                                  /* Lanczos iteration each, restarted), no      */
+                                  /* convergence loop; OK only when the stopping */
+                                  /* rule then holds                             */
+    PSDP_METHOD_TOP_R = 2         /* the r = method_param largest Ritz pairs     */
+                                  /* (fixed block, no guard, no expansion) and   */
+                                  /* Pi~ = sum_{i<=r} max(theta_i, 0) v_i v_i^T; */
+                                  /* status says whether the r pairs met tol;    */
+                                  /* info.trunc_bound = sqrt(n - r) max(theta_r, */
+                                  /* 0), the bound that assumes exact pairs      */
+} psdp_method;
 
 typedef struct {
     double err_bound;   /* sqrt(2 ||R||_F^2 + tail_est^2), absolute Frobenius     */
@@ -159,6 +180,8 @@ typedef struct {
                         /* warm_side of the next call                             */
     double cert_delta;  /* threshold the certificate proved (NaN when not run)    */
     double cert_eta;    /* its rounding margin eta (NaN when not run)             */
+    double trunc_bound; /* PSDP_METHOD_TOP_R: sqrt(n - r) max(theta_r, 0), else  */
+                        /* NaN                                                    */
 } psdp_info;
 
 /* Fill *opt with the defaults documented above. */

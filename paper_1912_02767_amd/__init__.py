@@ -31,6 +31,8 @@ __all__ = ["Projector", "Session", "Server", "Result", "ServedResult", "PsdpErro
 
 PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 SIDE = {"auto": SIDE_AUTO, "pos": SIDE_POS, "neg": SIDE_NEG, "full": SIDE_FULL}
+METHOD = {"lobpcg": _abi.METHOD_LOBPCG, "block_krylov": _abi.METHOD_BLOCK_KRYLOV,
+          "top_r": _abi.METHOD_TOP_R}
 
 
 class PsdpError(RuntimeError):
@@ -72,7 +74,7 @@ class Result:
 def _opts(lib, side="pos", prec="fp64", tol=0.0, max_iter=300, refine=True,
           ladder=True, seed=None, side_threshold=1.0 / 3.0, expand_cols=0,
           pos_hint=-1, fallback_full=False, block_guard=4, bound_rel_max=0.0,
-          certify=True, certify_delta=0.0, warm_side="auto"):
+          certify=True, certify_delta=0.0, warm_side="auto", method="lobpcg", method_param=0):
     o = _abi.Options()
     lib.psdp_default_options(ctypes.byref(o))
     o.side = SIDE[side] if isinstance(side, str) else int(side)
@@ -92,6 +94,8 @@ def _opts(lib, side="pos", prec="fp64", tol=0.0, max_iter=300, refine=True,
     o.certify = 1 if certify else 0
     o.certify_delta = float(certify_delta)
     o.warm_side = SIDE[warm_side] if isinstance(warm_side, str) else int(warm_side)
+    o.method = METHOD[method] if isinstance(method, str) else int(method)
+    o.method_param = int(method_param)
     return o
 
 
@@ -143,7 +147,7 @@ class Projector:
                 side_threshold: float = 1.0 / 3.0, block_guard: int = 4, V_buf=None,
                 Pi_out=None, lam_buf=None, raise_on_error: bool = True,
                 bound_rel_max: float = 0.0, certify: bool = True, certify_delta: float = 0.0,
-                warm_side="auto") -> Result:
+                warm_side="auto", method="lobpcg", method_param: int = 0) -> Result:
         """Pi(X) with LOBPCG on one spectral side (psdp_project).
 
         V: optional warm start (n x k).  V_buf: optional column-major
@@ -170,7 +174,7 @@ class Projector:
         m_io = ctypes.c_int(k)
         opt = _opts(self.lib, side, prec, tol, max_iter, refine, ladder, seed, side_threshold,
                     expand_cols, pos_hint, fallback_full, block_guard, bound_rel_max, certify,
-                    certify_delta, warm_side)
+                    certify_delta, warm_side, method, method_param)
         info = _abi.Info()
         rc = self.lib.psdp_project(self._h, n, ctypes.c_void_p(Xf.data_ptr()), Xf.stride(1),
                                    ctypes.c_void_p(V_buf.data_ptr()), V_buf.stride(1), cap,

@@ -18,6 +18,7 @@ PSDP_ERR_NUMERICAL = -4
 PSDP_ERR_CAPACITY = -5
 
 SIDE_AUTO, SIDE_POS, SIDE_NEG, SIDE_FULL = 0, 1, 2, 3
+METHOD_LOBPCG, METHOD_BLOCK_KRYLOV, METHOD_TOP_R = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 
 # every symbol include/psdp.h declares
@@ -57,6 +58,8 @@ class Options(ctypes.Structure):
         ("bound_rel_max", ctypes.c_double),
         ("certify_delta", ctypes.c_double),
         ("warm_side", ctypes.c_int),
+        ("method", ctypes.c_int),
+        ("method_param", ctypes.c_int),
     ]
 
 
@@ -81,6 +84,7 @@ class Info(ctypes.Structure):
         ("block_side", ctypes.c_int),
         ("cert_delta", ctypes.c_double),
         ("cert_eta", ctypes.c_double),
+        ("trunc_bound", ctypes.c_double),
     ]
 
     def as_dict(self):

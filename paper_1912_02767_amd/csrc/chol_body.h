@@ -118,9 +118,11 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       const int npos = __popcll(posm);
       double rm = (in && i < npos) ? rn : 0.0;
       double r2 = rm * rm;
+      double ra = in ? rn : 0.0;  // over every pair of the block
       for (int o = 32; o > 0; o >>= 1) {
         rm = fmax(rm, __shfl_xor(rm, o, 64));
         r2 += __shfl_xor(r2, o, 64);
+        ra = fmax(ra, __shfl_xor(ra, o, 64));
       }
       const bool bad = in && (!isfinite(th) || !isfinite(rn));
       const bool nonfin_any = __ballot(bad) != 0ull;
@@ -169,7 +171,10 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
           stop = kNonFinite;
         } else if (lowp && npos > 0 && rmax <= lp_floor) {
           stop = kStalled;  // at the floor: continue with the next precision
-        } else if (st->expand_req) {
+        } else if (st->fixed_block && ra <= tol) {
+          // top-r: every pair of the block, positive or not, meets tol
+          stop = lowp ? kStalled : kConverged;
+        } else if (st->expand_req && !st->fixed_block) {
           stop = lowp ? kStalled : kExpand;
         } else if (npos == m && rmax <= tol && m >= st->n) {
           stop = kConverged;  // the block spans the whole space

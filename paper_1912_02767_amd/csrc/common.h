@@ -70,7 +70,8 @@ struct State {
   int jacobi_rounds;    // rotation rounds of the last RR
   int eval_stop;        // decision an evaluation pass would have taken
   int last_npos;        // positive count at the last progress check
-  int pad1;
+  int fixed_block;      // truncated top-r variant: converged once every pair of the
+                        // block meets tol, never expanded
   long long t_phase[12]; // device clock at phase boundaries of the last RR (0-4)
                          // and of the last first-pass Cholesky-QR (6-10)
   long long t_sub[12];    // device clock ticks inside the last RR: tridiagonalization

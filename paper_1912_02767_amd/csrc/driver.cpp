@@ -794,6 +794,8 @@ void psdp_default_options(psdp_options* o) {
   o->bound_rel_max = 0.0;
   o->certify_delta = 0.0;
   o->warm_side = PSDP_SIDE_AUTO;
+  o->method = PSDP_METHOD_LOBPCG;
+  o->method_param = 0;
 }
 
 psdp_status psdp_workspace_bytes(int n, int m_cap, int prec, size_t* bytes) {
@@ -1072,6 +1074,7 @@ static void fill_info_defaults(psdp_info* info) {
   info->block_side = PSDP_SIDE_POS;
   info->cert_delta = NAN;
   info->cert_eta = NAN;
+  info->trunc_bound = NAN;
 }
 
 // Exact projection of many cones (n <= 256) through zero-padded buckets of
@@ -1334,7 +1337,9 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   if (opt.side < 0 || opt.side > 3 || opt.prec < 0 || opt.prec > 2) return PSDP_ERR_INVALID_ARG;
   if (opt.max_iter < 1 || opt.certify < 0 || opt.certify > 1 || !(opt.side_threshold > 0.0) ||
       opt.side_threshold > 0.5 || opt.expand_cols < 0 || opt.pos_hint > n ||
-      !(opt.certify_delta >= 0.0) || opt.warm_side < 0 || opt.warm_side > 2)
+      !(opt.certify_delta >= 0.0) || opt.warm_side < 0 || opt.warm_side > 2 ||
+      opt.method < PSDP_METHOD_LOBPCG || opt.method > PSDP_METHOD_TOP_R ||
+      (opt.method == PSDP_METHOD_TOP_R && opt.method_param < 1) || opt.method_param < 0)
     return PSDP_ERR_INVALID_ARG;
   if ((const void*)Pi == (const void*)X) return PSDP_ERR_INVALID_ARG;
   if (hipSetDevice(h->device) != hipSuccess) return PSDP_ERR_HIP;
@@ -1373,6 +1378,8 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     if (est >= 0) m0 = est + std::max(opt.block_guard, (int)std::ceil(0.2 * est));
     else m0 = std::max(8, opt.block_guard);
   }
+  const bool top_r = opt.method == PSDP_METHOD_TOP_R;
+  if (top_r) m0 = opt.method_param;  // the truncation width is the block
   m0 = std::max(1, std::min(m0, mcap));
   int prec0 = opt.prec;
   psdp_status ps = ensure_workspace(h, n, mcap, prec0);
@@ -1406,6 +1413,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   hs.best_res = INFINITY;
   hs.last_npos = -1;
   hs.stall_window = (prec0 == 0) ? 30 : 8;
+  hs.fixed_block = top_r ? 1 : 0;
   hs.fro2_x = fro2;
   HIP_TRY(hipMemcpyAsync(w.st, &hs, sizeof(State), hipMemcpyHostToDevice, s));
   // ---- start block: warm start columns, then seeded normals
@@ -1416,7 +1424,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   if (m0 > m_in) HIP_TRY(launch_fill_normal(w.X, w.L, n, m_in, m0 - m_in, seed, rng_stream++, s));
   HIP_TRY(hipStreamSynchronize(s));
 
-  Solver sv(h, n, mcap);
+  Solver sv(h, n, top_r ? m0 : mcap);
   sv.m = m0;
   sv.has_p = 0;
   psdp_status rc = PSDP_OK;
@@ -1436,6 +1444,21 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   bool finished = false;
   bool converged = false;
   int fell_back = 0;
+  if (opt.method == PSDP_METHOD_BLOCK_KRYLOV) {
+    // Rayleigh-Ritz on span(X, AX) (one block Lanczos iteration from the
+    // warm start), method_param times, and no convergence loop
+    const int steps = std::max(1, opt.method_param);
+    for (int i = 0; i < steps; ++i) {
+      rc = sv.iterate(kModeXR, phase, sv.m, 0);
+      if (rc != PSDP_OK) { info->status = rc; return rc; }
+      const int stp = h->h_state->stop;
+      if (stp == kNonFinite) { info->status = PSDP_ERR_NUMERICAL; return PSDP_ERR_NUMERICAL; }
+      if (stp == kConverged) converged = true;
+      if (stp != kRunning) break;  // converged (or stopped) before the step
+      sv.has_p = 0;
+    }
+    finished = true;
+  }
   auto refresh = [&](int pprec) -> psdp_status {
     // Rayleigh-Ritz on span(X) with a fresh product: exact AX at pprec
     psdp_status r = sv.iterate(kModeXOnly, pprec, sv.m, 0);
@@ -1644,7 +1667,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   }
   // a certificate that was asked for and failed: positive eigenvalues of the
   // complement may exceed the threshold, so the result is not converged
-  if (opt.certify && !certified) {
+  if (opt.certify && !certified && !top_r) {
     converged = false;
     if (opt.fallback_full) return full_instead();
   }
@@ -1686,6 +1709,8 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   info->cert_eta = cert_eta;
   info->pos_est = (side == PSDP_SIDE_POS) ? npos : n - npos;
   info->block_side = side;
+  if (top_r)
+    info->trunc_bound = std::sqrt((double)std::max(n - m, 0)) * std::max(st.theta[m - 1], 0.0);
   info->expansions = expansions;
   info->prec_final = phase;
   info->status = converged ? PSDP_OK : PSDP_NOT_CONVERGED;

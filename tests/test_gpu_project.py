@@ -322,3 +322,50 @@ def test_session_carries_library_side(proj):
                      pos_hint=8, warm_side="neg")
     assert r.status == 0
     _check(r, c0.X)
+
+
+@pytest.mark.parametrize("steps", [1, 2])
+def test_block_krylov_variant_matches_oracle(proj, steps):
+    """PSDP_METHOD_BLOCK_KRYLOV (paper §5: Rayleigh-Ritz on span(X, AX), a
+    single block Lanczos iteration from the warm start) gives the oracle's
+    projection from the same subspace; its reported bound covers the error."""
+    from gpu_util import to_dev, to_host
+    c = random_spectrum_matrix(300, 10, rng_for(47, steps))
+    X0 = rng_for(47, 10 + steps).standard_normal((300, 16))
+    res = proj.project(to_dev(c.X), V=to_dev(X0), m_cap=16, side="pos", tol=1e-14,
+                       method="block_krylov", method_param=steps, raise_on_error=False)
+    assert res.status in (0, 1), res.info
+    Pi_k, theta, _ = oracle.block_krylov_projection(c.X, X0, steps=steps)
+    Pi = to_host(res.Pi)
+    lam = np.sort(res.lam.cpu().numpy())[::-1]
+    print(steps, res.status, res.info["iters"], np.abs(Pi - Pi_k).max(), lam[:4], theta[:4])
+    assert np.abs(lam - theta).max() <= 1e-9 * np.abs(theta).max()
+    assert oracle.rel_error(Pi, Pi_k) <= 1e-9
+    Pi_ref, _ = oracle.project(c.X)
+    err = oracle.true_error(Pi, Pi_ref)
+    assert res.info["err_bound"] >= err
+
+
+@pytest.mark.parametrize("r", [6, 16])
+def test_top_r_variant_matches_truncated_oracle(proj, r):
+    """PSDP_METHOD_TOP_R (paper §1: the truncated projection over the r
+    largest eigenpairs): the oracle's truncation, the truncation bound above
+    the true error, and a certificate only when no positive eigenvalue is
+    left out."""
+    from gpu_util import to_dev, to_host
+    c = random_spectrum_matrix(300, 12, rng_for(48, r), pos=(1.0, 10.0), neg=(-10.0, -0.1))
+    res = proj.project(to_dev(c.X), m_cap=32, side="pos", tol=1e-10, method="top_r",
+                       method_param=r, raise_on_error=False)
+    assert res.status == 0, res.info
+    Pi_r, lam = oracle.truncated_projection(c.X, r)
+    Pi = to_host(res.Pi)
+    Pi_ref, _ = oracle.project(c.X)
+    print(r, res.info["m_out"], res.info["certified"], oracle.rel_error(Pi, Pi_r),
+          res.info["trunc_bound"], oracle.true_error(Pi, Pi_ref))
+    assert res.info["m_out"] == r
+    assert oracle.rel_error(Pi, Pi_r) <= 1e-8
+    assert res.info["trunc_bound"] + 1e-9 >= oracle.true_error(Pi, Pi_ref)
+    if r >= 12:
+        assert res.info["certified"] == 1 and oracle.rel_error(Pi, Pi_ref) <= 1e-8
+    else:
+        assert res.info["certified"] == 0 and np.isinf(res.info["err_bound"])
