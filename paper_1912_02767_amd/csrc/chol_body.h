@@ -127,7 +127,22 @@ __device__ inline void decide_chol_body(const DecideArgs& a, double* lds, const 
       const bool bad = in && (!isfinite(th) || !isfinite(rn));
       const bool nonfin_any = __ballot(bad) != 0ull;
       const double tol = st->tol;
-      const bool act = in && rn > tol;
+      // Active residuals: a positive pair, and the first non-positive (guard)
+      // pair, which is the one that rises toward positive eigenvalues not
+      // yet in the block, until they meet tol; the further non-positive
+      // pairs only while the guard rule (largest non-positive pair within
+      // max(tol, gap / 2), the stopping rule below) is unmet: past that
+      // they stay in X but their R and P columns leave the trial basis (the
+      // top-r variant needs every pair of its block)
+      double gtl = tol;
+      {
+        const int g0 = npos < m ? npos : m - 1;
+        const double thp = npos > 0 ? st->theta[npos - 1] : 0.0;
+        const double thg = st->theta[g0];
+        const double dl = npos > 0 ? (thp - thg) : fabs(thg);
+        gtl = fmax(tol, 0.5 * dl);
+      }
+      const bool act = in && rn > ((i <= npos || st->fixed_block) ? tol : gtl);
       const unsigned long long actm = __ballot(act);
       const int nact = __popcll(actm);
       const int pre = __popcll(actm & ((1ull << i) - 1ull));
