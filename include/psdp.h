@@ -248,7 +248,10 @@ psdp_status psdp_project(psdp_handle h, int n, const double *X, int ldx,
  * tol <= 0 picks 1e-8 ||X_i||_F / sqrt(2 m) per cone.  With
  * opt->fallback_full, cones that do not converge are projected exactly by
  * psdp_full_eig_project_batched in the same call (status
- * PSDP_FELL_BACK_FULL_EIG).  Results do not
+ * PSDP_FELL_BACK_FULL_EIG).  The tail term of each cone's bound is the
+ * estimate sqrt(n - m~) max(theta_g + r_g, 0) from its largest
+ * non-positive Ritz pair (info.certified = 0): the batched engine does not
+ * run the certificate, whatever opt->certify says.  Results do not
  * depend on the queue order or the launch shape beyond rounding of the
  * product sums.  info is a HOST array[count]; a cone that does not converge
  * reports PSDP_NOT_CONVERGED with its bound, a non-finite cone
@@ -522,6 +525,15 @@ psdp_status psdp_profile_get(psdp_handle h, const char *family, long *launches,
  * measurement times only the family it reports.  The filter is kept by the
  * handle until changed; PSDP_ERR_INVALID_ARG for a null handle. */
 psdp_status psdp_profile_filter(psdp_handle h, const char *families);
+
+/* Device-to-host copies the library has made (in every call and thread of
+ * the process, the server's workers included) since the last reset: their
+ * count, total bytes and largest single copy.  They are state snapshots,
+ * norms and eigenvalue counts, never a warm-start block: a session's block
+ * (n x m doubles) stays on the device between requests.  reset != 0 clears
+ * the counters after reading them. */
+psdp_status psdp_transfer_stats(long long *copies, long long *bytes, long long *max_bytes,
+                                int reset);
 
 /* Library version string. */
 const char *psdp_version(void);

@@ -27,7 +27,7 @@ from ._abi import (PREC_BF16, PREC_FP32, PREC_FP64, PSDP_ERR_CAPACITY,
                    SIDE_POS, LibraryMissing, load, status_str)
 
 __all__ = ["Projector", "Session", "Server", "Result", "ServedResult", "PsdpError", "load",
-           "status_str", "fortran", "PREC", "SIDE", "LibraryMissing"]
+           "status_str", "fortran", "PREC", "SIDE", "LibraryMissing", "transfer_stats"]
 
 PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 SIDE = {"auto": SIDE_AUTO, "pos": SIDE_POS, "neg": SIDE_NEG, "full": SIDE_FULL}
@@ -429,6 +429,14 @@ class Session:
             self.pos_hint = info["pos_est"]
         self.calls += 1
         return res
+
+
+def transfer_stats(reset: bool = False) -> dict:
+    """Device-to-host copies made by the library (psdp_transfer_stats)."""
+    lib = load()
+    c, b, m = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+    lib.psdp_transfer_stats(ctypes.byref(c), ctypes.byref(b), ctypes.byref(m), 1 if reset else 0)
+    return {"copies": c.value, "bytes": b.value, "max_bytes": m.value}
 
 
 @dataclass

@@ -32,7 +32,7 @@ EXPORTED = [
     "psdp_server_wait", "psdp_server_drain", "psdp_server_session_block",
     "psdp_server_stats_get", "psdp_server_stats_reset", "psdp_full_eig_project_batched",
     "psdp_profile_filter", "psdp_certify_tail", "psdp_block_product_noalloc",
-    "psdp_admm_default_options", "psdp_admm_solve",
+    "psdp_admm_default_options", "psdp_admm_solve", "psdp_transfer_stats",
 ]
 
 ADMM_SOLVED, ADMM_MAX_ITER, ADMM_PRIMAL_INFEASIBLE, ADMM_DUAL_INFEASIBLE = 0, 1, 2, 3
@@ -285,6 +285,8 @@ def load():
     lib.psdp_server_stats_get.restype = ctypes.c_int
     lib.psdp_server_stats_reset.argtypes = [vp]
     lib.psdp_server_stats_reset.restype = ctypes.c_int
+    lib.psdp_transfer_stats.argtypes = [llp, llp, llp, ctypes.c_int]
+    lib.psdp_transfer_stats.restype = ctypes.c_int
     lib.psdp_version.argtypes = []
     lib.psdp_version.restype = ctypes.c_char_p
     _lib = lib

@@ -153,7 +153,7 @@ extern "C" psdp_status psdp_admm_solve(psdp_handle h, const psdp_sdp* pr,
                    double out[kNorms]) -> hipError_t {
     hipError_t e = launch_admm_norms(n, Ym, Zm, Cs, Wm, con_of, aval, ym, part, nblk, s);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(hpart.data(), part, 8 * (size_t)nblk * kNorms, hipMemcpyDeviceToHost, s);
+    e = copy_to_host(hpart.data(), part, 8 * (size_t)nblk * kNorms, s);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
@@ -167,7 +167,7 @@ extern "C" psdp_status psdp_admm_solve(psdp_handle h, const psdp_sdp* pr,
     if (p == 0) return hipSuccess;
     hipError_t e = launch_admm_cdot(cs, M, n, kDotStore, prm, t_d, nullptr, s);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(ht.data(), t_d, 8 * (size_t)p, hipMemcpyDeviceToHost, s);
+    e = copy_to_host(ht.data(), t_d, 8 * (size_t)p, s);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
   };
@@ -272,7 +272,7 @@ extern "C" psdp_status psdp_admm_solve(psdp_handle h, const psdp_sdp* pr,
       double aeq2 = 0.0;
       for (int i = 0; i < p; ++i) aeq2 += ht[i] * ht[i];
       if (p) {
-        ADMM_TRY(hipMemcpyAsync(hy.data(), yp_d, 8 * (size_t)p, hipMemcpyDeviceToHost, s));
+        ADMM_TRY(copy_to_host(hy.data(), yp_d, 8 * (size_t)p, s));
         ADMM_TRY(hipStreamSynchronize(s));
       }
       double dy2 = 0.0, bdy = 0.0;

@@ -23,6 +23,7 @@
 
 #include "../../include/psdp.h"
 #include "batched.h"
+#include "internal.h"
 
 namespace psdp {
 
@@ -330,7 +331,7 @@ psdp_status batch_engine_run(BatchEngine* e, hipStream_t s, int count, const int
   if (ps != PSDP_OK) return ps;
   e->last_ms = ms;
   e->last_variant = vi;
-  BT_TRY(hipMemcpyAsync(e->h_outs, e->d_outs, sizeof(BatchOut) * count, hipMemcpyDeviceToHost, s));
+  BT_TRY(copy_to_host(e->h_outs, e->d_outs, sizeof(BatchOut) * count, s));
   BT_TRY(hipStreamSynchronize(s));
   int worst_err = 0, worst = 0;
   for (int i = 0; i < count; ++i) {

@@ -19,6 +19,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -355,7 +356,7 @@ struct Solver {
   const void* amat(int p) const { return p == 0 ? (const void*)w.A64 : w.Alp; }
 
   psdp_status read_state() {
-    HIP_TRY(hipMemcpyAsync(hs, w.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(copy_to_host(hs, w.st, sizeof(State), s));
     HIP_TRY(spin_wait(h, s));
     return PSDP_OK;
   }
@@ -558,7 +559,7 @@ struct Solver {
     next_slot ^= 1;
     q.ev_begin = first_ev;
     q.ev_end = h->pending.size();
-    HIP_TRY(hipMemcpyAsync(h->h_snap + q.slot, w.st, sizeof(State), hipMemcpyDeviceToHost, s));
+    HIP_TRY(copy_to_host(h->h_snap + q.slot, w.st, sizeof(State), s));
     HIP_TRY(hipEventRecord(h->snap_ev[q.slot], s));
     return PSDP_OK;
   }
@@ -740,7 +741,7 @@ psdp_status run_certificate(psdp_handle h, int n, int mt, double fro2, double de
                               s));
     HIP_TRY(launch_cert_chol(h->cert_M, L, h->cert_dev, s));
   }
-  HIP_TRY(hipMemcpyAsync(hc, h->cert_dev, sizeof(CertState), hipMemcpyDeviceToHost, s));
+  HIP_TRY(copy_to_host(hc, h->cert_dev, sizeof(CertState), s));
   HIP_TRY(hipStreamSynchronize(s));
   *out = *hc;
   *certified = (hc->fail == 0) ? 1 : 0;
@@ -953,8 +954,8 @@ static psdp_status full_eig_core(psdp_handle h, int n, const double* X, int ldx,
   // count positive eigenvalues (ascending order)
   psdp_status pp = ensure_pinned(h, sizeof(double) * (size_t)n + 64);
   if (pp != PSDP_OK) return pp;
-  HIP_TRY(hipMemcpyAsync(h->h_pin, d, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h->h_pin + n, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(copy_to_host(h->h_pin, d, sizeof(double) * n, s));
+  HIP_TRY(copy_to_host(h->h_pin + n, info, sizeof(rocblas_int), s));
   HIP_TRY(hipStreamSynchronize(s));
   int infov = 0;
   std::memcpy(&infov, h->h_pin + n, sizeof(rocblas_int));
@@ -1043,8 +1044,8 @@ extern "C" psdp_status psdp_certify_tail(psdp_handle h, int n, const double* X, 
   int nb = 0;
   HIP_TRY(launch_ingest(X, ldx, n, 1.0, w.A64, w.L, w.L, w.Alp, 0, w.fro_part, w.nonfinite, s, &nb));
   HIP_TRY(launch_reduce_sum(w.fro_part, nb, w.scal, s));
-  HIP_TRY(hipMemcpyAsync(h->h_pin, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h->h_pin + 1, w.nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(copy_to_host(h->h_pin, w.scal, sizeof(double), s));
+  HIP_TRY(copy_to_host(h->h_pin + 1, w.nonfinite, sizeof(int), s));
   HIP_TRY(hipStreamSynchronize(s));
   const double fro2 = h->h_pin[0];
   int nonfin = 0;
@@ -1150,9 +1151,9 @@ static psdp_status full_eig_batched(psdp_handle h, int count, const int* n,
     HIP_TRY(launch_eig_leading(dc + q, cnt, A, D, nb, dout + 2 * q, s));
     q += cnt;
   }
-  HIP_TRY(hipMemcpyAsync(hint, dout, 2 * sizeof(int) * count, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(hint + 2 * count, dbad, sizeof(int) * count, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(hint + 3 * count, dinfo, sizeof(int) * count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(copy_to_host(hint, dout, 2 * sizeof(int) * count, s));
+  HIP_TRY(copy_to_host(hint + 2 * count, dbad, sizeof(int) * count, s));
+  HIP_TRY(copy_to_host(hint + 3 * count, dinfo, sizeof(int) * count, s));
   HIP_TRY(hipStreamSynchronize(s));
   for (int t = 0; t < count; ++t) {
     const int i = order[t];
@@ -1291,6 +1292,20 @@ extern "C" psdp_status psdp_project_batched(psdp_handle h, int count, const int*
 }
 
 namespace psdp {
+namespace {
+std::atomic<long long> g_d2h_copies{0}, g_d2h_bytes{0}, g_d2h_max{0};
+}  // namespace
+
+hipError_t copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  g_d2h_copies.fetch_add(1, std::memory_order_relaxed);
+  g_d2h_bytes.fetch_add((long long)bytes, std::memory_order_relaxed);
+  long long cur = g_d2h_max.load(std::memory_order_relaxed);
+  while ((long long)bytes > cur &&
+         !g_d2h_max.compare_exchange_weak(cur, (long long)bytes, std::memory_order_relaxed)) {
+  }
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s);
+}
+
 int handle_device(psdp_handle h) { return h->device; }
 hipStream_t handle_stream(psdp_handle h) { return h->stream; }
 
@@ -1314,6 +1329,19 @@ int auto_side(int n, int pos_hint, int m_cap, const psdp_options& opt) {
   return side;
 }
 }  // namespace psdp
+
+extern "C" psdp_status psdp_transfer_stats(long long* copies, long long* bytes, long long* max_bytes,
+                                           int reset) {
+  if (copies) *copies = g_d2h_copies.load();
+  if (bytes) *bytes = g_d2h_bytes.load();
+  if (max_bytes) *max_bytes = g_d2h_max.load();
+  if (reset) {
+    g_d2h_copies = 0;
+    g_d2h_bytes = 0;
+    g_d2h_max = 0;
+  }
+  return PSDP_OK;
+}
 
 extern "C" psdp_status psdp_batched_tuning(psdp_handle h, int* variant, double* last_ms) {
   if (!h || !variant || !last_ms) return PSDP_ERR_INVALID_ARG;
@@ -1396,8 +1424,8 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   }
   psdp_status pp = ensure_pinned(h, 64);
   if (pp != PSDP_OK) return pp;
-  HIP_TRY(hipMemcpyAsync(h->h_pin, w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(h->h_pin + 1, w.nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(copy_to_host(h->h_pin, w.scal, sizeof(double), s));
+  HIP_TRY(copy_to_host(h->h_pin + 1, w.nonfinite, sizeof(int), s));
   HIP_TRY(hipStreamSynchronize(s));
   double fro2 = h->h_pin[0];
   int nonfin = 0;

@@ -16,5 +16,8 @@ int block_need(int est, const psdp_options& opt);
 // device and stream a handle enqueues on
 int handle_device(psdp_handle h);
 hipStream_t handle_stream(psdp_handle h);
+// Every device-to-host copy the library makes goes through here: it is
+// counted (copies, bytes, largest single copy) for psdp_transfer_stats.
+hipError_t copy_to_host(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 }  // namespace psdp

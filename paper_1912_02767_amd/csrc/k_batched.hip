@@ -435,10 +435,9 @@ struct ConeSolver {
     if (threadIdx.x == 0) {
       double tail = 0.0;
       if (npos < m) {
-        const double thg = st->guard_theta, rg = st->guard_res;
-        const double delta = npos > 0 ? (st->theta_min_pos - thg) : fabs(thg);
-        const double est = delta > 0.0 ? thg + rg * rg / delta : thg + rg;
-        tail = sqrt((double)(n - npos)) * fmax(est, 0.0);
+        // estimate (uncertified): the largest non-positive Ritz value plus
+        // its residual norm, an eigenvalue lies within r_g of theta_g
+        tail = sqrt((double)(n - npos)) * fmax(st->guard_theta + st->guard_res, 0.0);
       } else if (m < n) {
         tail = INFINITY;  // no non-positive pair in the block to estimate from
       }

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import serving_sessions, session_sequence
+from workloads import gapped_sessions, serving_sessions, session_sequence
 
 pytestmark = pytest.mark.gpu
 
@@ -167,3 +167,46 @@ def test_invalid_requests(gpu):
     with pytest.raises(psdp.PsdpError):
         srv.open_session(10, m_cap=100)
     srv.close()
+
+
+def test_mix_serves_warm_requests_with_the_block_solver(gpu):
+    """Sessions whose spectra keep a gap: after each session's first request
+    (no inertia estimate yet: the exact path) the warm-started requests are
+    served by the block eigensolver on the positive side, in the mix as
+    alone, and match the oracle and their stand-alone results."""
+    torch = gpu
+    import paper_1912_02767_amd as psdp
+    from gpu_util import to_host
+    specs = gapped_sessions(count=5, stream=1)
+    reqs = _requests(specs, steps=4)
+    mix, stats, _ = _serve(psdp, torch, specs, reqs, slots=4, batch_lane=False)
+    alone = _alone(psdp, torch, specs, reqs, slots=4, batch_lane=False)
+    sides = [r.info["side_used"] for r in mix]
+    print("stats", stats, "sides", sides)
+    block = [k for k, s in enumerate(sides) if s == 1]
+    assert len(block) >= len(specs), sides
+    for k in block:
+        assert mix[k].status == 0 and mix[k].info["certified"] == 1, mix[k].info
+    for (i, X), a, b in zip(reqs, mix, alone):
+        Pa, Pb = to_host(a.Pi), to_host(b.Pi)
+        Pi_ref, _ = oracle.project(X)
+        assert oracle.rel_error(Pa, Pi_ref, X) <= REL, (specs[i].n, a.info)
+        assert np.linalg.norm(Pa - Pb) <= 2 * REL * max(np.linalg.norm(Pi_ref), 1e-300)
+
+
+def test_session_blocks_never_copied_to_host(gpu):
+    """While the server works, every device-to-host copy the library makes is
+    smaller than the smallest session block (n x m doubles): the warm-start
+    blocks stay in device memory between requests."""
+    torch = gpu
+    import paper_1912_02767_amd as psdp
+    specs = gapped_sessions(count=4, n_min=200, n_max=400, stream=2)
+    reqs = _requests(specs, steps=4)
+    psdp.transfer_stats(reset=True)
+    res, stats, blocks = _serve(psdp, torch, specs, reqs, slots=3)
+    t = psdp.transfer_stats()
+    smallest_block = min(8 * sp.n * max(1, V.shape[1]) for sp, (V, _) in zip(specs, blocks))
+    print("transfers", t, "smallest block bytes", smallest_block)
+    assert all(r.status >= 0 for r in res)
+    assert t["copies"] > 0
+    assert t["max_bytes"] < smallest_block

@@ -23,7 +23,7 @@ __all__ = [
     "cold_block", "Cone", "HouseholderBasis",
     "single_cone", "warm_sequence", "large_cone", "large_cone_sequence",
     "batched_cones", "serving_sessions", "poisson_arrivals", "SessionSpec",
-    "session_sequence",
+    "session_sequence", "gapped_sessions",
     "random_spectrum_matrix",
 ]
 
@@ -225,6 +225,21 @@ def serving_sessions(count: int = 64, n_min: int = 32, n_max: int = 2048,
         if build:
             Q = haar_orthogonal(n, rng)
             cone = Cone(from_spectrum(Q, lam), lam, Q)
+        out.append(SessionSpec(s, n, p, cone))
+    return out
+
+
+def gapped_sessions(count: int = 6, n_min: int = 150, n_max: int = 500, frac_pos: float = 0.05,
+                    stream: int = 0) -> List[SessionSpec]:
+    """Sessions whose spectra keep a gap under the 1e-3 ||X||_F perturbations
+    of session_sequence: p = max(1, round(frac_pos n)) eigenvalues U[1, 10],
+    the rest U[-10, -0.1], Haar basis, n log-uniform in [n_min, n_max]."""
+    rng = rng_for(5, 50_000 + stream)
+    out = []
+    for s in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        p = max(1, int(round(frac_pos * n)))
+        cone = random_spectrum_matrix(n, p, rng, pos=(1.0, 10.0), neg=(-10.0, -0.1))
         out.append(SessionSpec(s, n, p, cone))
     return out
 
