@@ -129,7 +129,9 @@ typedef struct {
                             /* uses                                               */
     int method;             /* psdp_method (default PSDP_METHOD_LOBPCG)           */
     int method_param;       /* BLOCK_KRYLOV: block iterations (0 = 1);            */
-                            /* TOP_R: r, the block width (>= 1)                   */
+                            /* TOP_R: r, the block width (>= 1);                  */
+                            /* CHEBYSHEV: largest filter degree per pass (0 = 24, */
+                            /* at most 64)                                        */
 } psdp_options;
 
 /* Eigensolvers behind psdp_project (paper §5, the block Krylov discussion,
@@ -142,12 +144,21 @@ typedef enum {
                                   /* Lanczos iteration each, restarted), no      */
                                   /* convergence loop; OK only when the stopping */
                                   /* rule then holds                             */
-    PSDP_METHOD_TOP_R = 2         /* the r = method_param largest Ritz pairs     */
+    PSDP_METHOD_TOP_R = 2,        /* the r = method_param largest Ritz pairs     */
                                   /* (fixed block, no guard, no expansion) and   */
                                   /* Pi~ = sum_{i<=r} max(theta_i, 0) v_i v_i^T; */
                                   /* status says whether the r pairs met tol;    */
                                   /* info.trunc_bound = sqrt(n - r) max(theta_r, */
                                   /* 0), the bound that assumes exact pairs      */
+    PSDP_METHOD_CHEBYSHEV = 3     /* polynomial subspace extraction (§1): passes */
+                                  /* of X <- T_d((A - c) / e) X, the Chebyshev   */
+                                  /* polynomial of degree d damping [lo, theta_m]*/
+                                  /* (lo from 10 Lanczos steps, theta_m the      */
+                                  /* block's smallest Ritz value), each followed */
+                                  /* by Rayleigh-Ritz on span(X) with an FP64    */
+                                  /* product, until the same stopping rule as    */
+                                  /* LOBPCG holds; products in FP64; the same    */
+                                  /* bound and certificate; info.iters = passes  */
 } psdp_method;
 
 typedef struct {
@@ -182,6 +193,10 @@ typedef struct {
     double cert_eta;    /* its rounding margin eta (NaN when not run)             */
     double trunc_bound; /* PSDP_METHOD_TOP_R: sqrt(n - r) max(theta_r, 0), else  */
                         /* NaN                                                    */
+    double spec_lower;  /* PSDP_METHOD_CHEBYSHEV: the lower end of the damped     */
+                        /* interval (a bound on the smallest eigenvalue), else NaN*/
+    int products;       /* PSDP_METHOD_CHEBYSHEV: products with A (filter,        */
+                        /* Rayleigh-Ritz and Lanczos), else 0                     */
 } psdp_info;
 
 /* Fill *opt with the defaults documented above. */

@@ -32,7 +32,7 @@ __all__ = ["Projector", "Session", "Server", "Result", "ServedResult", "PsdpErro
 PREC = {"fp64": PREC_FP64, "fp32": PREC_FP32, "bf16": PREC_BF16}
 SIDE = {"auto": SIDE_AUTO, "pos": SIDE_POS, "neg": SIDE_NEG, "full": SIDE_FULL}
 METHOD = {"lobpcg": _abi.METHOD_LOBPCG, "block_krylov": _abi.METHOD_BLOCK_KRYLOV,
-          "top_r": _abi.METHOD_TOP_R}
+          "top_r": _abi.METHOD_TOP_R, "chebyshev": _abi.METHOD_CHEBYSHEV}
 
 
 class PsdpError(RuntimeError):

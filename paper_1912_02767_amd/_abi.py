@@ -18,7 +18,7 @@ PSDP_ERR_NUMERICAL = -4
 PSDP_ERR_CAPACITY = -5
 
 SIDE_AUTO, SIDE_POS, SIDE_NEG, SIDE_FULL = 0, 1, 2, 3
-METHOD_LOBPCG, METHOD_BLOCK_KRYLOV, METHOD_TOP_R = 0, 1, 2
+METHOD_LOBPCG, METHOD_BLOCK_KRYLOV, METHOD_TOP_R, METHOD_CHEBYSHEV = 0, 1, 2, 3
 PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 
 # every symbol include/psdp.h declares
@@ -85,6 +85,8 @@ class Info(ctypes.Structure):
         ("cert_delta", ctypes.c_double),
         ("cert_eta", ctypes.c_double),
         ("trunc_bound", ctypes.c_double),
+        ("spec_lower", ctypes.c_double),
+        ("products", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpsdp.so")
-SOURCES = ["k_tall.hip", "k_small.hip", "k_cert.hip", "k_admm.hip", "admm.cpp", "k_rr_tri.hip", "k_product.hip", "k_batched.hip", "k_batched_eig.hip", "batched_host.cpp",
+SOURCES = ["k_tall.hip", "k_small.hip", "k_cert.hip", "k_cheb.hip", "k_admm.hip", "admm.cpp", "k_rr_tri.hip", "k_product.hip", "k_batched.hip", "k_batched_eig.hip", "batched_host.cpp",
            "driver.cpp", "server.cpp", "noalloc.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -251,6 +251,15 @@ hipError_t small_kernels_init();
 
 // ------------------------------------------------------------------ launch
 // Host-side launch helpers (defined in the kernel files).
+// Optional epilogue of a block product: Y = ca (A S) + cb B1 + cc B0 (B0 may
+// be null), B1 and B0 n x cols with leading dim ld, neither aliasing Y.
+struct ProductComb {
+  const double* b1;
+  const double* b0;
+  int ld;
+  double ca, cb, cc;
+};
+
 struct ProductArgs {
   const void* A;     // FP64 / FP32 / BF16 matrix, column-major, leading dim lda
   int lda;
@@ -267,6 +276,7 @@ struct ProductArgs {
   size_t partial_bytes;
   int max_slices;       // split-K slices the partial buffer holds
   const int* stop;      // device stop flag: the launch is a no-op when set
+  ProductComb comb;     // b1 == nullptr: plain product
 };
 
 hipError_t launch_ingest(const double* X, int ldx, int n, double sign, double* A64, int lda,
@@ -274,6 +284,11 @@ hipError_t launch_ingest(const double* X, int ldx, int n, double sign, double* A
                          hipStream_t st, int* nblocks_out);
 hipError_t launch_reduce_sum(const double* partial, int count, double* out, hipStream_t st);
 hipError_t launch_product(const ProductArgs& a, hipStream_t st);
+hipError_t launch_axpby3(int n, int cols, double ca, const double* Y, int ldy, double cb,
+                         const double* B1, int ld1, double cc, const double* B0, int ld0,
+                         double* out, int ldo, hipStream_t st);
+hipError_t launch_lanczos_vec(int n, int step, int last, double* w, const double* v,
+                              const double* vprev, double* coef, double* out, hipStream_t st);
 hipError_t launch_fill_normal(double* B, int ld, int n, int col0, int cols, uint64_t seed,
                               uint64_t stream_id, hipStream_t st);
 hipError_t launch_copy_cols(const double* src, int lds, double* dst, int ldd, int n, int cols,

@@ -104,6 +104,7 @@ struct Workspace {
   double* scal = nullptr;  // [0] fro2
   int* nonfinite = nullptr;
   State* st = nullptr;
+  double* lz = nullptr;  // Lanczos bound: three vectors (ld L), coefficients, result
 };
 
 }  // namespace
@@ -196,8 +197,9 @@ struct ProfScope {
   const char* fam;
   hipEvent_t a = nullptr, b = nullptr;
   double bytes, flops;
-  ProfScope(psdp_handle h_, const char* f, double by = 0, double fl = 0)
-      : h(h_), fam(f), bytes(by), flops(fl) {
+  int prec;
+  ProfScope(psdp_handle h_, const char* f, double by = 0, double fl = 0, int pr = -1)
+      : h(h_), fam(f), bytes(by), flops(fl), prec(pr) {
     if (h->prof && (h->prof_only.empty() || h->prof_only.count(f))) {
       a = get_event(h);
       b = get_event(h);
@@ -207,7 +209,7 @@ struct ProfScope {
   ~ProfScope() {
     if (a && b) {
       (void)hipEventRecord(b, h->stream);
-      h->pending.push_back({fam, a, b, bytes, flops, -1});
+      h->pending.push_back({fam, a, b, bytes, flops, prec});
     }
   }
 };
@@ -284,6 +286,7 @@ psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
   size_t oScal = take(sizeof(double) * 16);
   size_t oNf = take(sizeof(int) * 16);
   size_t oSt = take(sizeof(State));
+  size_t oLz = take(sizeof(double) * (3 * (size_t)L + 128));
   if (w.base) {
     (void)hipStreamSynchronize(h->stream);
     hipFree(w.base);
@@ -322,6 +325,7 @@ psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
   w.scal = (double*)(base + oScal);
   w.nonfinite = (int*)(base + oNf);
   w.st = (State*)(base + oSt);
+  w.lz = (double*)(base + oLz);
   // zero everything once so padded rows are zero
   HIP_TRY(hipMemsetAsync(base, 0, sz, h->stream));
   return PSDP_OK;
@@ -655,6 +659,49 @@ struct Solver {
   }
 };
 
+
+// Lower bound on the smallest eigenvalue of the ingested matrix: `steps`
+// plain Lanczos steps from a seeded random vector (products at precision
+// `prec`), then theta_min(T) - beta_steps (Zhou and Saad's estimator; the
+// Ritz value lies above the spectrum's lower end and the last coupling
+// bounds how far).  Used for the damped interval of the Chebyshev filter.
+psdp_status lanczos_lower(psdp_handle h, int n, int prec, int steps, uint64_t seed,
+                          uint64_t stream_id, double* lo, double* theta_min) {
+  Workspace& w = h->ws;
+  hipStream_t s = h->stream;
+  const int L = w.L;
+  steps = std::max(1, std::min(steps, std::min(n, 30)));
+  double* vb[3] = {w.lz, w.lz + L, w.lz + 2 * (size_t)L};
+  double* coef = w.lz + 3 * (size_t)L;
+  double* out = coef + 96;
+  HIP_TRY(launch_fill_normal(vb[0], L, n, 0, 1, seed, stream_id, s));
+  HIP_TRY(launch_lanczos_vec(n, -1, 0, vb[0], nullptr, nullptr, coef, out, s));
+  int iv = 0, iw = 1, ip = 2;
+  for (int j = 0; j < steps; ++j) {
+    {
+      ProfScope ps(h, "lanczos", (double)product_elem_bytes(prec) * n * (double)n + 16.0 * n,
+                   2.0 * n * (double)n);
+      ProductArgs pa{};
+      pa.A = prec == 0 ? (const void*)w.A64 : w.Alp; pa.lda = L; pa.n = n; pa.prec = prec;
+      pa.S = vb[iv]; pa.lds = L; pa.Y = vb[iw]; pa.ldy = L;
+      pa.cols_dev = nullptr; pa.cols_max = 1; pa.stop = nullptr;
+      pa.partial = w.ppart; pa.partial_bytes = w.ppart_bytes; pa.max_slices = kProductSlices;
+      HIP_TRY(launch_product(pa, s));
+      HIP_TRY(launch_lanczos_vec(n, j, j == steps - 1, vb[iw], vb[iv], vb[ip], coef, out, s));
+    }
+    const int t = ip;
+    ip = iv;
+    iv = iw;
+    iw = t;
+  }
+  psdp_status pp = ensure_pinned(h, 64);
+  if (pp != PSDP_OK) return pp;
+  HIP_TRY(copy_to_host(h->h_pin, out, 3 * sizeof(double), s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *lo = h->h_pin[0];
+  *theta_min = h->h_pin[1];
+  return std::isfinite(*lo) ? PSDP_OK : PSDP_ERR_NUMERICAL;
+}
 
 psdp_status ensure_cert(psdp_handle h, int L) {
   if (h->cert_base && h->cert_L >= L) return PSDP_OK;
@@ -1076,6 +1123,7 @@ static void fill_info_defaults(psdp_info* info) {
   info->cert_delta = NAN;
   info->cert_eta = NAN;
   info->trunc_bound = NAN;
+  info->spec_lower = NAN;
 }
 
 // Exact projection of many cones (n <= 256) through zero-padded buckets of
@@ -1366,7 +1414,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   if (opt.max_iter < 1 || opt.certify < 0 || opt.certify > 1 || !(opt.side_threshold > 0.0) ||
       opt.side_threshold > 0.5 || opt.expand_cols < 0 || opt.pos_hint > n ||
       !(opt.certify_delta >= 0.0) || opt.warm_side < 0 || opt.warm_side > 2 ||
-      opt.method < PSDP_METHOD_LOBPCG || opt.method > PSDP_METHOD_TOP_R ||
+      opt.method < PSDP_METHOD_LOBPCG || opt.method > PSDP_METHOD_CHEBYSHEV ||
       (opt.method == PSDP_METHOD_TOP_R && opt.method_param < 1) || opt.method_param < 0)
     return PSDP_ERR_INVALID_ARG;
   if ((const void*)Pi == (const void*)X) return PSDP_ERR_INVALID_ARG;
@@ -1484,6 +1532,128 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       if (stp == kConverged) converged = true;
       if (stp != kRunning) break;  // converged (or stopped) before the step
       sv.has_p = 0;
+    }
+    finished = true;
+  }
+  int cheb_passes = 0, cheb_products = 0;
+  double cheb_lo = NAN;
+  int pre_cert = -1;  // certificate already run on the final block: its result
+  CertState pre_cs{};
+  if (opt.method == PSDP_METHOD_CHEBYSHEV) {
+    // Chebyshev-filtered subspace iteration: X <- T_d((A - c) / e) X with the
+    // interval [lo, theta_m] (the spectrum's lower end to the smallest Ritz
+    // value of the block) damped to |T_d| <= 1 and the positive Ritz values
+    // amplified by T_d at their scaled position, then Rayleigh-Ritz on
+    // span(X) with an FP64 product; repeated until the stopping rule holds.
+    double thmin = 0.0;
+    rc = lanczos_lower(h, n, prec0, 10, seed, rng_stream++, &cheb_lo, &thmin);
+    if (rc != PSDP_OK) { info->status = rc; return rc; }
+    cheb_lo -= 1e-2 * std::fabs(cheb_lo);  // margin for the rounding of the bound
+    cheb_products += 10;
+    const int dmax = opt.method_param > 0 ? std::min(opt.method_param, 64) : 24;
+    const int max_pass = std::max(1, std::min(opt.max_iter, 200));
+    const int L = w.L;
+    for (;;) {
+      rc = sv.evaluate();
+      if (rc != PSDP_OK) { info->status = rc; return rc; }
+      const State& st = *h->h_state;
+      const int ev = st.eval_stop;
+      if (ev == kNonFinite) { info->status = PSDP_ERR_NUMERICAL; return PSDP_ERR_NUMERICAL; }
+      const int m = sv.m, np = st.npos_blk;
+      bool expand = np >= m || ev == kExpand;
+      if (ev == kConverged) {
+        // the stopping rule judges the guard pair against half its gap to
+        // the smallest positive Ritz value, which a block still far from the
+        // top of the spectrum can meet: with the certificate on, it decides
+        if (!opt.certify || np >= n) { converged = true; break; }
+        const double delta = opt.certify_delta > 0.0
+                                 ? opt.certify_delta
+                                 : std::sqrt(2.0 * std::max(np, 1)) * tol / std::sqrt((double)n);
+        rc = run_certificate(h, n, np, fro2, delta, &pre_cert, &pre_cs);
+        if (rc != PSDP_OK) { info->status = rc; return rc; }
+        if (pre_cert) { converged = true; break; }
+        pre_cert = -1;  // a positive eigenvalue outside the block: filter on
+      }
+      if (expand) {
+        // no non-positive Ritz pair left in the block: append columns
+        int e = opt.expand_cols > 0 ? opt.expand_cols : (n + 49) / 50;
+        e = std::min(std::max(1, e), sv.mcap - sv.m);
+        if (e <= 0) {
+          if (opt.fallback_full) fell_back = 1;
+          break;
+        }
+        HIP_TRY(launch_fill_normal(w.Z, L, n, 0, e, seed, rng_stream++, s));
+        rc = sv.iterate(kModeXZ, 0, sv.m + e, e);
+        if (rc != PSDP_OK) { info->status = rc; return rc; }
+        sv.has_p = 0;
+        cheb_products += 1;
+        expansions += 1;
+        continue;
+      }
+      if (cheb_passes >= max_pass) break;
+      ++cheb_passes;
+      // filter degree: enough to bring the largest positive residual below
+      // tol (with a factor 4 in hand) at the smallest positive Ritz value's
+      // amplification, at most dmax, and with the amplification of the top
+      // of the spectrum at most 1e5 times that of the smallest positive
+      // value (so the filtered columns stay numerically independent)
+      const double b = st.theta[m - 1];
+      const double a = std::min(cheb_lo, b - 1e-3 * std::max(std::fabs(b), 1e-300));
+      const double c = 0.5 * (a + b), e = 0.5 * (b - a);
+      const double thp = np > 0 ? st.theta[np - 1] : st.theta[0];
+      const double xp = std::max((thp - c) / e, 1.0 + 1e-12);
+      const double xmax = std::max((st.theta[0] + st.res_max_pos - c) / e, xp);
+      double ratio = st.res_max_pos / tol;
+      if (np < m && std::isfinite(st.guard_res)) {
+        const double gap = np > 0 ? st.theta[np - 1] - st.guard_theta : std::fabs(st.guard_theta);
+        ratio = std::max(ratio, st.guard_res / std::max(tol, 0.5 * gap));
+      }
+      const double need = 4.0 * std::max(ratio, 2.0);
+      const double ap = std::acosh(xp);
+      int d = (int)std::ceil(std::acosh(need) / ap);
+      const double spread = std::acosh(xmax) - ap;
+      if (spread > 0) d = std::min(d, (int)(std::log(1e5) / spread));
+      d = std::max(2, std::min(d, dmax));
+      // Y0 = X, Y1 = (AX - c X) / e (AX exact from the last Rayleigh-Ritz),
+      // Y_{k+1} = 2 (A Y_k - c Y_k) / e - Y_{k-1} through the product epilogue
+      double* yb[3] = {w.X, w.R, w.P};
+      {
+        ProfScope ps(h, "tsmm", 24.0 * n * (double)m, 3.0 * n * (double)m);
+        HIP_TRY(launch_axpby3(n, m, 1.0 / e, w.AX, L, -c / e, w.X, L, 0.0, nullptr, L, w.R, L, s));
+      }
+      int i0 = 0, i1 = 1;
+      for (int k = 2; k <= d; ++k) {
+        const int i2 = 3 - i0 - i1;
+        ProfScope ps(h, "product", (double)product_elem_bytes(0) * n * (double)n + 40.0 * n * m,
+                     2.0 * n * (double)n * m, 0);
+        ProductArgs pa{};
+        pa.A = w.A64; pa.lda = L; pa.n = n; pa.prec = 0;
+        pa.S = yb[i1]; pa.lds = L; pa.Y = yb[i2]; pa.ldy = L;
+        pa.cols_dev = nullptr; pa.cols_max = m; pa.stop = nullptr;
+        pa.partial = w.ppart; pa.partial_bytes = w.ppart_bytes; pa.max_slices = kProductSlices;
+        pa.comb.b1 = yb[i1]; pa.comb.b0 = yb[i0]; pa.comb.ld = L;
+        pa.comb.ca = 2.0 / e; pa.comb.cb = -2.0 * c / e; pa.comb.cc = -1.0;
+        HIP_TRY(launch_product(pa, s));
+        i0 = i1;
+        i1 = i2;
+      }
+      cheb_products += d - 1;
+      if (i1 != 0) HIP_TRY(launch_copy_cols(yb[i1], L, w.X, L, n, m, s));
+      if (h->trace)
+        std::fprintf(stderr, "psdp: chebyshev pass %d degree %d interval [%.4e, %.4e] xp %.6f "
+                     "rmax %.3e tol %.3e npos %d m %d\n", cheb_passes, d, a, b, xp,
+                     st.res_max_pos, tol, np, m);
+      // Rayleigh-Ritz on span(X); columns the Cholesky-QR drops as dependent
+      // are replaced by seeded random ones
+      sv.has_p = 0;
+      for (int attempt = 0; attempt < 4; ++attempt) {
+        rc = sv.iterate(kModeXOnly, 0, m, 0);
+        if (rc != PSDP_OK) { info->status = rc; return rc; }
+        cheb_products += 1;
+        if (sv.m >= m) break;
+        HIP_TRY(launch_fill_normal(w.X, L, n, sv.m, m - sv.m, seed, rng_stream++, s));
+        sv.m = m;
+      }
     }
     finished = true;
   }
@@ -1676,8 +1846,13 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
                              ? opt.certify_delta
                              : std::sqrt(2.0 * std::max(npos, 1)) * tol / std::sqrt((double)n);
     CertState cs{};
-    rc = run_certificate(h, n, npos, fro2, delta, &certified, &cs);
-    if (rc != PSDP_OK) { info->status = rc; return rc; }
+    if (pre_cert >= 0) {
+      certified = pre_cert;  // the filtered iteration's stopping test ran it on this block
+      cs = pre_cs;
+    } else {
+      rc = run_certificate(h, n, npos, fro2, delta, &certified, &cs);
+      if (rc != PSDP_OK) { info->status = rc; return rc; }
+    }
     cert_delta = cs.delta_eff;
     cert_eta = cs.eta;
     if (certified) tail = std::sqrt((double)(n - npos)) * cert_delta;
@@ -1739,6 +1914,11 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   info->block_side = side;
   if (top_r)
     info->trunc_bound = std::sqrt((double)std::max(n - m, 0)) * std::max(st.theta[m - 1], 0.0);
+  if (opt.method == PSDP_METHOD_CHEBYSHEV) {
+    info->iters = cheb_passes;
+    info->products = cheb_products;
+    info->spec_lower = cheb_lo;
+  }
   info->expansions = expansions;
   info->prec_final = phase;
   info->status = converged ? PSDP_OK : PSDP_NOT_CONVERGED;

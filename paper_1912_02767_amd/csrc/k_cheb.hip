@@ -1,0 +1,141 @@
+// Kernels of the Chebyshev-filtered subspace iteration behind
+// PSDP_METHOD_CHEBYSHEV (a polynomial subspace-extraction variant of the
+// block eigensolver, paper §1 on polynomial subspace extraction and §5 on
+// block Krylov methods):
+//
+//  * k_axpby3: out = ca Y + cb B1 + cc B0 on n x cols column blocks, the
+//    three-term recurrence of the Chebyshev polynomials where the product
+//    A B1 is already in Y (the MFMA path folds the same combination into its
+//    split-K reduction instead);
+//  * k_lanczos_vec: one step of the plain Lanczos recurrence on a single
+//    vector (one workgroup), and after the last step the smallest eigenvalue
+//    of the tridiagonal by Sturm bisection, from which the lower end of the
+//    spectrum is bounded (theta_min - beta_k, the Zhou-Saad estimator).
+#include "common.h"
+
+namespace psdp {
+
+__global__ __launch_bounds__(256) void k_axpby3(int n, int cols, double ca,
+                                                const double* __restrict__ Y, int ldy, double cb,
+                                                const double* __restrict__ B1, int ld1, double cc,
+                                                const double* __restrict__ B0, int ld0,
+                                                double* out, int ldo) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int i = (int)(e % (size_t)n), j = (int)(e / (size_t)n);
+  if (j >= cols) return;
+  double v = ca * Y[i + (size_t)j * ldy] + cb * B1[i + (size_t)j * ld1];
+  if (B0) v += cc * B0[i + (size_t)j * ld0];
+  out[i + (size_t)j * ldo] = v;
+}
+
+hipError_t launch_axpby3(int n, int cols, double ca, const double* Y, int ldy, double cb,
+                         const double* B1, int ld1, double cc, const double* B0, int ld0,
+                         double* out, int ldo, hipStream_t st) {
+  if (n <= 0 || cols <= 0) return hipSuccess;
+  const size_t total = (size_t)n * cols;
+  hipLaunchKernelGGL(k_axpby3, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, cols,
+                     ca, Y, ldy, cb, B1, ld1, cc, B0, ld0, out, ldo);
+  return hipGetLastError();
+}
+
+constexpr int kLzThreads = 1024;
+
+__device__ inline double lz_block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < kLzThreads / 64; ++q) s += red[q];  // same order in every thread
+  return s;
+}
+
+// Sturm count: eigenvalues of the k x k tridiagonal (alpha, beta[1..k-1])
+// below x
+__device__ inline int sturm_below(const double* al, const double* be, int k, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  for (int i = 0; i < k; ++i) {
+    const double b2 = i > 0 ? be[i] * be[i] : 0.0;
+    q = (al[i] - x) - (i > 0 ? b2 / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// coef: alpha[0..31], beta[32..64] (beta[32 + j] = beta_j, beta_0 = 0),
+// out[0] = lower bound, out[1] = theta_min, out[2] = last beta.
+//   step < 0 : v <- v / ||v||
+//   step j   : w <- w - beta_j vprev; alpha_j = w.v; w <- w - alpha_j v;
+//              beta_{j+1} = ||w||; w <- w / beta_{j+1}  (the next v)
+//   last     : bound from T_{j+1}
+__global__ __launch_bounds__(kLzThreads) void k_lanczos_vec(int n, int step, int last,
+                                                            double* __restrict__ w,
+                                                            const double* __restrict__ v,
+                                                            const double* __restrict__ vprev,
+                                                            double* coef, double* out) {
+  __shared__ double red[kLzThreads / 64];
+  const int tid = threadIdx.x;
+  if (step < 0) {
+    double s = 0.0;
+    for (int i = tid; i < n; i += kLzThreads) s += w[i] * w[i];
+    s = lz_block_sum(s, red);
+    const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int i = tid; i < n; i += kLzThreads) w[i] *= sc;
+    return;
+  }
+  const double bj = step > 0 ? coef[32 + step] : 0.0;
+  double s = 0.0;
+  for (int i = tid; i < n; i += kLzThreads) {
+    const double x = w[i] - (step > 0 ? bj * vprev[i] : 0.0);
+    w[i] = x;
+    s += x * v[i];
+  }
+  const double al = lz_block_sum(s, red);
+  double s2 = 0.0;
+  for (int i = tid; i < n; i += kLzThreads) {
+    const double x = w[i] - al * v[i];
+    w[i] = x;
+    s2 += x * x;
+  }
+  const double b = sqrt(lz_block_sum(s2, red));
+  // breakdown (an invariant subspace): the next vector is zero, so later
+  // steps add zero rows whose eigenvalue 0 only loosens the bound
+  const double sc = b > 1e-300 ? 1.0 / b : 0.0;
+  for (int i = tid; i < n; i += kLzThreads) w[i] *= sc;
+  if (tid == 0) {
+    coef[step] = al;
+    coef[32 + step + 1] = b;
+    if (last) {
+      const int k = step + 1;
+      const double* A = coef;
+      const double* B = coef + 32;  // B[i] couples rows i - 1 and i
+      double lo = A[0], hi = A[0];
+      for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(B[i]) : 0.0) + (i + 1 < k ? fabs(B[i + 1]) : 0.0);
+        lo = fmin(lo, A[i] - r);
+        hi = fmax(hi, A[i] + r);
+      }
+      // smallest eigenvalue: the largest x with no eigenvalue below it
+      for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (sturm_below(A, B, k, mid) >= 1) hi = mid; else lo = mid;
+      }
+      out[1] = lo;
+      out[2] = b;
+      out[0] = lo - b;
+    }
+  }
+}
+
+hipError_t launch_lanczos_vec(int n, int step, int last, double* w, const double* v,
+                              const double* vprev, double* coef, double* out, hipStream_t st) {
+  if (step > 30) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lanczos_vec, dim3(1), dim3(kLzThreads), 0, st, n, step, last, w, v, vprev,
+                     coef, out);
+  return hipGetLastError();
+}
+
+}  // namespace psdp

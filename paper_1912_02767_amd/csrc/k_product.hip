@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_product_reduce(const part_t* __restrict
                                                         size_t part_stride, int ldp, int n,
                                                         const int* cols_dev, int cols_host,
                                                         double* __restrict__ Y, int ldy,
-                                                        const int* stop) {
+                                                        const int* stop, ProductComb cb) {
   if (stop && *stop) return;
   const int cols = cols_dev ? *cols_dev : cols_host;
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -274,6 +274,12 @@ __global__ __launch_bounds__(256) void k_product_reduce(const part_t* __restrict
 #pragma unroll
     for (int u = 0; u < 16; ++u)
       if (q0 + u < nsl) s += (double)v[u];
+  }
+  if (cb.b1) {
+    // fused three-term combination: Y = ca (A S) + cb B1 + cc B0
+    double v = cb.ca * s + cb.cb * cb.b1[i + (size_t)j * cb.ld];
+    if (cb.b0) v += cb.cc * cb.b0[i + (size_t)j * cb.ld];
+    s = v;
   }
   Y[i + (size_t)j * ldy] = s;
 }
@@ -325,13 +331,19 @@ hipError_t launch_product(const ProductArgs& a, hipStream_t st) {
     dim3 rg((unsigned)((total + 255) / 256));
     if (a.prec == 0)
       hipLaunchKernelGGL(k_product_reduce<double>, rg, dim3(256), 0, st, (const double*)a.partial,
-                         sk, pstride, a.lda, a.n, a.cols_dev, a.cols_max, a.Y, a.ldy, a.stop);
+                         sk, pstride, a.lda, a.n, a.cols_dev, a.cols_max, a.Y, a.ldy, a.stop,
+                         a.comb);
     else
       hipLaunchKernelGGL(k_product_reduce<float>, rg, dim3(256), 0, st, (const float*)a.partial,
-                         sk, pstride, a.lda, a.n, a.cols_dev, a.cols_max, a.Y, a.ldy, a.stop);
+                         sk, pstride, a.lda, a.n, a.cols_dev, a.cols_max, a.Y, a.ldy, a.stop,
+                         a.comb);
     return hipGetLastError();
   }
-  return launch_product_ref(a, st);
+  hipError_t e = launch_product_ref(a, st);
+  if (e != hipSuccess || !a.comb.b1) return e;
+  if (a.cols_dev) return hipErrorInvalidValue;  // the combination takes a host column count
+  return launch_axpby3(a.n, a.cols_max, a.comb.ca, a.Y, a.ldy, a.comb.cb, a.comb.b1, a.comb.ld,
+                       a.comb.cc, a.comb.b0, a.comb.ld, a.Y, a.ldy, st);
 }
 
 hipError_t launch_product_ref(const ProductArgs& a, hipStream_t st) {
