@@ -25,14 +25,16 @@ Workloads (one step = one pass of the whole projection path):
                   the block eigensolver at the paper's 10/k^1.01 tolerance; value =
                   projections/s inside the block-solver run, with the per-iteration
                   projection time of both runs.
-  serving_mix     Poisson arrivals at 2000 requests/s for --serve-seconds from
-                  64 sessions (n log-uniform in [32, 2048], 1-20% positive,
-                  magnitudes 10^U[-3,2], warm-start sequences at 1e-3 ||X||_F)
-                  through the serving loop; value = served requests/s, beside
-                  the plain path (one projection at a time, same arrivals).
+  serving_mix     Poisson arrivals at 2000 requests/s for --serve-seconds (after
+                  2 s of warm-up) from 64 sessions (n log-uniform in [32, 2048],
+                  1-20% positive, magnitudes 10^U[-3,2], warm-start sequences at
+                  1e-3 ||X||_F, each request generated on the device when it
+                  arrives) through the serving loop; value = served requests/s,
+                  with p50/p99 latency, rejections and the fraction served by the
+                  block solver, beside the plain path (one projection at a time).
 
 Prints ONE JSON line.  Inputs are generated on the host (seeded) and
-uploaded before the timed region.  Every timed step of a sequence is checked
+uploaded before the timed region (serving_mix: on the device, see above).  Every timed step of a sequence is checked
 against the full eigendecomposition of the same matrix; `value` counts only
 the steps within 1e-6.  The cpu_baseline leg times the FP64 Jacobi oracle on
 a sample of the same matrices at full size (one n = 4000 matrix takes about
@@ -59,7 +61,7 @@ PEAKS = {  # MI355X published dense peaks
     "fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12,
 }
 FAMILIES = ["product", "gram", "tsmm", "chol", "rr", "rrback", "rebuild", "ingest", "cert",
-            "batched", "fulleig"]
+            "lanczos", "batched", "fulleig"]
 LIBRARY_FAMILIES = {"fulleig"}  # rocSOLVER calls, not hand-written kernels
 KERNEL_TABLE_STEPS = 10   # untimed steps that time every family
 
@@ -214,13 +216,13 @@ def run_sequence(args, torch, psdp):
 
     proj = psdp.Projector(0)
 
-    def session():
+    def session(method=args.method):
         # AUTO side (paper §6) from the previous call's inertia; the tail of
         # the bound is certified; a step the block solver cannot certify, or
         # whose bound is above 1e-6 ||Pi||_F at n = 4000, takes the exact path
         return psdp.Session(proj, n, m_cap=m_cap, tol=tol, side="auto", pos_hint=p, prec=prec,
                             block_guard=block - p, fallback_full=True,
-                            bound_rel_max=(1e-6 if big else 0.0))
+                            bound_rel_max=(1e-6 if big else 0.0), method=method)
 
     # untimed pass over every kernel family (the kernel table; it also names
     # the dominant hand-written family that the timed region times)
@@ -273,17 +275,43 @@ def run_sequence(args, torch, psdp):
     proj.full_eig(Xs[warm])
     torch.cuda.synchronize()
     t_fe, rel_vs_fe = 0.0, []
-    Pi_f = psdp._empty_f(n, n, dev)
+    Pi_fs = []
     for i in range(steps):
+        Pi_f = psdp._empty_f(n, n, dev)
         torch.cuda.synchronize()
         t = time.perf_counter()
         proj.full_eig(Xs[warm + i], Pi_out=Pi_f)
         torch.cuda.synchronize()
         t_fe += time.perf_counter() - t
+        Pi_fs.append(Pi_f)
         rel_vs_fe.append(float(torch.linalg.norm(outs[i] - Pi_f) / torch.linalg.norm(Pi_f)))
     fe_rate = steps / t_fe
     bad = [warm + i for i, r in enumerate(rel_vs_fe) if not r <= 1e-6]
     ok_steps = steps - len(bad)
+
+    # the other eigensolver on the same matrices (fresh session, same
+    # warm-up), checked against the same full eigendecompositions
+    other = "lobpcg" if args.method == "chebyshev" else "chebyshev"
+    sess = session(other)
+    for k in range(warm):
+        sess.project(Xs[k], Pi_out=Pis[k % 2])
+    o_infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        o_infos.append(sess.project(Xs[warm + i], Pi_out=outs[i]).info)
+    torch.cuda.synchronize()
+    o_wall = time.perf_counter() - t0
+    o_rel = [float(torch.linalg.norm(outs[i] - Pi_fs[i]) / torch.linalg.norm(Pi_fs[i]))
+             for i in range(steps)]
+    o_ok = sum(1 for r in o_rel if r <= 1e-6)
+    other_method = {"method": other, "value": o_ok / o_wall, "unit": "projections/s",
+                    "ms_per_step": 1e3 * o_wall / steps,
+                    "speedup_vs_full_eig": (o_ok / o_wall) / fe_rate,
+                    "steps_over_1e-6": [warm + i for i, r in enumerate(o_rel) if not r <= 1e-6],
+                    "iters_mean": float(np.mean([inf["iters"] for inf in o_infos])),
+                    "steps_full_eig": int(sum(1 for inf in o_infos if inf["side_used"] == 3))}
+    del Pi_fs
 
     # step 0 against the construction closed form
     rel_step0 = None
@@ -311,19 +339,23 @@ def run_sequence(args, torch, psdp):
                          f"FP64 cyclic Jacobi + clip"}
     iters = np.array([inf["iters"] for inf in infos])
     lob = [inf for inf in infos if inf["side_used"] != 3]
+    rp = prec if args.method == "lobpcg" else "fp64"  # the filter's products are FP64
     cert = fams_all.get("cert", {"launches": 0, "ms": 0.0})
     out = {
         "value": ok_steps / wall, "steps": steps, "warmup": warm, "ms_per_step": 1e3 * wall / steps,
-        "dtype": prec,
+        "dtype": rp,
         "config": {"workload": wl, "n": n, "n_pos": p, "block": block, "tol": tol,
                    "bound_rel_target": args.bound_rel if big else None,
-                   "matrices": len(mats), "products": prec, "ortho_rr_refine": "fp64",
+                   "matrices": len(mats), "method": args.method,
+                   "products": prec if args.method == "lobpcg" else "fp64",
+                   "ortho_rr_refine": "fp64",
                    "tail": "certified (FP64 Cholesky certificate)"},
         "value_note": "projections/s counting only steps within 1e-6 of the full eig "
                       "(every timed step is checked)",
         "accuracy_ok": not bad, "steps_over_1e-6": bad,
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
+        "products_mean": float(np.mean([inf["products"] for inf in infos])),
         "status_ok": int(sum(1 for inf in infos if inf["status"] == 0)),
         "steps_block_solver": len(lob),
         "steps_full_eig": int(sum(1 for inf in infos if inf["side_used"] == 3)),
@@ -332,6 +364,7 @@ def run_sequence(args, torch, psdp):
         "full_eig": {"value": fe_rate, "unit": "projections/s", "method": "rocsolver_dsyevd",
                      "samples": steps},
         "speedup_vs_full_eig": (ok_steps / wall) / fe_rate,
+        "other_method": other_method,
         "rel_err_vs_full_eig_max": max(rel_vs_fe),
         "rel_err_step0_vs_closed_form": rel_step0,
         "rel_err_vs_oracle_max": max(rel_oracle.values()) if rel_oracle else None,
@@ -340,7 +373,7 @@ def run_sequence(args, torch, psdp):
         "certificate": {"launch_groups": cert["launches"],
                         "ms_per_projection": cert["ms"] / max(1, kt_steps),
                         "ms_per_certificate": cert["ms"] / max(1, cert["launches"])},
-        "roofline": roofline(fams, prec, wl), "product_roofline": product_roofline(fams_all, prec),
+        "roofline": roofline(fams, rp, wl), "product_roofline": product_roofline(fams_all, rp),
         "cpu_baseline": cpu, "kernels": kernels_table(fams_all),
         "kernels_note": f"every family timed on an untimed pass over the first {kt_steps} "
                         f"timed matrices (after the same warm-up); the timed region times only "
@@ -407,6 +440,22 @@ def run_batched(args, torch, psdp):
     rel_fe = max(float(torch.linalg.norm(res[i].Pi - fe[i]) / max(torch.linalg.norm(fe[i]), 1e-300))
                  for i in idx)
 
+    # the library's own batched exact path (all 512 cones, zero-padded
+    # buckets, one batched rocSOLVER eigendecomposition per bucket): the fair
+    # baseline for one launch over every cone
+    Pfb = [psdp._empty_f(n, n, dev) for n in ns]
+    proj.full_eig_batched(Xs, Pi_outs=Pfb)
+    torch.cuda.synchronize()
+    fb_steps = max(1, min(steps, 5))
+    t = time.perf_counter()
+    for _ in range(fb_steps):
+        proj.full_eig_batched(Xs, Pi_outs=Pfb)
+    torch.cuda.synchronize()
+    fb_rate = 512 * fb_steps / (time.perf_counter() - t)
+    rel_fb = max(float(torch.linalg.norm(res[i].Pi - Pfb[i]) / max(torch.linalg.norm(Pfb[i]), 1e-300))
+                 for i in range(512))
+    del Pfb
+
     cpu, rel_oracle = None, []
     if not args.no_cpu_baseline:
         import oracle
@@ -431,10 +480,14 @@ def run_batched(args, torch, psdp):
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "iters_mean": float(iters.mean()), "iters_max": int(iters.max()),
         "status_ok": int(sum(1 for inf in infos if inf["status"] == 0)),
-        "full_eig": {"value": fe_rate, "unit": "projections/s",
-                     "method": "rocsolver_dsyevd one cone at a time", "samples": len(idx)},
-        "speedup_vs_full_eig": value / fe_rate,
-        "rel_err_vs_full_eig_max": rel_fe,
+        "full_eig": {"value": fb_rate, "unit": "projections/s",
+                     "method": "psdp_full_eig_project_batched (bucketed batched rocSOLVER "
+                               "dsyevd over all 512 cones per call)", "calls": fb_steps},
+        "speedup_vs_full_eig": value / fb_rate,
+        "rel_err_vs_full_eig_max": rel_fb,
+        "full_eig_one_at_a_time": {"value": fe_rate, "unit": "projections/s",
+                                   "method": "rocsolver_dsyevd one cone at a time",
+                                   "samples": len(idx), "rel_err_max": rel_fe},
         "rel_err_vs_oracle_max": max(rel_oracle) if rel_oracle else None,
         "err_bound_rel_max": max(inf["err_bound"] / max(inf["pi_fro"], 1e-300) for inf in infos),
         "roofline": roofline(fams, prec, "batched512"), "cpu_baseline": cpu, "kernels": kernels_table(fams),
@@ -445,105 +498,172 @@ def run_batched(args, torch, psdp):
 
 # -------------------------------------------------------------- serving ---
 def run_serving(args, torch, psdp):
-    """Poisson stream of requests from 64 sessions through the server, then
-    the same stream through the plain path (one projection at a time)."""
-    from workloads import poisson_arrivals, serving_sessions, session_sequence
+    """Open-loop Poisson stream (2000 requests/s) from 64 sessions through
+    the server for args.serve_seconds after a 2 s warm-up.  Each session's
+    requests X_{j+1} = X_j + E_j (||E_j||_F = 1e-3 ||X_j||_F, E symmetric
+    Gaussian) are generated on the device at arrival time (torch's seeded
+    generator) into a ring of 4 request buffers per session; an arrival that
+    finds its session's ring full is rejected (counted).  Then the plain path
+    (one projection at a time, one Session per session) over a closed loop of
+    requests from the same mix."""
+    from workloads import poisson_arrivals, serving_sessions
     rate = 2000.0
-    duration = args.serve_seconds
+    warm_s, duration = 2.0, args.serve_seconds
     prec = args.prec or "fp32"
+    K = 4
     t_gen = time.time()
     specs = serving_sessions(count=64)
-    t_arr, sid = poisson_arrivals(rate, duration, len(specs))
-    gens = [session_sequence(sp, 10 ** 6) for sp in specs]
-    mats = [np.asfortranarray(next(gens[s_])) for s_ in sid]
-    log(f"generated {len(specs)} sessions, {len(mats)} requests in {time.time() - t_gen:.1f}s")
+    t_arr, sid = poisson_arrivals(rate, warm_s + duration, len(specs))
+    log(f"generated {len(specs)} sessions and {len(t_arr)} arrivals in {time.time() - t_gen:.1f}s")
     dev = torch.device("cuda", 0)
-    Xd = [torch.from_numpy(X).to(dev) for X in mats]
-    Pd = [psdp._empty_f(X.shape[0], X.shape[0], dev) for X in mats]
+    Xcur = [torch.from_numpy(np.asfortranarray(sp.cone.X)).to(dev) for sp in specs]
+    for sp in specs:
+        sp.cone = None  # host copies no longer needed
+    Xring = [[psdp._empty_f(X.shape[0], X.shape[0], dev) for _ in range(K)] for X in Xcur]
+    Pring = [[psdp._empty_f(X.shape[0], X.shape[0], dev) for _ in range(K)] for X in Xcur]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(19122767)
     torch.cuda.synchronize()
 
-    def serve(slots, lane):
-        srv = psdp.Server(0, slots=slots, batch_lane=lane, prec=prec)
-        ids = [srv.open_session(sp.n, m_cap=48, pos_hint=-1) for sp in specs]
-        torch.cuda.synchronize()
-        tickets = []
-        t0 = time.perf_counter()
-        for k in range(len(mats)):
-            while time.perf_counter() - t0 < t_arr[k]:
-                pass
-            tickets.append(srv.submit(ids[sid[k]], Xd[k], Pi_out=Pd[k]))
-        res = [srv.wait(t) for t in tickets]
-        wall = time.perf_counter() - t0
-        st = srv.stats()
-        srv.close()
-        return res, st, wall
+    def next_request(s_, slot):
+        X = Xcur[s_]
+        G = torch.randn(X.shape, generator=gen, device=dev, dtype=torch.float64)
+        E = G + G.t()
+        X.add_(E * (1e-3 * torch.linalg.norm(X) / torch.linalg.norm(E)))
+        Xring[s_][slot].copy_(X)
+        return Xring[s_][slot]
 
-    # untimed warm-up pass of the server (library init, solver handles)
-    serve(4, True)
-    res, st, wall = serve(4, True)
-    lat = np.array([r.latency_ms for r in res])
-    n_lane = sum(1 for r in res if r.lane == 1)
-    n_full = sum(1 for r in res if r.info["side_used"] == 3)
-    keep = {k: Pd[k].clone() for k in range(0, len(mats), max(1, len(mats) // 24))}
+    srv = psdp.Server(0, slots=4, batch_lane=True, prec=prec, method=args.method)
+    ids = [srv.open_session(sp.n, m_cap=48, pos_hint=-1) for sp in specs]
+    free = [list(range(K)) for _ in specs]
+    queue = [[] for _ in specs]  # outstanding (ticket, slot, k) per session, FIFO
+    results, rejected_win, arrived_win = [], 0, 0
+    sample_every = max(1, len(t_arr) // 48)
+    samples = {}
 
-    # plain path: one Projector, one Session per session, FIFO in arrival order
-    proj = psdp.Projector(0)
-    sess = [psdp.Session(proj, sp.n, m_cap=48, prec=prec, side="auto", pos_hint=-1,
-                         fallback_full=True) for sp in specs]
-    proj.profile_filter("fulleig")  # every request of this mix takes the exact path
-    proj.profile_enable(True)
-    plain_lat = []
-    torch.cuda.synchronize()
+    def poll_session(s_, block=False):
+        while queue[s_]:
+            tk, slot, k = queue[s_][0]
+            r = srv.wait(tk, -1.0 if block else 0.0)
+            if r is None:
+                break
+            queue[s_].pop(0)
+            free[s_].append(slot)
+            results.append((k, r))
+            if k in samples:
+                samples[k] = (samples[k], Pring[s_][slot].clone())
+
+    def poll(block=False):
+        for s_ in range(len(specs)):
+            poll_session(s_, block)
+
     t0 = time.perf_counter()
-    for k in range(len(mats)):
+    last_poll = 0.0
+    for k in range(len(t_arr)):
+        # completions are collected every 2 ms (each poll asks every session's
+        # oldest ticket) and while waiting for the next arrival
         now = time.perf_counter() - t0
-        if now < t_arr[k]:
-            time.sleep(t_arr[k] - now)
-        sess[sid[k]].project(Xd[k], Pi_out=Pd[k])
-        torch.cuda.synchronize()
-        plain_lat.append(1e3 * (time.perf_counter() - t0 - t_arr[k]))
-    plain_wall = time.perf_counter() - t0
-    fams = {f: proj.profile_get(f) for f in FAMILIES}
-    proj.profile_enable(False)
-    proj.profile_filter("")
-    plain_lat = np.array(plain_lat)
-    rel_fe = max(float(torch.linalg.norm(keep[k] - Pd[k]) / max(torch.linalg.norm(Pd[k]), 1e-300))
-                 for k in keep)
+        if now - last_poll > 2e-3 or now < t_arr[k]:
+            poll()
+            last_poll = time.perf_counter() - t0
+        while time.perf_counter() - t0 < t_arr[k]:
+            pass
+        s_ = int(sid[k])
+        in_win = t_arr[k] >= warm_s
+        arrived_win += in_win
+        if not free[s_]:
+            poll_session(s_)
+        if not free[s_]:
+            rejected_win += in_win
+            continue
+        slot = free[s_].pop()
+        X = next_request(s_, slot)
+        if k % sample_every == 0:
+            samples[k] = X.clone()
+        tk = srv.submit(ids[s_], X, Pi_out=Pring[s_][slot])
+        queue[s_].append((tk, slot, k))
+    t_end_arr = time.perf_counter() - t0
+    poll(block=True)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    win = [(k, r) for k, r in results if t_arr[k] >= warm_s]
+    lat = np.array([r.latency_ms for _, r in win])
+    n_block = sum(1 for _, r in win if r.info["side_used"] != 3 and r.status >= 0)
+    n_lane = sum(1 for _, r in win if r.lane == 1)
+    n_full = sum(1 for _, r in win if r.info["side_used"] == 3)
+    # throughput: requests of the window completed, over the window plus the
+    # drain after the last arrival
+    served_rate = len(win) / max(wall - warm_s, 1e-9)
 
+    # sampled requests against the exact path on the device (and the oracle
+    # for a few small ones)
+    proj = psdp.Projector(0)
+    pairs = [(k, v) for k, v in samples.items() if isinstance(v, tuple)]
+    rel_fe = 0.0
+    for k, (Xs_, Pi_s) in pairs:
+        Pf, _ = proj.full_eig(Xs_)
+        rel_fe = max(rel_fe, float(torch.linalg.norm(Pi_s - Pf) / max(torch.linalg.norm(Pf), 1e-300)))
     cpu, rel_oracle = None, []
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        small = [k for k in keep if mats[k].shape[0] <= 700][:8]
+        small = [(k, v) for k, v in pairs if v[0].shape[0] <= 700][:8]
         t = time.perf_counter()
-        for k in small:
-            Pi_ref, _ = oracle.project(mats[k])
-            rel_oracle.append(oracle.rel_error(keep[k].cpu().numpy(), Pi_ref))
+        for k, (Xs_, Pi_s) in small:
+            Pi_ref, _ = oracle.project(Xs_.cpu().numpy())
+            rel_oracle.append(oracle.rel_error(Pi_s.cpu().numpy(), Pi_ref))
         dt = time.perf_counter() - t
         cpu = {"value": len(small) / max(dt, 1e-9), "unit": "projections/s",
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"{len(small)} served requests with n <= 700, FP64 cyclic Jacobi + clip"}
-    value = st["throughput"]
+
+    # plain path: one projection at a time through a Session per session,
+    # closed loop over requests drawn from the same arrival order
+    sess = [psdp.Session(proj, sp.n, m_cap=48, prec=prec, side="auto", pos_hint=-1,
+                         fallback_full=True, method=args.method) for sp in specs]
+    n_plain = min(len(t_arr), 400)
+    for k in range(min(64, n_plain)):  # warm-up: one request per session touched
+        s_ = int(sid[k])
+        sess[s_].project(next_request(s_, 0), Pi_out=Pring[s_][0])
+    proj.profile_enable(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(n_plain):
+        s_ = int(sid[k])
+        sess[s_].project(next_request(s_, 0), Pi_out=Pring[s_][0])
+    torch.cuda.synchronize()
+    plain_rate = n_plain / (time.perf_counter() - t)
+    fams = {f: proj.profile_get(f) for f in FAMILIES}
+    proj.profile_enable(False)
+    proj.close()
     out = {
-        "value": value, "steps": len(mats), "warmup": 1, "ms_per_step": 1e3 * wall / len(mats),
+        "value": served_rate, "steps": len(win), "warmup": 1, "ms_per_step": 1e3 / served_rate,
         "dtype": prec,
         "config": {"workload": "serving_mix", "sessions": 64, "rate_per_s": rate,
-                   "duration_s": duration, "requests": len(mats), "n_range": [32, 2048],
-                   "slots": 4, "batch_lane": True, "products": prec, "refine": "fp64"},
-        "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                   "warmup_s": warm_s, "duration_s": duration, "n_range": [32, 2048],
+                   "slots": 4, "batch_lane": True, "ring_per_session": K,
+                   "method": args.method, "products": prec, "refine": "fp64"},
+        "value_note": "requests of the measured window completed per second (window plus the "
+                      "drain after its last arrival); requests arriving at a full session ring "
+                      "are rejected",
+        "arrived": int(arrived_win), "rejected": int(rejected_win), "completed": len(win),
+        "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+        "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+        "mean_ms": float(lat.mean()) if lat.size else None,
+        "served_by_block_solver": n_block,
+        "fraction_block_solver": n_block / max(1, len(win)),
         "served_in_lane": n_lane, "served_full_eig": n_full,
         "batched_launches": st["batched_launches"], "max_active": st["max_active"],
-        "hbm_peak_bytes": st["hbm_peak"],
-        "plain_path": {"value": len(mats) / plain_wall, "unit": "projections/s",
-                       "p50_ms": float(np.percentile(plain_lat, 50)),
-                       "p99_ms": float(np.percentile(plain_lat, 99))},
-        "speedup_vs_plain_path": value / (len(mats) / plain_wall),
-        "rel_err_served_vs_plain_max": rel_fe,
+        "hbm_peak_bytes": st["hbm_peak"], "arrivals_end_s": t_end_arr,
+        "plain_path": {"value": plain_rate, "unit": "projections/s", "requests": n_plain,
+                       "mode": "closed loop, one projection at a time"},
+        "speedup_vs_plain_path": served_rate / plain_rate,
+        "rel_err_sampled_vs_full_eig_max": rel_fe, "samples": len(pairs),
         "rel_err_vs_oracle_max": max(rel_oracle) if rel_oracle else None,
         "roofline": roofline(fams, prec, "serving_mix"), "cpu_baseline": cpu,
         "kernels": kernels_table(fams),
     }
-    proj.close()
     return out
 
 
@@ -624,9 +744,12 @@ def main():
     ap.add_argument("--workload", default="n4000_mixed",
                     choices=["n1000_warm_seq", "n4000_mixed", "n4000_mixed_iid", "batched512",
                              "serving_mix", "admm_maxcut800"])
-    ap.add_argument("--serve-seconds", type=float, default=0.25,
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson arrival window (serving_mix)")
     ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--method", default="chebyshev", choices=["chebyshev", "lobpcg"],
+                    help="eigensolver of the sequence workloads (the other one is timed "
+                         "on the same matrices and reported beside)")
     ap.add_argument("--full-eig-samples", type=int, default=None)
     ap.add_argument("--oracle-samples", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -671,7 +794,7 @@ def main():
         "config": body.pop("config"),
     }
     out.update(body)
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=lambda o: o.item() if hasattr(o, "item") else str(o)), flush=True)
 
 
 if __name__ == "__main__":

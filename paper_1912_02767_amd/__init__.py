@@ -459,7 +459,7 @@ class Server:
     def __init__(self, device: int = 0, slots: int = 4, hbm_budget: int = 0,
                  batch_lane: bool = True, small_n: int = 256, max_batch: int = 512,
                  prec="fp32", tol: float = 0.0, max_iter: int = 300, seed=None,
-                 block_guard: int = 4):
+                 block_guard: int = 4, method="lobpcg"):
         self.lib = load()
         torch = _torch()
         if not torch.cuda.is_available():
@@ -473,7 +473,7 @@ class Server:
         cfg.small_n = int(small_n)
         cfg.max_batch = int(max_batch)
         cfg.opt = _opts(self.lib, "auto", prec, tol, max_iter, True, True, seed,
-                        block_guard=block_guard)
+                        block_guard=block_guard, method=method)
         self._s = ctypes.c_void_p()
         rc = self.lib.psdp_server_create(ctypes.byref(self._s), self.device, ctypes.byref(cfg))
         if rc != 0:
