@@ -49,65 +49,114 @@ __device__ inline double bcast_lane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
-// Right-looking Cholesky of the lower triangle of the 64 x 64 tile held
-// row-major (stride 65) in LDS, by the first wave of the workgroup: lane i
-// keeps row i in registers; at column j the pivot comes from lane j by
-// readlane, every lane forms 1 / sqrt(pivot) itself, writes its l_ij to an
+// Right-looking Cholesky of the 32 x 32 diagonal block at (o, o) of the
+// 64 x 64 tile held row-major (stride 65) in LDS, by the first wave: lane i
+// < 32 keeps row o + i in registers; at column j the pivot comes from lane j
+// by readlane, every lane forms 1 / sqrt(pivot) itself, writes its l_ij to an
 // LDS column buffer and updates its row with the broadcast l_cj, c > j (the
 // entries right of its diagonal take junk updates that are never read).
-// Called by every thread of the workgroup (the other waves wait at the
-// closing barrier).  Returns false, on every thread, when a pivot is not
-// positive and finite; on success the lower triangle holds the factor.
-__device__ __attribute__((always_inline)) inline bool chol_tile_lds(double* a, double* cb, int* flag) {
-  if (threadIdx.x < kT) {
-    const int lane = threadIdx.x;
-    double r[kT];
+// Returns 0 when a pivot is not positive and finite (the same on every lane).
+__device__ __attribute__((always_inline)) inline int chol32_wave(double* a, double* cb, int o) {
+  const int lane = threadIdx.x;
+  const bool act = lane < 32;
+  double r[32];
 #pragma unroll
-    for (int c = 0; c < kT; ++c) r[c] = a[lane * kLd + c];
-    int ok = 1;
+  for (int c = 0; c < 32; ++c) r[c] = act ? a[(o + lane) * kLd + o + c] : 0.0;
+  int ok = 1;
 #pragma unroll
-    for (int j = 0; j < kT; ++j) {
-      const double d = bcast_lane(r[j], j);
-      if (!(d > 0.0) || !(d < INFINITY)) {  // the same value on every lane
-        ok = 0;
-        break;
-      }
-      const double inv = rsqrt_nr(d);
-      const double l = r[j] * inv;
-      r[j] = (lane == j) ? d * inv : l;
-      double* b = cb + (j & 1) * kT;
-      b[lane] = l;
+  for (int j = 0; j < 32; ++j) {
+    const double d = bcast_lane(r[j], j);
+    if (!(d > 0.0) || !(d < INFINITY)) {  // the same value on every lane
+      ok = 0;
+      break;
+    }
+    const double inv = rsqrt_nr(d);
+    const double l = r[j] * inv;
+    r[j] = (lane == j) ? d * inv : l;
+    double* b = cb + (j & 1) * kT;
+    b[lane] = l;
+    // every read of the column issued before the first update uses one
+    double w[32];
 #pragma unroll
-      for (int c0 = (j + 1) & ~1; c0 < kT; c0 += 2) {
-        const double2 w = *(const double2*)(b + c0);
-        if (c0 > j) r[c0] = fma(-l, w.x, r[c0]);
-        r[c0 + 1] = fma(-l, w.y, r[c0 + 1]);
-      }
+    for (int c0 = (j + 1) & ~1; c0 < 32; c0 += 2) {
+      const double2 v = *(const double2*)(b + c0);
+      w[c0] = v.x;
+      w[c0 + 1] = v.y;
     }
 #pragma unroll
-    for (int c = 0; c < kT; ++c) a[lane * kLd + c] = r[c];
-    if (lane == 0) *flag = ok;
+    for (int c = j + 1; c < 32; ++c) r[c] = fma(-l, w[c], r[c]);
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 32; ++c) a[(o + lane) * kLd + o + c] = r[c];
+  }
+  return ok;
+}
+
+// Cholesky of the lower triangle of the 64 x 64 tile in LDS, blocked 2 x 2 on
+// 32-column halves: L11 (first wave), L21 = A21 L11^{-T} by column-ordered
+// substitution (eight lanes per row, lane g owning columns 4g .. 4g + 3, the
+// quotient x_c = a_c / l_cc by the rounded reciprocal shuffled to the row's
+// lanes), A22 -= L21 L21^T, then L22 (first wave).  Every entry is the
+// standard algorithm's inner product in some order.  Called by every thread
+// of the workgroup; returns false, on every thread, when a pivot is not
+// positive and finite; on success the lower triangle holds the factor.
+__device__ __attribute__((always_inline)) inline bool chol_tile_lds(double* a, double* cb, int* flag) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int ok = chol32_wave(a, cb, 0);
+    if (t == 0) *flag = ok;
+  }
+  __syncthreads();
+  if (!*flag) return false;
+  double* rinv = cb;  // the column buffers are free again
+  if (t < 32) rinv[t] = 1.0 / a[t * kLd + t];
+  __syncthreads();
+  {
+    const int row = 32 + (t >> 3), g = t & 7, base = t & 56;
+    double x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) x[q] = a[row * kLd + 4 * g + q];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      const int own = c >> 2, qq = c & 3;
+      const double v = __shfl(x[qq] * rinv[c], base | own, 64);
+      x[qq] = (g == own) ? v : x[qq];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = 4 * g + q;
+        const double w = (col > c) ? a[col * kLd + c] : 0.0;
+        x[q] = fma(-v, w, x[q]);
+      }
+    }
+    __syncthreads();  // every row of A21 read before L21 overwrites it
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[row * kLd + 4 * g + q] = x[q];
+  }
+  __syncthreads();
+  {
+    // A22 -= L21 L21^T: thread -> row 32 + t / 8, columns 32 + 4 (t % 8) + q
+    const int i = 32 + (t >> 3), j0 = 32 + 4 * (t & 7);
+    double acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = a[i * kLd + j0 + q];
+#pragma unroll 8
+    for (int c = 0; c < 32; ++c) {
+      const double li = a[i * kLd + c];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(-li, a[(j0 + q) * kLd + c], acc[q]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[i * kLd + j0 + q] = acc[q];
+  }
+  __syncthreads();
+  if (t < 64) {
+    const int ok = chol32_wave(a, cb, 32);
+    if (t == 0) *flag = ok;
   }
   __syncthreads();
   return *flag != 0;
-}
-
-// v from the lane (lane & ~3) | K of this lane's quad (DPP quad permute)
-template <int K>
-__device__ inline double quad_bcast(double v) {
-  constexpr int ctrl = K | (K << 2) | (K << 4) | (K << 6);
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ inline double quad_bcast_k(double v, int k) {
-  switch (k) {
-    case 0: return quad_bcast<0>(v);
-    case 1: return quad_bcast<1>(v);
-    case 2: return quad_bcast<2>(v);
-    default: return quad_bcast<3>(v);
-  }
 }
 
 // tile (row block bi, column block bj) of column-major M <-> row-major LDS
@@ -368,41 +417,20 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int L
   }
 }
 
-// Columns 16 O .. 16 O + 15 of the row solve in k_chol_trsm (their owner is
-// lane O of each quad).  The staged factor is zero on and above its
-// diagonal, so every lane applies every update unconditionally.
-template <int O>
-__device__ inline void trsm_quarter(double (&x)[16], const double* lt, const double* rinv, int g) {
-#pragma unroll
-  for (int cc = 0; cc < 16; ++cc) {
-    const int c = 16 * O + cc;
-    const double2* lc = (const double2*)(lt + c * kT + 16 * g);
-    double2 w[8];
-#pragma unroll
-    for (int s2 = 0; s2 < 8; ++s2) w[s2] = lc[s2];
-    const double v = quad_bcast<O>(x[cc] * rinv[c]);
-    x[cc] = (g == O) ? v : x[cc];
-#pragma unroll
-    for (int s2 = 0; s2 < 8; ++s2) {
-      x[2 * s2] = fma(-v, w[s2].x, x[2 * s2]);
-      x[2 * s2 + 1] = fma(-v, w[s2].y, x[2 * s2 + 1]);
-    }
-  }
-}
-
-// L_ik = A_ik L_kk^{-T} for the row blocks i > k: row r of the block is
-// solved by the four lanes 4r .. 4r + 3 of a quad (lane g owns the columns
-// 16 g .. 16 g + 15) in column order: x_c = a_c / l_cc by the rounded
-// reciprocal, broadcast in the quad by DPP, then a_q -= x_c l_qc for q > c.
-// L_kk is held transposed in LDS so a lane's 16 values of column c are
-// contiguous.
+// L_ik = A_ik L_kk^{-T} for the row blocks i > k, sixteen rows per
+// workgroup: the sixteen lanes of a row each own four of its columns (lane g
+// of the row: columns 4g .. 4g + 3).  At column c the owning lane forms
+// x_c = a_c / l_cc by the rounded reciprocal, the row's lanes receive it by a
+// shuffle and update their columns q > c with l_qc, read from L_kk staged
+// transposed in LDS and zero on and above its diagonal (so every lane
+// applies every update unconditionally).  The arithmetic is the column-
+// ordered substitution of the standard algorithm.
 __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int L, int k,
                                                    CertState* cs) {
   if (cert_failed(cs)) return;
   __shared__ __align__(16) double lt[kT * kT];  // lt[c * 64 + q] = L_kk(q, c), q > c
   __shared__ double rinv[kT];
   const int t = threadIdx.x;
-  const int bi = k + 1 + blockIdx.x;
   {
     const double* src = M + (size_t)(k * kT) + (size_t)(k * kT) * L;
 #pragma unroll 4
@@ -410,22 +438,31 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int L
       const int e = t + 256 * u, q = e & 63, c = e >> 6;
       const double v = src[q + (size_t)c * L];
       if (q == c) rinv[c] = 1.0 / v;
-      // only q > c updates: the diagonal and the upper triangle are zero here
       lt[c * kT + q] = (q > c) ? v : 0.0;
     }
   }
   __syncthreads();
-  const int r = t >> 2, g = t & 3;
-  double* rowp = M + (size_t)(bi * kT + r) + (size_t)(k * kT + 16 * g) * L;
-  double x[16];
+  const int g = t & 15;
+  const int row = (k + 1) * kT + blockIdx.x * 16 + (t >> 4);
+  const int base = t & 48;  // first lane of this row's sixteen in the wavefront
+  double* rowp = M + (size_t)row + (size_t)(k * kT + 4 * g) * L;
+  double x[4];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) x[s] = rowp[(size_t)s * L];
-  trsm_quarter<0>(x, lt, rinv, g);
-  trsm_quarter<1>(x, lt, rinv, g);
-  trsm_quarter<2>(x, lt, rinv, g);
-  trsm_quarter<3>(x, lt, rinv, g);
+  for (int q = 0; q < 4; ++q) x[q] = rowp[(size_t)q * L];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) rowp[(size_t)s * L] = x[s];
+  for (int c = 0; c < kT; ++c) {
+    const int own = c >> 2, qq = c & 3;
+    const double v = __shfl(x[qq] * rinv[c], base | own, 64);
+    x[qq] = (g == own) ? v : x[qq];
+    const double2 w0 = *(const double2*)(lt + c * kT + 4 * g);
+    const double2 w1 = *(const double2*)(lt + c * kT + 4 * g + 2);
+    x[0] = fma(-v, w0.x, x[0]);
+    x[1] = fma(-v, w0.y, x[1]);
+    x[2] = fma(-v, w1.x, x[2]);
+    x[3] = fma(-v, w1.y, x[3]);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) rowp[(size_t)q * L] = x[q];
 }
 
 // Trailing update A_ij -= L_ik L_jk^T for k < j <= i; workgroup 0 takes the
@@ -523,7 +560,7 @@ hipError_t launch_cert_chol(double* M, int L, CertState* cs, hipStream_t st) {
   hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, M, L, 0, cs);
   for (int k = 0; k + 1 < T; ++k) {
     const int R = T - k - 1;
-    hipLaunchKernelGGL(k_chol_trsm, dim3(R), dim3(256), 0, st, M, L, k, cs);
+    hipLaunchKernelGGL(k_chol_trsm, dim3(4 * R), dim3(256), 0, st, M, L, k, cs);
     hipLaunchKernelGGL(k_chol_syrk, dim3(R * (R + 1) / 2), dim3(256), 0, st, M, L, k, cs);
   }
   return hipGetLastError();
