@@ -49,6 +49,36 @@ __device__ inline double bcast_lane(double v, int src) {
   return __hiloint2double(hi, lo);
 }
 
+// v of lane N of this lane's sixteen-lane row (DPP row broadcast)
+template <int N>
+__device__ inline double row_bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + N, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + N, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// row_bcast with the lane given at run time (a constant once unrolled)
+__device__ inline double row_bcast_n(double v, int n) {
+  switch (n) {
+    case 0: return row_bcast<0>(v);
+    case 1: return row_bcast<1>(v);
+    case 2: return row_bcast<2>(v);
+    case 3: return row_bcast<3>(v);
+    case 4: return row_bcast<4>(v);
+    case 5: return row_bcast<5>(v);
+    case 6: return row_bcast<6>(v);
+    case 7: return row_bcast<7>(v);
+    case 8: return row_bcast<8>(v);
+    case 9: return row_bcast<9>(v);
+    case 10: return row_bcast<10>(v);
+    case 11: return row_bcast<11>(v);
+    case 12: return row_bcast<12>(v);
+    case 13: return row_bcast<13>(v);
+    case 14: return row_bcast<14>(v);
+    default: return row_bcast<15>(v);
+  }
+}
+
 // Right-looking Cholesky of the 32 x 32 diagonal block at (o, o) of the
 // 64 x 64 tile held row-major (stride 65) in LDS, by the first wave: lane i
 // < 32 keeps row o + i in registers; at column j the pivot comes from lane j
@@ -62,20 +92,21 @@ __device__ __attribute__((always_inline)) inline int chol32_wave(double* a, doub
   double r[32];
 #pragma unroll
   for (int c = 0; c < 32; ++c) r[c] = act ? a[(o + lane) * kLd + o + c] : 0.0;
+  // No branch per column: a failed pivot clears `ok` (the same on every
+  // lane) and is replaced by 1 so the remaining arithmetic stays finite;
+  // the next column's update comes first so that the next pivot's broadcast
+  // and reciprocal square root overlap the rest of this column's updates.
   int ok = 1;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
-    const double d = bcast_lane(r[j], j);
-    if (!(d > 0.0) || !(d < INFINITY)) {  // the same value on every lane
-      ok = 0;
-      break;
-    }
+    double d = bcast_lane(r[j], j);
+    ok &= (d > 0.0 && d < INFINITY) ? 1 : 0;
+    d = ok ? d : 1.0;
     const double inv = rsqrt_nr(d);
     const double l = r[j] * inv;
     r[j] = (lane == j) ? d * inv : l;
     double* b = cb + (j & 1) * kT;
     b[lane] = l;
-    // every read of the column issued before the first update uses one
     double w[32];
 #pragma unroll
     for (int c0 = (j + 1) & ~1; c0 < 32; c0 += 2) {
@@ -83,8 +114,9 @@ __device__ __attribute__((always_inline)) inline int chol32_wave(double* a, doub
       w[c0] = v.x;
       w[c0 + 1] = v.y;
     }
+    if (j + 1 < 32) r[j + 1] = fma(-l, w[j + 1], r[j + 1]);
 #pragma unroll
-    for (int c = j + 1; c < 32; ++c) r[c] = fma(-l, w[c], r[c]);
+    for (int c = j + 2; c < 32; ++c) r[c] = fma(-l, w[c], r[c]);
   }
   if (act) {
 #pragma unroll
@@ -96,8 +128,8 @@ __device__ __attribute__((always_inline)) inline int chol32_wave(double* a, doub
 // Cholesky of the lower triangle of the 64 x 64 tile in LDS, blocked 2 x 2 on
 // 32-column halves: L11 (first wave), L21 = A21 L11^{-T} by column-ordered
 // substitution (eight lanes per row, lane g owning columns 4g .. 4g + 3, the
-// quotient x_c = a_c / l_cc by the rounded reciprocal shuffled to the row's
-// lanes), A22 -= L21 L21^T, then L22 (first wave).  Every entry is the
+// quotient x_c = a_c / l_cc by the rounded reciprocal broadcast to the row's
+// lanes by DPP), A22 -= L21 L21^T, then L22 (first wave).  Every entry is the
 // standard algorithm's inner product in some order.  Called by every thread
 // of the workgroup; returns false, on every thread, when a pivot is not
 // positive and finite; on success the lower triangle holds the factor.
@@ -109,18 +141,21 @@ __device__ __attribute__((always_inline)) inline bool chol_tile_lds(double* a, d
   }
   __syncthreads();
   if (!*flag) return false;
-  double* rinv = cb;  // the column buffers are free again
-  if (t < 32) rinv[t] = 1.0 / a[t * kLd + t];
-  __syncthreads();
   {
-    const int row = 32 + (t >> 3), g = t & 7, base = t & 56;
-    double x[4];
+    // eight lanes per row, two rows per sixteen-lane DPP row
+    const int row = 32 + (t >> 3), g = t & 7, hi8 = t & 8;
+    double x[4], rv[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = a[row * kLd + 4 * g + q];
+    for (int q = 0; q < 4; ++q) {
+      x[q] = a[row * kLd + 4 * g + q];
+      rv[q] = 1.0 / a[(4 * g + q) * kLd + 4 * g + q];
+    }
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
       const int own = c >> 2, qq = c & 3;
-      const double v = __shfl(x[qq] * rinv[c], base | own, 64);
+      const double p = x[qq] * rv[qq];  // meaningful on the owning lane
+      const double v0 = row_bcast_n(p, own), v1 = row_bcast_n(p, 8 + own);
+      const double v = hi8 ? v1 : v0;
       x[qq] = (g == own) ? v : x[qq];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -421,7 +456,7 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int L
 // workgroup: the sixteen lanes of a row each own four of its columns (lane g
 // of the row: columns 4g .. 4g + 3).  At column c the owning lane forms
 // x_c = a_c / l_cc by the rounded reciprocal, the row's lanes receive it by a
-// shuffle and update their columns q > c with l_qc, read from L_kk staged
+// DPP row broadcast and update their columns q > c with l_qc, read from L_kk staged
 // transposed in LDS and zero on and above its diagonal (so every lane
 // applies every update unconditionally).  The arithmetic is the column-
 // ordered substitution of the standard algorithm.
@@ -442,17 +477,19 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int L
     }
   }
   __syncthreads();
-  const int g = t & 15;
+  const int g = t & 15;  // this lane's place in its sixteen-lane DPP row
   const int row = (k + 1) * kT + blockIdx.x * 16 + (t >> 4);
-  const int base = t & 48;  // first lane of this row's sixteen in the wavefront
   double* rowp = M + (size_t)row + (size_t)(k * kT + 4 * g) * L;
-  double x[4];
+  double x[4], rv[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) x[q] = rowp[(size_t)q * L];
+  for (int q = 0; q < 4; ++q) {
+    x[q] = rowp[(size_t)q * L];
+    rv[q] = rinv[4 * g + q];
+  }
 #pragma unroll
   for (int c = 0; c < kT; ++c) {
     const int own = c >> 2, qq = c & 3;
-    const double v = __shfl(x[qq] * rinv[c], base | own, 64);
+    const double v = row_bcast_n(x[qq] * rv[qq], own);
     x[qq] = (g == own) ? v : x[qq];
     const double2 w0 = *(const double2*)(lt + c * kT + 4 * g);
     const double2 w1 = *(const double2*)(lt + c * kT + 4 * g + 2);
