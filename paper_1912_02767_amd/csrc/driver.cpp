@@ -1595,8 +1595,12 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       // filter degree: enough to bring the largest positive residual below
       // tol (with a factor 4 in hand) at the smallest positive Ritz value's
       // amplification, at most dmax, and with the amplification of the top
-      // of the spectrum at most 1e5 times that of the smallest positive
-      // value (so the filtered columns stay numerically independent)
+      // of the spectrum at most R times that of the smallest positive value,
+      // so that the filtered columns stay numerically independent: a column
+      // with residual r has components of at most r / (theta_0 - theta_m)
+      // along the top eigenvectors, which the filter multiplies by R
+      // relative to its own, so R = 1e4 (theta_0 - theta_m) / max r, kept
+      // within [1e5, 1e10] (rounding of the products bounds it above)
       const double b = st.theta[m - 1];
       const double a = std::min(cheb_lo, b - 1e-3 * std::max(std::fabs(b), 1e-300));
       const double c = 0.5 * (a + b), e = 0.5 * (b - a);
@@ -1612,7 +1616,10 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       const double ap = std::acosh(xp);
       int d = (int)std::ceil(std::acosh(need) / ap);
       const double spread = std::acosh(xmax) - ap;
-      if (spread > 0) d = std::min(d, (int)(std::log(1e5) / spread));
+      double rall = 0.0;
+      for (int i = 0; i < m; ++i) rall = std::max(rall, st.rnorm[i]);
+      const double R = std::min(1e10, std::max(1e5, 1e4 * (st.theta[0] - b) / std::max(rall, 1e-300)));
+      if (spread > 0) d = std::min(d, (int)(std::log(R) / spread));
       d = std::max(2, std::min(d, dmax));
       // Y0 = X, Y1 = (AX - c X) / e (AX exact from the last Rayleigh-Ritz),
       // Y_{k+1} = 2 (A Y_k - c Y_k) / e - Y_{k-1} through the product epilogue
