@@ -157,8 +157,10 @@ typedef enum {
                                   /* block's smallest Ritz value), each followed */
                                   /* by Rayleigh-Ritz on span(X) with an FP64    */
                                   /* product, until the same stopping rule as    */
-                                  /* LOBPCG holds; products in FP64; the same    */
-                                  /* bound and certificate; info.iters = passes  */
+                                  /* LOBPCG holds and the certificate succeeds   */
+                                  /* (at most min(max_iter, 40) passes and three */
+                                  /* failed certificates); products in FP64; the */
+                                  /* same bound; info.iters = passes             */
 } psdp_method;
 
 typedef struct {

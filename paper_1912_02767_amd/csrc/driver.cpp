@@ -1551,7 +1551,12 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     cheb_lo -= 1e-2 * std::fabs(cheb_lo);  // margin for the rounding of the bound
     cheb_products += 10;
     const int dmax = opt.method_param > 0 ? std::min(opt.method_param, 64) : 24;
-    const int max_pass = std::max(1, std::min(opt.max_iter, 200));
+    // a pass applies a whole polynomial: max_iter passes, at most 40; and
+    // after three certificates failed on blocks that met the stopping rule
+    // the positive eigenvalues outside the block are taken as out of reach
+    // (eigenvalues clustered at zero): not converged
+    const int max_pass = std::max(1, std::min(opt.max_iter, 40));
+    int cert_fail = 0;
     const int L = w.L;
     for (;;) {
       rc = sv.evaluate();
@@ -1573,6 +1578,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
         if (rc != PSDP_OK) { info->status = rc; return rc; }
         if (pre_cert) { converged = true; break; }
         pre_cert = -1;  // a positive eigenvalue outside the block: filter on
+        if (++cert_fail >= 3) break;
       }
       if (expand) {
         // no non-positive Ritz pair left in the block: append columns

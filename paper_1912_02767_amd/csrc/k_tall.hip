@@ -502,7 +502,8 @@ hipError_t launch_copy_cols(const double* src, int lds, double* dst, int ldd, in
 // (paper §1 eq. `projection`; the negative side adds X by the Moreau
 // identity).  base = 0 (positive side) or sym(X) read from the FP64 copy
 // (negative side; A64 holds -sym(X) there, so base = -A64).  Each
-// workgroup writes one 64 x 64 tile of Pi, both triangles.
+// workgroup computes one 64 x 64 tile (i, j), i >= j, of the lower triangle
+// and writes it and its transpose: the result is symmetric by construction.
 constexpr int kRB = 64;
 __global__ __launch_bounds__(256) void k_rebuild(const double* __restrict__ V, int ldv,
                                                  const double* __restrict__ lt, int mt, int n,
@@ -511,7 +512,12 @@ __global__ __launch_bounds__(256) void k_rebuild(const double* __restrict__ V, i
                                                  int ldpi) {
   __shared__ double sa[16][kRB + 1];
   __shared__ double sb[16][kRB + 1];
-  const int i0 = blockIdx.x * kRB, j0 = blockIdx.y * kRB;
+  // lower-triangular tile index -> (ti, tj), ti >= tj
+  int ti = (int)((sqrt(8.0 * blockIdx.x + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= (int)blockIdx.x) ++ti;
+  while (ti * (ti + 1) / 2 > (int)blockIdx.x) --ti;
+  const int tj = (int)blockIdx.x - ti * (ti + 1) / 2;
+  const int i0 = ti * kRB, j0 = tj * kRB;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
   double acc[4][4];
 #pragma unroll
@@ -551,6 +557,11 @@ __global__ __launch_bounds__(256) void k_rebuild(const double* __restrict__ V, i
         double v = acc[a][c];
         if (base) v += base_sign * base[i + (size_t)j * ldb];
         Pi[i + (size_t)j * ldpi] = v;
+        if (ti != tj) {
+          double u = acc[a][c];
+          if (base) u += base_sign * base[j + (size_t)i * ldb];
+          Pi[j + (size_t)i * ldpi] = u;
+        }
       }
     }
 }
@@ -627,7 +638,8 @@ hipError_t launch_update(const double* S, const double* AS, int lds, const doubl
 hipError_t launch_rebuild(const double* V, int ldv, const double* lt, int mt, int n,
                           const double* base, int ldb, double base_sign, double* Pi, int ldpi,
                           hipStream_t st) {
-  dim3 grid((n + kRB - 1) / kRB, (n + kRB - 1) / kRB);
+  const int T = (n + kRB - 1) / kRB;
+  dim3 grid((unsigned)(T * (T + 1) / 2));
   hipLaunchKernelGGL(k_rebuild, grid, dim3(256), 0, st, V, ldv, lt, mt, n, base, ldb, base_sign,
                      Pi, ldpi);
   return hipGetLastError();
