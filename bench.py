@@ -71,12 +71,11 @@ KERNEL_TABLE_STEPS = 10   # untimed steps that time every family
 # when the sources have changed since, the figure no longer describes the
 # kernel and is reported as null.
 TRAFFIC = {
-    ("n1000_warm_seq", "rr"): {
-        "bytes": 110.0e3,
-        "files": ["paper_1912_02767_amd/csrc/rr_fast.h", "paper_1912_02767_amd/csrc/rr_body.h",
-                  "paper_1912_02767_amd/csrc/k_rr_tri.hip", "paper_1912_02767_amd/csrc/common.h"],
-        "sha256": "229773ac0459cb4650254c02fbf64280cfb5174a955ea979d9ac9e36a6250188",
-        "profile": "profiles/hbm_traffic_n1000_warm_seq.txt",
+    ("n4000_mixed_iid", "product"): {
+        "bytes": 178.58e6,  # k_product_mfma<0, 3> 161975.4 KB + k_product_reduce 16601.0 KB
+        "files": ["paper_1912_02767_amd/csrc/k_product.hip", "paper_1912_02767_amd/csrc/common.h"],
+        "sha256": "46ef570f9b95da0c231393ec1d4b7d39ee0debfed29160660860c324eed1c130",
+        "profile": "profiles/hbm_traffic_n4000_mixed_iid.txt",
     },
 }
 
