@@ -53,8 +53,16 @@ def test_kernel_table_keeps_families_only(bench):
 def test_traffic_pin_follows_sources(bench):
     # the stored figure is reported only while the kernel sources hash to the
     # value recorded with it
-    t = bench.TRAFFIC[("n1000_warm_seq", "rr")]
-    assert bench.measured_traffic("n1000_warm_seq", "rr") in (None, t["bytes"])
-    assert bench.measured_traffic("no_such_workload", "rr") is None
+    t = bench.TRAFFIC[("n4000_mixed_iid", "product")]
+    assert bench.measured_traffic("n4000_mixed_iid", "product") in (None, t["bytes"])
+    assert bench.measured_traffic("no_such_workload", "product") is None
+    assert os.path.exists(os.path.join(ROOT, t["profile"]))
     for f in t["files"]:
         assert os.path.exists(os.path.join(ROOT, f)), f
+
+
+def test_rebuild_roofline_bound_follows_intensity(bench):
+    # a rebuild from hundreds of pairs is compute-bound, from a few HBM-bound
+    big = bench.roofline({"rebuild": _fam(1, 0.3, 4000.0 ** 2 * 370, 8 * 4000.0 ** 2)}, "fp64")
+    small = bench.roofline({"rebuild": _fam(1, 0.05, 4000.0 ** 2 * 40, 8 * 4000.0 ** 2)}, "fp64")
+    assert big["bound"] == "alu" and small["bound"] == "hbm"
