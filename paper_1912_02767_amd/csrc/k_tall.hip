@@ -503,67 +503,85 @@ hipError_t launch_copy_cols(const double* src, int lds, double* dst, int ldd, in
 // identity).  base = 0 (positive side) or sym(X) read from the FP64 copy
 // (negative side; A64 holds -sym(X) there, so base = -A64).  Each
 // workgroup computes one 64 x 64 tile (i, j), i >= j, of the lower triangle
-// and writes it and its transpose: the result is symmetric by construction.
+// on the matrix cores (v_mfma_f64_16x16x4f64: wave w takes rows 16w .. 16w +
+// 15 of the tile, four 16 x 16 column tiles), K = the pairs in chunks of 16
+// staged in LDS (V diag(lt) for the rows, V for the columns), and writes it
+// and its transpose through an LDS copy of the tile so that both stores are
+// coalesced: the result is symmetric by construction.
 constexpr int kRB = 64;
+constexpr int kRK = 16;       // pairs per LDS chunk
+constexpr int kRLd = kRB + 1;  // padded LDS row
+typedef double rb_d4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_rebuild(const double* __restrict__ V, int ldv,
                                                  const double* __restrict__ lt, int mt, int n,
                                                  const double* __restrict__ base, int ldb,
                                                  double base_sign, double* __restrict__ Pi,
                                                  int ldpi) {
-  __shared__ double sa[16][kRB + 1];
-  __shared__ double sb[16][kRB + 1];
+  __shared__ double sa[kRK * kRLd];  // sa[k * 65 + r] = V(i0 + r, k) lt[k]
+  __shared__ double sb[kRK * kRLd];  // sb[k * 65 + c] = V(j0 + c, k)
+  __shared__ double tile[kRB * kRLd];
   // lower-triangular tile index -> (ti, tj), ti >= tj
   int ti = (int)((sqrt(8.0 * blockIdx.x + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= (int)blockIdx.x) ++ti;
   while (ti * (ti + 1) / 2 > (int)blockIdx.x) --ti;
   const int tj = (int)blockIdx.x - ti * (ti + 1) / 2;
   const int i0 = ti * kRB, j0 = tj * kRB;
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  double acc[4][4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, li = lane & 15, g = lane >> 4;
+  rb_d4 acc[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int c = 0; c < 4; ++c) acc[c] = rb_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < mt; k0 += kRK) {
+    // 2 x 16 x 64 values, four per thread per side; rows past n and pairs
+    // past mt are zero
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-  for (int k0 = 0; k0 < mt; k0 += 16) {
-    for (int e = threadIdx.x; e < 16 * kRB; e += 256) {
-      int r = e % kRB, kc = e / kRB;
-      int k = k0 + kc;
-      double w = (k < mt) ? lt[k] : 0.0;
-      int ia = i0 + r, ja = j0 + r;
-      sa[kc][r] = (k < mt && ia < n) ? V[ia + (size_t)k * ldv] * w : 0.0;
-      sb[kc][r] = (k < mt && ja < n) ? V[ja + (size_t)k * ldv] : 0.0;
+    for (int u = 0; u < kRK * kRB / 256; ++u) {
+      const int e = t + 256 * u, r = e & 63, kk = e >> 6, k = k0 + kk;
+      const bool kin = k < mt;
+      const double w = kin ? lt[k] : 0.0;
+      sa[kk * kRLd + r] = (kin && i0 + r < n) ? V[(i0 + r) + (size_t)k * ldv] * w : 0.0;
+      sb[kk * kRLd + r] = (kin && j0 + r < n) ? V[(j0 + r) + (size_t)k * ldv] : 0.0;
     }
     __syncthreads();
 #pragma unroll
-    for (int kc = 0; kc < 16; ++kc) {
-      double av[4], bv[4];
+    for (int ks = 0; ks < kRK; ks += 4) {
+      const double a = sa[(ks + g) * kRLd + 16 * wv + li];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sa[kc][ty + 16 * a];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bv[c] = sb[kc][tx + 16 * c];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = fma(av[a], bv[c], acc[a][c]);
+      for (int c = 0; c < 4; ++c) {
+        const double b = sb[(ks + g) * kRLd + 16 * c + li];
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
+  // D[row][col] of column tile c: lane -> col 16 c + li, rows g + 4 r
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int c = 0; c < 4; ++c)
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      int i = i0 + ty + 16 * a, j = j0 + tx + 16 * c;
+    for (int r = 0; r < 4; ++r) tile[(16 * wv + g + 4 * r) * kRLd + 16 * c + li] = acc[c][r];
+  __syncthreads();
+  // Pi(i0 + r, j0 + c) for consecutive r, then the transpose Pi(j0 + r, i0 + c)
+#pragma unroll 4
+  for (int u = 0; u < kRB * kRB / 256; ++u) {
+    const int e = t + 256 * u, r = e & 63, c = e >> 6;
+    const int i = i0 + r, j = j0 + c;
+    if (i < n && j < n) {
+      double v = tile[r * kRLd + c];
+      if (base) v += base_sign * base[i + (size_t)j * ldb];
+      Pi[i + (size_t)j * ldpi] = v;
+    }
+  }
+  if (ti != tj) {
+#pragma unroll 4
+    for (int u = 0; u < kRB * kRB / 256; ++u) {
+      const int e = t + 256 * u, r = e & 63, c = e >> 6;
+      const int i = j0 + r, j = i0 + c;  // element (i, j) of Pi = tile(c, r)
       if (i < n && j < n) {
-        double v = acc[a][c];
+        double v = tile[c * kRLd + r];
         if (base) v += base_sign * base[i + (size_t)j * ldb];
         Pi[i + (size_t)j * ldpi] = v;
-        if (ti != tj) {
-          double u = acc[a][c];
-          if (base) u += base_sign * base[j + (size_t)i * ldb];
-          Pi[j + (size_t)i * ldpi] = u;
-        }
       }
     }
+  }
 }
 
 }  // namespace psdp

@@ -450,3 +450,20 @@ def test_chebyshev_zero_cluster_is_honest(proj):
         if np.isfinite(r.info["err_bound"]):
             assert r.info["err_bound"] * (1 + 1e-6) + 1e-9 >= err
         V, k = r.V, r.info["m_out"]
+
+
+def test_method_arguments_validated(proj):
+    """An unknown method or a negative method_param is rejected before any
+    launch; LOBPCG reports no Chebyshev figures."""
+    from gpu_util import to_dev
+    c = random_spectrum_matrix(64, 4, rng_for(50, 1))
+    X = to_dev(c.X)
+    for kw in ({"method": 4}, {"method": "chebyshev", "method_param": -1}):
+        r = proj.project(X, m_cap=16, side="pos", raise_on_error=False, **kw)
+        assert r.status == -1, (kw, r.info)
+    r = proj.project(X, m_cap=16, side="pos", raise_on_error=False)
+    assert r.status == 0 and r.info["products"] == 0 and np.isnan(r.info["spec_lower"])
+    r = proj.project(X, m_cap=16, side="pos", method="chebyshev", method_param=6,
+                     raise_on_error=False)
+    assert r.status == 0 and r.info["products"] > 0
+    _check(r, c.X)
