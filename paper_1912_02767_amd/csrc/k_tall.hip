@@ -530,18 +530,31 @@ __global__ __launch_bounds__(256) void k_rebuild(const double* __restrict__ V, i
   rb_d4 acc[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) acc[c] = rb_d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < mt; k0 += kRK) {
-    // 2 x 16 x 64 values, four per thread per side; rows past n and pairs
-    // past mt are zero
+  // 2 x 16 x 64 values per chunk, four per thread per side, fetched into
+  // registers one chunk ahead (in flight while the current chunk is
+  // multiplied); rows past n and pairs past mt are zero
+  constexpr int PU = kRK * kRB / 256;
+  double pa[PU], pb[PU], pw[PU];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < kRK * kRB / 256; ++u) {
+    for (int u = 0; u < PU; ++u) {
       const int e = t + 256 * u, r = e & 63, kk = e >> 6, k = k0 + kk;
       const bool kin = k < mt;
-      const double w = kin ? lt[k] : 0.0;
-      sa[kk * kRLd + r] = (kin && i0 + r < n) ? V[(i0 + r) + (size_t)k * ldv] * w : 0.0;
-      sb[kk * kRLd + r] = (kin && j0 + r < n) ? V[(j0 + r) + (size_t)k * ldv] : 0.0;
+      pw[u] = kin ? lt[k] : 0.0;
+      pa[u] = (kin && i0 + r < n) ? V[(i0 + r) + (size_t)k * ldv] : 0.0;
+      pb[u] = (kin && j0 + r < n) ? V[(j0 + r) + (size_t)k * ldv] : 0.0;
+    }
+  };
+  if (mt > 0) fetch(0);
+  for (int k0 = 0; k0 < mt; k0 += kRK) {
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int e = t + 256 * u, r = e & 63, kk = e >> 6;
+      sa[kk * kRLd + r] = pa[u] * pw[u];
+      sb[kk * kRLd + r] = pb[u];
     }
     __syncthreads();
+    if (k0 + kRK < mt) fetch(k0 + kRK);
 #pragma unroll
     for (int ks = 0; ks < kRK; ks += 4) {
       const double a = sa[(ks + g) * kRLd + 16 * wv + li];
