@@ -159,8 +159,10 @@ typedef enum {
                                   /* product, until the same stopping rule as    */
                                   /* LOBPCG holds and the certificate succeeds   */
                                   /* (at most min(max_iter, 40) passes and three */
-                                  /* failed certificates); products in FP64; the */
-                                  /* same bound; info.iters = passes             */
+                                  /* failed certificates); filter products at    */
+                                  /* opt.prec while the largest residual is 10x  */
+                                  /* above that precision's rounding floor, else */
+                                  /* FP64; the same bound; info.iters = passes   */
 } psdp_method;
 
 typedef struct {

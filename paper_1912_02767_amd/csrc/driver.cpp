@@ -1634,13 +1634,22 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
         ProfScope ps(h, "tsmm", 24.0 * n * (double)m, 3.0 * n * (double)m);
         HIP_TRY(launch_axpby3(n, m, 1.0 / e, w.AX, L, -c / e, w.X, L, 0.0, nullptr, L, w.R, L, s));
       }
+      // product precision of the pass: the low-precision copy of A while the
+      // largest residual is above ten times that precision's rounding floor
+      // (about 8 u_p ||A||_F / sqrt(n) per unit column, as for the LOBPCG
+      // ladder), FP64 otherwise; the Rayleigh-Ritz after it is FP64
+      int fprec = 0;
+      if (prec0 != 0) {
+        const double up = prec0 == 2 ? 3.9e-3 : 6.0e-8;
+        if (st.res_max_pos > 10.0 * 8.0 * up * std::sqrt(fro2 / (double)n)) fprec = prec0;
+      }
       int i0 = 0, i1 = 1;
       for (int k = 2; k <= d; ++k) {
         const int i2 = 3 - i0 - i1;
-        ProfScope ps(h, "product", (double)product_elem_bytes(0) * n * (double)n + 40.0 * n * m,
-                     2.0 * n * (double)n * m, 0);
+        ProfScope ps(h, "product", (double)product_elem_bytes(fprec) * n * (double)n + 40.0 * n * m,
+                     2.0 * n * (double)n * m, fprec);
         ProductArgs pa{};
-        pa.A = w.A64; pa.lda = L; pa.n = n; pa.prec = 0;
+        pa.A = fprec == 0 ? (const void*)w.A64 : w.Alp; pa.lda = L; pa.n = n; pa.prec = fprec;
         pa.S = yb[i1]; pa.lds = L; pa.Y = yb[i2]; pa.ldy = L;
         pa.cols_dev = nullptr; pa.cols_max = m; pa.stop = nullptr;
         pa.partial = w.ppart; pa.partial_bytes = w.ppart_bytes; pa.max_slices = kProductSlices;
@@ -1654,8 +1663,8 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       if (i1 != 0) HIP_TRY(launch_copy_cols(yb[i1], L, w.X, L, n, m, s));
       if (h->trace)
         std::fprintf(stderr, "psdp: chebyshev pass %d degree %d interval [%.4e, %.4e] xp %.6f "
-                     "rmax %.3e tol %.3e npos %d m %d\n", cheb_passes, d, a, b, xp,
-                     st.res_max_pos, tol, np, m);
+                     "rmax %.3e tol %.3e npos %d m %d prec %d\n", cheb_passes, d, a, b, xp,
+                     st.res_max_pos, tol, np, m, fprec);
       // Rayleigh-Ritz on span(X); columns the Cholesky-QR drops as dependent
       // are replaced by seeded random ones
       sv.has_p = 0;

@@ -467,3 +467,17 @@ def test_method_arguments_validated(proj):
                      raise_on_error=False)
     assert r.status == 0 and r.info["products"] > 0
     _check(r, c.X)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_chebyshev_low_precision_passes(proj, prec):
+    """With FP32 (or BF16) products requested, the filter's early passes run
+    on the low-precision copy of A while the residuals are far above its
+    rounding floor, the later ones in FP64: the result still meets 1e-6 with
+    a certified bound."""
+    from gpu_util import to_dev
+    X, lam = _iid_like(900, 9, 51)
+    res = proj.project(to_dev(X), m_cap=24, side="pos", prec=prec, method="chebyshev",
+                       raise_on_error=False)
+    assert res.status == 0 and res.info["certified"] == 1, res.info
+    _check(res, X)
