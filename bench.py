@@ -102,15 +102,24 @@ def log(*a):
 def roofline(fams, prec, workload=None):
     """Dominant kernel family: algorithmic bytes or flops per launch divided
     by its average launch time (hipEvents on the launching stream)."""
-    dom = max(fams, key=lambda f: fams[f]["ms"])
+    dom = max((f for f in fams if not f.startswith("product_")), key=lambda f: fams[f]["ms"])
     fd = fams[dom]
     if not fd["launches"] or fd["ms"] <= 0:
         return None
+    pk_prec = prec
+    if dom == "product":
+        # launches of mixed precisions: the precision with the most time,
+        # against its own peak
+        byp = {p: fams.get("product_" + p) for p in ("fp64", "fp32", "bf16")}
+        byp = {p: q for p, q in byp.items() if q and q["launches"] and q["ms"] > 0}
+        if byp:
+            pk_prec = max(byp, key=lambda p: byp[p]["ms"])
+            fd = byp[pk_prec]
     avg_ms = fd["ms"] / max(1, fd["launches"])
     flops_l = fd["flops"] / max(1, fd["launches"])
     bytes_l = fd["bytes"] / max(1, fd["launches"])
     if dom == "product":
-        pk = PEAKS[prec]
+        pk = PEAKS[pk_prec]
         ai = flops_l / max(bytes_l, 1.0)
         if ai >= pk / PEAKS["hbm"]:
             roof = {"bound": "mfma", "achieved": flops_l / (avg_ms * 1e-3) / 1e12,
@@ -132,7 +141,9 @@ def roofline(fams, prec, workload=None):
         roof = {"bound": "alu", "achieved": flops_l / (avg_ms * 1e-3) / 1e12,
                 "peak": PEAKS["fp64"] / 1e12, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(workload, dom)
+    if dom == "product":
+        roof["precision"] = pk_prec
+    roof["traffic"] = measured_traffic(workload, dom) if pk_prec == "fp64" or dom != "product" else None
     roof["algorithmic_bytes"] = bytes_l
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
@@ -275,7 +286,7 @@ def run_sequence(args, torch, psdp):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in ev])
-    fams = {f: proj.profile_get(f) for f in FAMILIES}
+    fams = {f: proj.profile_get(f) for f in FAMILIES + ["product_fp64", "product_fp32", "product_bf16"]}
     proj.profile_enable(False)
     proj.profile_filter("")
 
@@ -285,7 +296,7 @@ def run_sequence(args, torch, psdp):
         # counter-collection runs: the block solver's launches only
         proj.close()
         return {"value": steps / wall, "steps": steps, "warmup": warm,
-                "ms_per_step": 1e3 * wall / steps, "dtype": prec if args.method == "lobpcg" else "fp64",
+                "ms_per_step": 1e3 * wall / steps, "dtype": prec,
                 "config": {"workload": wl, "n": n, "method": args.method},
                 "value_note": "--skip-baselines: no full-eigendecomposition check or baseline",
                 "accuracy_ok": None, "kernels": kernels_table(fams_all)}
@@ -356,7 +367,7 @@ def run_sequence(args, torch, psdp):
                          f"FP64 cyclic Jacobi + clip"}
     iters = np.array([inf["iters"] for inf in infos])
     lob = [inf for inf in infos if inf["side_used"] != 3]
-    rp = prec if args.method == "lobpcg" else "fp64"  # the filter's products are FP64
+    rp = prec  # products at prec, the FP64 ladder or late passes beside them
     cert = fams_all.get("cert", {"launches": 0, "ms": 0.0})
     out = {
         "value": ok_steps / wall, "steps": steps, "warmup": warm, "ms_per_step": 1e3 * wall / steps,
@@ -364,7 +375,8 @@ def run_sequence(args, torch, psdp):
         "config": {"workload": wl, "n": n, "n_pos": p, "block": block, "tol": tol,
                    "bound_rel_target": args.bound_rel if big else None,
                    "matrices": len(mats), "method": args.method,
-                   "products": prec if args.method == "lobpcg" else "fp64",
+                   "products": (prec if args.method == "lobpcg" or prec == "fp64"
+                                else f"{prec} while far from convergence, then fp64"),
                    "ortho_rr_refine": "fp64",
                    "tail": "certified (FP64 Cholesky certificate)"},
         "value_note": "projections/s counting only steps within 1e-6 of the full eig "

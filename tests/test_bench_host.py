@@ -66,3 +66,14 @@ def test_rebuild_roofline_bound_follows_intensity(bench):
     big = bench.roofline({"rebuild": _fam(1, 0.3, 4000.0 ** 2 * 370, 8 * 4000.0 ** 2)}, "fp64")
     small = bench.roofline({"rebuild": _fam(1, 0.05, 4000.0 ** 2 * 40, 8 * 4000.0 ** 2)}, "fp64")
     assert big["bound"] == "alu" and small["bound"] == "hbm"
+
+
+def test_product_roofline_takes_dominant_precision(bench):
+    fams = {"product": _fam(20, 2.0, 20 * 1.5e9, 20 * 1.3e8),
+            "product_fp64": _fam(10, 1.2, 10 * 1.5e9, 10 * 1.3e8),
+            "product_fp32": _fam(10, 0.8, 10 * 1.5e9, 10 * 0.65e8),
+            "rr": _fam(5, 0.5, 1e6, 1e5)}
+    r = bench.roofline(fams, "fp32")
+    assert r["kernel"] == "product" and r["precision"] == "fp64"
+    assert abs(r["peak"] - 78.6) < 1e-9
+    assert abs(r["achieved"] - 1.5e9 / 0.12e-3 / 1e12) < 1e-9
