@@ -80,6 +80,12 @@ TRAFFIC = {
         "sha256": "46ef570f9b95da0c231393ec1d4b7d39ee0debfed29160660860c324eed1c130",
         "profile": "profiles/hbm_traffic_n4000_mixed_iid.txt",
     },
+    ("n4000_mixed_iid", "cert"): {
+        "bytes": 3880.8e6,  # per certificate: k_cert_* + 62 k_chol_trsm + 62 k_chol_syrk + W = A V
+        "files": ['paper_1912_02767_amd/csrc/k_cert.hip', 'paper_1912_02767_amd/csrc/cert.h', 'paper_1912_02767_amd/csrc/k_product.hip', 'paper_1912_02767_amd/csrc/common.h'],
+        "sha256": "a094c849e3be8652bb90c524804f461f72ef8537360887426ff6f57308ce92b8",
+        "profile": "profiles/hbm_traffic_n4000_mixed_iid.txt",
+    },
 }
 
 
