@@ -718,12 +718,16 @@ def run_admm(args, torch, psdp):
     proj = psdp.Projector(0)
     proj.admm_solve(sdp, max_iter=20)  # untimed: library and solver warm-up
     torch.cuda.synchronize()
-    Ya, ya, Wa, ia = proj.admm_solve(sdp, max_iter=2500, eps_abs=eps, eps_rel=eps)
+    Ya, ya, Wa, ia = proj.admm_solve(sdp, max_iter=2500, eps_abs=eps, eps_rel=eps,
+                                     method=args.method)
+    other = "lobpcg" if args.method == "chebyshev" else "chebyshev"
+    Yo, yo, Wo, io = proj.admm_solve(sdp, max_iter=2500, eps_abs=eps, eps_rel=eps, method=other)
     Ye, ye, We, ie = proj.admm_solve(sdp, exact=True, max_iter=2500, eps_abs=eps, eps_rel=eps)
     # kernel families of one untimed approximate solve (the dominant
     # hand-written family and its roofline)
     proj.profile_enable(True)
-    proj.admm_solve(sdp, max_iter=min(400, ia["iters"]), eps_abs=eps, eps_rel=eps)
+    proj.admm_solve(sdp, max_iter=min(400, ia["iters"]), eps_abs=eps, eps_rel=eps,
+                    method=args.method)
     fams_all = {f: proj.profile_get(f) for f in FAMILIES + ["product_fp64", "product_fp32", "product_bf16"]}
     proj.profile_enable(False)
     ours = {f: v for f, v in fams_all.items() if f in FAMILIES and f not in LIBRARY_FAMILIES}
@@ -744,9 +748,10 @@ def run_admm(args, torch, psdp):
         "ms_per_step": ia["total_ms"] / max(1, ia["iters"]), "dtype": "fp64",
         "config": {"workload": "admm_maxcut800", "n": n, "edges": int(((sdp.C != 0).sum() - (np.diag(sdp.C) != 0).sum()) // 2),
                    "eps_abs": eps, "eps_rel": eps, "tol_schedule": "10/k^1.01",
-                   "rho": 0.1, "sigma": 1e-6, "alpha": 1.6},
+                   "rho": 0.1, "sigma": 1e-6, "alpha": 1.6, "method": args.method},
         "value_note": "ADMM projections per second (block-solver run)",
-        "admm_block": ia, "admm_exact": ie,
+        "admm_block": ia, "admm_exact": ie, "admm_other_method": dict(io, method=other),
+        "proj_ms_per_iter_other_method": io["proj_ms"] / max(1, io["iters"]),
         "proj_ms_per_iter_block": ia["proj_ms"] / max(1, ia["iters"]),
         "proj_ms_per_iter_exact": ie["proj_ms"] / max(1, ie["iters"]),
         "speedup_proj_per_iter": (ie["proj_ms"] / max(1, ie["iters"])) /

@@ -487,6 +487,8 @@ typedef struct {
     double tol_power;       /* tol_scale / k^tol_power (10, 1.01: paper §6)       */
     int prec;               /* psdp_prec of the block products (FP64)             */
     int m_cap;              /* block capacity of the projections (48)             */
+    int method;             /* eigensolver of the projections: PSDP_METHOD_LOBPCG */
+                            /* (default) or PSDP_METHOD_CHEBYSHEV                 */
 } psdp_admm_options;
 
 enum {

@@ -316,6 +316,8 @@ class Projector:
         for k, v in opts.items():
             if k == "prec" and isinstance(v, str):
                 v = PREC[v]
+            if k == "method" and isinstance(v, str):
+                v = METHOD[v]
             setattr(o, k, v)
         Y = _empty_f(n, n, dev)
         W = _empty_f(n, n, dev)

@@ -123,6 +123,7 @@ class AdmmOptions(ctypes.Structure):
         ("tol_power", ctypes.c_double),
         ("prec", ctypes.c_int),
         ("m_cap", ctypes.c_int),
+        ("method", ctypes.c_int),
     ]
 
 

@@ -82,6 +82,7 @@ extern "C" void psdp_admm_default_options(psdp_admm_options* o) {
   o->tol_power = 1.01;
   o->prec = PSDP_PREC_FP64;
   o->m_cap = 48;
+  o->method = PSDP_METHOD_LOBPCG;
 }
 
 extern "C" psdp_status psdp_admm_solve(psdp_handle h, const psdp_sdp* pr,
@@ -103,7 +104,8 @@ extern "C" psdp_status psdp_admm_solve(psdp_handle h, const psdp_sdp* pr,
   if (!(opt.rho > 0.0) || !(opt.sigma > 0.0) || !(opt.alpha > 0.0) || !(opt.alpha < 2.0) ||
       opt.max_iter < 1 || opt.check_every < 1 || !(opt.eps_abs >= 0.0) || !(opt.eps_rel >= 0.0) ||
       !(opt.eps_inf > 0.0) || !(opt.tol_scale > 0.0) || !(opt.tol_power >= 0.0) || opt.prec < 0 ||
-      opt.prec > 2 || opt.m_cap < 1)
+      opt.prec > 2 || opt.m_cap < 1 ||
+      (opt.method != PSDP_METHOD_LOBPCG && opt.method != PSDP_METHOD_CHEBYSHEV))
     return PSDP_ERR_INVALID_ARG;
 
   const int n = pr->n, p = pr->p, nnz = pr->nnz;
@@ -220,6 +222,7 @@ extern "C" psdp_status psdp_admm_solve(psdp_handle h, const psdp_sdp* pr,
         po.pos_hint = pos_hint;
         po.warm_side = warm_side;
         po.fallback_full = 1;
+        po.method = opt.method;
         psdp_info pi;
         const double ta = now_ms();
         psdp_status r = psdp_project(h, n, V, n, Vblk, n, mcap, &m_io, lam, Z, n, &po, &pi);

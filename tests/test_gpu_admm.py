@@ -78,16 +78,18 @@ def test_block_solver_maxcut_complete_graph(proj, n):
     assert max(prim, dual, comp, wres) <= 1e-4, (prim, dual, comp, wres)
 
 
-def test_block_solver_random_maxcut_matches_exact(proj):
+@pytest.mark.parametrize("method", ["lobpcg", "chebyshev"])
+def test_block_solver_random_maxcut_matches_exact(proj, method):
     """With a projection tolerance that decays fast enough (10/k^2) the block
     solver reaches the exact run's optimum to 1e-6; with the paper's
     10/k^1.01 it reaches a modest accuracy (the schedule is summable, but its
-    tail keeps projection errors of ~1e-3 at k = 5000)."""
+    tail keeps projection errors of ~1e-3 at k = 5000).  Both eigensolvers."""
     sdp = maxcut(150, prob=0.1)
     Ya, ya, Wa, ia = proj.admm_solve(sdp, max_iter=5000, eps_abs=1e-7, eps_rel=1e-7,
-                                     tol_power=2.0)
+                                     tol_power=2.0, method=method)
     Ye, ye, We, ie = proj.admm_solve(sdp, exact=True, max_iter=5000, eps_abs=1e-7, eps_rel=1e-7)
-    Yp, yp, Wp, ip = proj.admm_solve(sdp, max_iter=5000, eps_abs=1e-4, eps_rel=1e-4)
+    Yp, yp, Wp, ip = proj.admm_solve(sdp, max_iter=5000, eps_abs=1e-4, eps_rel=1e-4,
+                                     method=method)
     print(ia, ie, ip)
     assert ia["status"] == 0 and ie["status"] == 0 and ip["status"] == 0
     assert ia["proj_block"] > 0 and ip["proj_block"] > 0
