@@ -169,18 +169,20 @@ def test_invalid_requests(gpu):
     srv.close()
 
 
-def test_mix_serves_warm_requests_with_the_block_solver(gpu):
+@pytest.mark.parametrize("method", ["lobpcg", "chebyshev"])
+def test_mix_serves_warm_requests_with_the_block_solver(gpu, method):
     """Sessions whose spectra keep a gap: after each session's first request
     (no inertia estimate yet: the exact path) the warm-started requests are
     served by the block eigensolver on the positive side, in the mix as
-    alone, and match the oracle and their stand-alone results."""
+    alone, and match the oracle and their stand-alone results (both
+    eigensolvers)."""
     torch = gpu
     import paper_1912_02767_amd as psdp
     from gpu_util import to_host
     specs = gapped_sessions(count=5, stream=1)
     reqs = _requests(specs, steps=4)
-    mix, stats, _ = _serve(psdp, torch, specs, reqs, slots=4, batch_lane=False)
-    alone = _alone(psdp, torch, specs, reqs, slots=4, batch_lane=False)
+    mix, stats, _ = _serve(psdp, torch, specs, reqs, slots=4, batch_lane=False, method=method)
+    alone = _alone(psdp, torch, specs, reqs, slots=4, batch_lane=False, method=method)
     sides = [r.info["side_used"] for r in mix]
     print("stats", stats, "sides", sides)
     block = [k for k, s in enumerate(sides) if s == 1]
