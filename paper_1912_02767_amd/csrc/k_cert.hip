@@ -466,26 +466,32 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int L
   __shared__ __align__(16) double lt[kT * kT];  // lt[c * 64 + q] = L_kk(q, c), q > c
   __shared__ double rinv[kT];
   const int t = threadIdx.x;
-  {
-    const double* src = M + (size_t)(k * kT) + (size_t)(k * kT) * L;
-#pragma unroll 4
-    for (int u = 0; u < kT * kT / 256; ++u) {
-      const int e = t + 256 * u, q = e & 63, c = e >> 6;
-      const double v = src[q + (size_t)c * L];
-      if (q == c) rinv[c] = 1.0 / v;
-      lt[c * kT + q] = (q > c) ? v : 0.0;
-    }
-  }
-  __syncthreads();
   const int g = t & 15;  // this lane's place in its sixteen-lane DPP row
   const int row = (k + 1) * kT + blockIdx.x * 16 + (t >> 4);
   double* rowp = M + (size_t)row + (size_t)(k * kT + 4 * g) * L;
   double x[4], rv[4];
+  // the row's loads and all of L_kk's are issued before any is used
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    x[q] = rowp[(size_t)q * L];
-    rv[q] = rinv[4 * g + q];
+  for (int q = 0; q < 4; ++q) x[q] = rowp[(size_t)q * L];
+  {
+    const double* src = M + (size_t)(k * kT) + (size_t)(k * kT) * L;
+    constexpr int U = kT * kT / 256;
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = t + 256 * u, q = e & 63, c = e >> 6;
+      v[u] = src[q + (size_t)c * L];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = t + 256 * u, q = e & 63, c = e >> 6;
+      if (q == c) rinv[c] = 1.0 / v[u];
+      lt[c * kT + q] = (q > c) ? v[u] : 0.0;
+    }
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) rv[q] = rinv[4 * g + q];
 #pragma unroll
   for (int c = 0; c < kT; ++c) {
     const int own = c >> 2, qq = c & 3;
@@ -517,17 +523,27 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ M, int L
   const int bi = k + 1 + ii, bj = k + 1 + jj;
   const int i0 = bi * kT, j0 = bj * kT, k0 = k * kT;
   const int t = threadIdx.x, tr = t & 15, tc = t >> 4;
-#pragma unroll 4
-  for (int u = 0; u < kT * kT / 256; ++u) {
+  // every global load (both panel tiles and the target tile) is issued
+  // before the first is used
+  constexpr int U = kT * kT / 256;
+  double pv[U], qv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
     const int e = t + 256 * u, r = e & 63, q = e >> 6;
-    pt[q * kT + r] = M[(size_t)(i0 + r) + (size_t)(k0 + q) * L];
-    qt[q * kT + r] = M[(size_t)(j0 + r) + (size_t)(k0 + q) * L];
+    pv[u] = M[(size_t)(i0 + r) + (size_t)(k0 + q) * L];
+    qv[u] = M[(size_t)(j0 + r) + (size_t)(k0 + q) * L];
   }
   double acc[4][4];
 #pragma unroll
   for (int b = 0; b < 4; ++b)
 #pragma unroll
     for (int a = 0; a < 4; ++a) acc[a][b] = M[(size_t)(i0 + 4 * tr + a) + (size_t)(j0 + 4 * tc + b) * L];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = t + 256 * u, r = e & 63, q = e >> 6;
+    pt[q * kT + r] = pv[u];
+    qt[q * kT + r] = qv[u];
+  }
   __syncthreads();
 #pragma unroll 4
   for (int q = 0; q < kT; ++q) {
