@@ -93,18 +93,21 @@ __device__ __attribute__((always_inline)) inline int chol32_wave(double* a, doub
 #pragma unroll
   for (int c = 0; c < 32; ++c) r[c] = act ? a[(o + lane) * kLd + o + c] : 0.0;
   // No branch per column: a failed pivot clears `ok` (the same on every
-  // lane) and is replaced by 1 so the remaining arithmetic stays finite;
-  // the next column's update comes first so that the next pivot's broadcast
-  // and reciprocal square root overlap the rest of this column's updates.
+  // lane) and is replaced by 1 so the remaining arithmetic stays finite.
+  // The next pivot is lane j + 1's own update of its diagonal entry,
+  // a_{j+1,j+1} - l_{j+1,j}^2 (the same FMA the column update below applies
+  // there), broadcast before the column goes through LDS, so that its
+  // reciprocal square root overlaps the rest of this column's updates.
   int ok = 1;
+  double d = bcast_lane(r[0], 0);
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
-    double d = bcast_lane(r[j], j);
     ok &= (d > 0.0 && d < INFINITY) ? 1 : 0;
     d = ok ? d : 1.0;
     const double inv = rsqrt_nr(d);
     const double l = r[j] * inv;
     r[j] = (lane == j) ? d * inv : l;
+    const double dn = (j + 1 < 32) ? bcast_lane(fma(-l, l, r[(j + 1) & 31]), (j + 1) & 31) : 0.0;
     double* b = cb + (j & 1) * kT;
     b[lane] = l;
     double w[32];
@@ -114,9 +117,9 @@ __device__ __attribute__((always_inline)) inline int chol32_wave(double* a, doub
       w[c0] = v.x;
       w[c0 + 1] = v.y;
     }
-    if (j + 1 < 32) r[j + 1] = fma(-l, w[j + 1], r[j + 1]);
 #pragma unroll
-    for (int c = j + 2; c < 32; ++c) r[c] = fma(-l, w[c], r[c]);
+    for (int c = j + 1; c < 32; ++c) r[c] = fma(-l, w[c], r[c]);
+    d = dn;
   }
   if (act) {
 #pragma unroll
