@@ -157,7 +157,8 @@ __device__ inline uint4 mask_k(uint4 v, int k0, int kend) {
   return v;
 }
 
-template <int PREC, int NCT>
+// FULL: the launch's width (known on the host) fills all NCT column tiles
+template <int PREC, int NCT, bool FULL>
 __global__ __launch_bounds__(256) void k_product_mfma(const void* __restrict__ A, int lda, int n,
                                                       const double* __restrict__ S, int lds,
                                                       int cols_alloc, void* __restrict__ part,
@@ -233,9 +234,21 @@ __global__ __launch_bounds__(256) void k_product_mfma(const void* __restrict__ A
       ring[s] = *(const uint4*)(arow + min(kb + KC, kmax));  // next chunk, same step
       if (tail) av = mask_k<PREC>(av, kb + EPL * g, kend);
       const el* bcol = sB + li * LDK + s * KPL + EPL * g;
+      if constexpr (FULL) {
+        // every tile in use: each tile's B fragment read before the first
+        // MFMA uses one
+        uint4 bv[NCT];
 #pragma unroll
-      for (int t = 0; t < NCT; ++t)
-        if (16 * t < colsr) mfma_step<PREC>(av, *(const uint4*)(bcol + 16 * t * LDK), acc[t]);
+        for (int t = 0; t < NCT; ++t) bv[t] = *(const uint4*)(bcol + 16 * t * LDK);
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) mfma_step<PREC>(av, bv[t], acc[t]);
+      } else {
+        // the width is read on the device (columns dropped or converged):
+        // the tiles past it are skipped
+#pragma unroll
+        for (int t = 0; t < NCT; ++t)
+          if (16 * t < colsr) mfma_step<PREC>(av, *(const uint4*)(bcol + 16 * t * LDK), acc[t]);
+      }
     }
     __syncthreads();
   }
@@ -309,10 +322,15 @@ hipError_t launch_product(const ProductArgs& a, hipStream_t st) {
     if ((size_t)sk * pstride * elem > a.partial_bytes) return hipErrorInvalidValue;
     dim3 grid(rt, sk);
     const int nct = (a.cols_max + 15) / 16;
-#define PSDP_LAUNCH_PRODUCT(P, T)                                                            \
-  hipLaunchKernelGGL((k_product_mfma<P, T>), grid, dim3(256), 0, st, a.A, a.lda, a.n, a.S, a.lds, \
-                     a.cols_max, (void*)a.partial, a.lda, pstride, a.cols_dev, a.cols_max,   \
-                     kslice, a.stop)
+#define PSDP_LAUNCH_PRODUCT(P, T)                                                              \
+  if (!a.cols_dev && (a.cols_max + 15) / 16 == T)                                              \
+    hipLaunchKernelGGL((k_product_mfma<P, T, true>), grid, dim3(256), 0, st, a.A, a.lda, a.n,   \
+                       a.S, a.lds, a.cols_max, (void*)a.partial, a.lda, pstride, a.cols_dev,    \
+                       a.cols_max, kslice, a.stop);                                            \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_product_mfma<P, T, false>), grid, dim3(256), 0, st, a.A, a.lda, a.n,  \
+                       a.S, a.lds, a.cols_max, (void*)a.partial, a.lda, pstride, a.cols_dev,    \
+                       a.cols_max, kslice, a.stop)
 #define PSDP_LAUNCH_PREC(P)                        \
   if (nct <= 3) PSDP_LAUNCH_PRODUCT(P, 3);         \
   else if (nct <= 6) PSDP_LAUNCH_PRODUCT(P, 6);    \
