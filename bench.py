@@ -75,15 +75,15 @@ KERNEL_TABLE_STEPS = 10   # untimed steps that time every family
 # kernel and is reported as null.
 TRAFFIC = {
     ("n4000_mixed_iid", "product"): {
-        "bytes": 178.58e6,  # k_product_mfma<0, 3> 161975.4 KB + k_product_reduce 16601.0 KB
-        "files": ["paper_1912_02767_amd/csrc/k_product.hip", "paper_1912_02767_amd/csrc/common.h"],
-        "sha256": "46ef570f9b95da0c231393ec1d4b7d39ee0debfed29160660860c324eed1c130",
+        "bytes": 1.7798e+08,  # FP64 launch: k_product_mfma<0, 3, true> + k_product_reduce<double>
+        "files": ['paper_1912_02767_amd/csrc/k_product.hip', 'paper_1912_02767_amd/csrc/common.h'],
+        "sha256": "b8ace7f171010211f63481b918692b4397e4a377b8ab5ea8305e3e3373c5ab10",
         "profile": "profiles/hbm_traffic_n4000_mixed_iid.txt",
     },
     ("n4000_mixed_iid", "cert"): {
-        "bytes": 3880.8e6,  # per certificate: k_cert_* + 62 k_chol_trsm + 62 k_chol_syrk + W = A V
+        "bytes": 3.9006e+09,  # per certificate: k_cert_* + 62 k_chol_trsm + 62 k_chol_syrk + W = A V
         "files": ['paper_1912_02767_amd/csrc/k_cert.hip', 'paper_1912_02767_amd/csrc/cert.h', 'paper_1912_02767_amd/csrc/k_product.hip', 'paper_1912_02767_amd/csrc/common.h'],
-        "sha256": "a094c849e3be8652bb90c524804f461f72ef8537360887426ff6f57308ce92b8",
+        "sha256": "5d13c13420e3f8d78b6cf4d5983e9dfd2a22dab1ad61c2644b4fdcc5cfa80fdd",
         "profile": "profiles/hbm_traffic_n4000_mixed_iid.txt",
     },
 }
