@@ -1605,8 +1605,11 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       // so that the filtered columns stay numerically independent: a column
       // with residual r has components of at most r / (theta_0 - theta_m)
       // along the top eigenvectors, which the filter multiplies by R
-      // relative to its own, so R = 1e4 (theta_0 - theta_m) / max r, kept
-      // within [1e5, 1e10] (rounding of the products bounds it above)
+      // relative to its own, so R = 1e6 (theta_0 - theta_m) / max r (that
+      // bound is far above the components Ritz vectors carry in practice),
+      // kept within [1e5, 1e13] (rounding of the products bounds it above);
+      // columns that still come out dependent are dropped by the
+      // Cholesky-QR and replaced
       const double b = st.theta[m - 1];
       const double a = std::min(cheb_lo, b - 1e-3 * std::max(std::fabs(b), 1e-300));
       const double c = 0.5 * (a + b), e = 0.5 * (b - a);
@@ -1624,7 +1627,7 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       const double spread = std::acosh(xmax) - ap;
       double rall = 0.0;
       for (int i = 0; i < m; ++i) rall = std::max(rall, st.rnorm[i]);
-      const double R = std::min(1e10, std::max(1e5, 1e4 * (st.theta[0] - b) / std::max(rall, 1e-300)));
+      const double R = std::min(1e13, std::max(1e5, 1e6 * (st.theta[0] - b) / std::max(rall, 1e-300)));
       if (spread > 0) d = std::min(d, (int)(std::log(R) / spread));
       d = std::max(2, std::min(d, dmax));
       // Y0 = X, Y1 = (AX - c X) / e (AX exact from the last Rayleigh-Ritz),
