@@ -120,20 +120,25 @@ def test_nonfinite_input_rejected(proj):
     assert e.value.code == psdp.PSDP_ERR_NUMERICAL
 
 
-def test_trivial_inputs(proj):
+@pytest.mark.parametrize("method", ["lobpcg", "chebyshev"])
+def test_trivial_inputs(proj, method):
     from gpu_util import to_dev, to_host
     # PSD input: Pi = X on the negative side (nothing negative to find)
     rng = rng_for(52, 0)
     Q = haar_orthogonal(40, rng)
     X = from_spectrum(Q, rng.uniform(0.5, 2.0, 40))
-    res = proj.project(to_dev(X), m_cap=8, side="neg", tol=1e-10)
+    res = proj.project(to_dev(X), m_cap=8, side="neg", tol=1e-10, method=method)
     assert np.abs(to_host(res.Pi) - X).max() <= 1e-9
     # NSD input: Pi = 0 on the positive side
-    res = proj.project(to_dev(-X), m_cap=8, side="pos", tol=1e-10)
+    res = proj.project(to_dev(-X), m_cap=8, side="pos", tol=1e-10, method=method)
     assert np.abs(to_host(res.Pi)).max() <= 1e-9
     # n = 1
-    res = proj.project(to_dev(np.array([[2.5]])), m_cap=1, side="pos", tol=1e-12)
+    res = proj.project(to_dev(np.array([[2.5]])), m_cap=1, side="pos", tol=1e-12, method=method)
     assert abs(to_host(res.Pi)[0, 0] - 2.5) <= 1e-12
+    # zero matrix
+    res = proj.project(to_dev(np.zeros((20, 20))), m_cap=4, side="pos", method=method,
+                       raise_on_error=False)
+    assert res.status >= 0 and np.abs(to_host(res.Pi)).max() == 0.0
 
 
 @pytest.mark.parametrize("n,npos,m_cap", [(120, 10, 24), (300, 20, 26), (300, 22, 27), (400, 40, 48)])
