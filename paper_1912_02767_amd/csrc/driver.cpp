@@ -104,7 +104,8 @@ struct Workspace {
   double* scal = nullptr;  // [0] fro2
   int* nonfinite = nullptr;
   State* st = nullptr;
-  double* lz = nullptr;  // Lanczos bound: three vectors (ld L), coefficients, result
+  double* lz = nullptr;  // Lanczos bound: three vectors (ld L), coefficients, result,
+                         // then the split-K partials of its one-column products
 };
 
 }  // namespace
@@ -132,6 +133,11 @@ struct psdp_handle_s {
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t sync_ev = nullptr;  // polled by spin_wait
+  // second stream (default priority, non-blocking) for the Lanczos bound of
+  // the Chebyshev variant, which runs beside the first Rayleigh-Ritz step;
+  // its pinned result slot
+  hipStream_t aux = nullptr;
+  double* h_pin_aux = nullptr;
   State* h_snap = nullptr;         // two pinned state snapshots of queued iterations
   hipEvent_t snap_ev[2] = {nullptr, nullptr};
   psdp::BatchEngine* batch = nullptr;
@@ -198,17 +204,19 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   double bytes, flops;
   int prec;
-  ProfScope(psdp_handle h_, const char* f, double by = 0, double fl = 0, int pr = -1)
-      : h(h_), fam(f), bytes(by), flops(fl), prec(pr) {
+  hipStream_t st;
+  ProfScope(psdp_handle h_, const char* f, double by = 0, double fl = 0, int pr = -1,
+            hipStream_t s_ = nullptr)
+      : h(h_), fam(f), bytes(by), flops(fl), prec(pr), st(s_ ? s_ : h_->stream) {
     if (h->prof && (h->prof_only.empty() || h->prof_only.count(f))) {
       a = get_event(h);
       b = get_event(h);
-      if (a) (void)hipEventRecord(a, h->stream);
+      if (a) (void)hipEventRecord(a, st);
     }
   }
   ~ProfScope() {
     if (a && b) {
-      (void)hipEventRecord(b, h->stream);
+      (void)hipEventRecord(b, st);
       h->pending.push_back({fam, a, b, bytes, flops, prec});
     }
   }
@@ -217,6 +225,7 @@ struct ProfScope {
 void prof_collect(psdp_handle h) {
   if (h->pending.empty()) return;
   (void)hipStreamSynchronize(h->stream);
+  if (h->aux) (void)hipStreamSynchronize(h->aux);
   for (auto& p : h->pending) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, p.a, p.b);
@@ -286,7 +295,7 @@ psdp_status ensure_workspace(psdp_handle h, int n, int mc, int prec) {
   size_t oScal = take(sizeof(double) * 16);
   size_t oNf = take(sizeof(int) * 16);
   size_t oSt = take(sizeof(State));
-  size_t oLz = take(sizeof(double) * (3 * (size_t)L + 128));
+  size_t oLz = take(sizeof(double) * ((3 + kProductSlices) * (size_t)L + 128));
   if (w.base) {
     (void)hipStreamSynchronize(h->stream);
     hipFree(w.base);
@@ -665,27 +674,42 @@ struct Solver {
 // `prec`), then theta_min(T) - beta_steps (Zhou and Saad's estimator; the
 // Ritz value lies above the spectrum's lower end and the last coupling
 // bounds how far).  Used for the damped interval of the Chebyshev filter.
-psdp_status lanczos_lower(psdp_handle h, int n, int prec, int steps, uint64_t seed,
-                          uint64_t stream_id, double* lo, double* theta_min) {
+// lanczos_launch queues the steps on the handle's second stream (the
+// ingested copies of A must be complete; only A and the Lanczos region of
+// the workspace are touched, so the first Rayleigh-Ritz step can run on the
+// main stream meanwhile); lanczos_finish waits for them and reads the bound.
+psdp_status lanczos_launch(psdp_handle h, int n, int prec, int steps, uint64_t seed,
+                           uint64_t stream_id) {
   Workspace& w = h->ws;
-  hipStream_t s = h->stream;
+  if (!h->aux && hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking) != hipSuccess) {
+    h->aux = nullptr;
+    return PSDP_ERR_HIP;
+  }
+  if (!h->h_pin_aux &&
+      hipHostMalloc((void**)&h->h_pin_aux, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    h->h_pin_aux = nullptr;
+    return PSDP_ERR_OUT_OF_MEMORY;
+  }
+  hipStream_t s = h->aux;
   const int L = w.L;
   steps = std::max(1, std::min(steps, std::min(n, 30)));
   double* vb[3] = {w.lz, w.lz + L, w.lz + 2 * (size_t)L};
   double* coef = w.lz + 3 * (size_t)L;
   double* out = coef + 96;
+  double* part = coef + 128;
   HIP_TRY(launch_fill_normal(vb[0], L, n, 0, 1, seed, stream_id, s));
   HIP_TRY(launch_lanczos_vec(n, -1, 0, vb[0], nullptr, nullptr, coef, out, s));
   int iv = 0, iw = 1, ip = 2;
   for (int j = 0; j < steps; ++j) {
     {
       ProfScope ps(h, "lanczos", (double)product_elem_bytes(prec) * n * (double)n + 16.0 * n,
-                   2.0 * n * (double)n);
+                   2.0 * n * (double)n, -1, s);
       ProductArgs pa{};
       pa.A = prec == 0 ? (const void*)w.A64 : w.Alp; pa.lda = L; pa.n = n; pa.prec = prec;
       pa.S = vb[iv]; pa.lds = L; pa.Y = vb[iw]; pa.ldy = L;
       pa.cols_dev = nullptr; pa.cols_max = 1; pa.stop = nullptr;
-      pa.partial = w.ppart; pa.partial_bytes = w.ppart_bytes; pa.max_slices = kProductSlices;
+      pa.partial = part; pa.partial_bytes = sizeof(double) * kProductSlices * (size_t)L;
+      pa.max_slices = kProductSlices;
       HIP_TRY(launch_product(pa, s));
       HIP_TRY(launch_lanczos_vec(n, j, j == steps - 1, vb[iw], vb[iv], vb[ip], coef, out, s));
     }
@@ -694,14 +718,27 @@ psdp_status lanczos_lower(psdp_handle h, int n, int prec, int steps, uint64_t se
     iv = iw;
     iw = t;
   }
-  psdp_status pp = ensure_pinned(h, 64);
-  if (pp != PSDP_OK) return pp;
-  HIP_TRY(copy_to_host(h->h_pin, out, 3 * sizeof(double), s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *lo = h->h_pin[0];
-  *theta_min = h->h_pin[1];
+  HIP_TRY(copy_to_host(h->h_pin_aux, out, 3 * sizeof(double), s));
+  return PSDP_OK;
+}
+
+psdp_status lanczos_finish(psdp_handle h, double* lo, double* theta_min) {
+  HIP_TRY(hipStreamSynchronize(h->aux));
+  *lo = h->h_pin_aux[0];
+  *theta_min = h->h_pin_aux[1];
   return std::isfinite(*lo) ? PSDP_OK : PSDP_ERR_NUMERICAL;
 }
+
+// Waits for the second stream when a call leaves while the Lanczos steps
+// may still be queued (an error return), so that nothing later overwrites
+// A under them.
+struct AuxJoin {
+  psdp_handle h;
+  bool pending = false;
+  ~AuxJoin() {
+    if (pending && h->aux) (void)hipStreamSynchronize(h->aux);
+  }
+};
 
 psdp_status ensure_cert(psdp_handle h, int L) {
   if (h->cert_base && h->cert_L >= L) return PSDP_OK;
@@ -895,6 +932,11 @@ psdp_status psdp_destroy(psdp_handle h) {
   prof_collect(h);
   for (auto e : h->event_pool) hipEventDestroy(e);
   if (h->sync_ev) hipEventDestroy(h->sync_ev);
+  if (h->aux) {
+    (void)hipStreamSynchronize(h->aux);
+    hipStreamDestroy(h->aux);
+  }
+  if (h->h_pin_aux) hipHostFree(h->h_pin_aux);
   for (auto e : h->snap_ev) if (e) hipEventDestroy(e);
   if (h->h_snap) hipHostFree(h->h_snap);
   if (h->ws.base) hipFree(h->ws.base);
@@ -1481,6 +1523,14 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   if (nonfin || !std::isfinite(fro2)) { info->status = PSDP_ERR_NUMERICAL; return PSDP_ERR_NUMERICAL; }
   double tol = opt.tol > 0 ? opt.tol : 1e-8 * std::sqrt(fro2) / std::sqrt(2.0 * m0);
   if (tol <= 0) tol = 1e-300;
+  // the Chebyshev variant's spectrum bound needs only the ingested A: it
+  // runs on the second stream beside the first Rayleigh-Ritz step
+  AuxJoin aux_join{h};
+  if (opt.method == PSDP_METHOD_CHEBYSHEV) {
+    psdp_status lr = lanczos_launch(h, n, prec0, 10, opt.seed, (h->calls << 8) | 0xFF);
+    if (lr != PSDP_OK) { info->status = lr; return lr; }
+    aux_join.pending = true;
+  }
   // ---- state init
   State& hs = *h->h_state;
   std::memset(&hs, 0, sizeof(State));
@@ -1546,7 +1596,8 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
     // amplified by T_d at their scaled position, then Rayleigh-Ritz on
     // span(X) with an FP64 product; repeated until the stopping rule holds.
     double thmin = 0.0;
-    rc = lanczos_lower(h, n, prec0, 10, seed, rng_stream++, &cheb_lo, &thmin);
+    rc = lanczos_finish(h, &cheb_lo, &thmin);
+    aux_join.pending = false;
     if (rc != PSDP_OK) { info->status = rc; return rc; }
     cheb_lo -= 1e-2 * std::fabs(cheb_lo);  // margin for the rounding of the bound
     cheb_products += 10;

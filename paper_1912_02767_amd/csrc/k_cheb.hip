@@ -39,6 +39,7 @@ hipError_t launch_axpby3(int n, int cols, double ca, const double* Y, int ldy, d
 }
 
 constexpr int kLzThreads = 1024;
+constexpr int kLzReg = 8;  // elements per thread kept in registers (n <= 8192)
 
 __device__ inline double lz_block_sum(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -65,19 +66,49 @@ __device__ inline int sturm_below(const double* al, const double* be, int k, dou
   return cnt;
 }
 
+// Smallest eigenvalue of the k x k tridiagonal (A, B[1..k-1]) by
+// multisection on one wave: each round the 64 lanes count at 64 interior
+// points of [lo, hi] and the bracket shrinks to the 1/65 in which the count
+// first reaches 1 (the largest x with no eigenvalue below it is lo).
+__device__ inline double tridiag_min_wave(const double* A, const double* B, int k) {
+  const int lane = threadIdx.x & 63;
+  double lo = A[0], hi = A[0];
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? fabs(B[i]) : 0.0) + (i + 1 < k ? fabs(B[i + 1]) : 0.0);
+    lo = fmin(lo, A[i] - r);
+    hi = fmax(hi, A[i] + r);
+  }
+  for (int it = 0; it < 40 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
+    const double w = (hi - lo) / 65.0;
+    const double x = lo + w * (lane + 1);
+    const unsigned long long above = __ballot(sturm_below(A, B, k, x) >= 1);
+    // points at and right of the first lane with a count >= 1 bound from above
+    const int first = above ? __builtin_ctzll(above) : 64;
+    const double nlo = lo + w * first, nhi = first < 64 ? lo + w * (first + 1) : hi;
+    lo = nlo;
+    hi = fmax(nhi, nlo);
+  }
+  return lo;
+}
+
 // coef: alpha[0..31], beta[32..64] (beta[32 + j] = beta_j, beta_0 = 0),
 // out[0] = lower bound, out[1] = theta_min, out[2] = last beta.
 //   step < 0 : v <- v / ||v||
 //   step j   : w <- w - beta_j vprev; alpha_j = w.v; w <- w - alpha_j v;
 //              beta_{j+1} = ||w||; w <- w / beta_{j+1}  (the next v)
 //   last     : bound from T_{j+1}
+// For n <= kLzReg * kLzThreads each thread keeps its elements (i = tid +
+// 1024 u) in registers between the passes: one read and one write of each
+// vector element per step.
 __global__ __launch_bounds__(kLzThreads) void k_lanczos_vec(int n, int step, int last,
                                                             double* __restrict__ w,
                                                             const double* __restrict__ v,
                                                             const double* __restrict__ vprev,
                                                             double* coef, double* out) {
   __shared__ double red[kLzThreads / 64];
+  __shared__ double tri[2 * 32];  // the tridiagonal T_{step+1} for the bound
   const int tid = threadIdx.x;
+  const bool reg = n <= kLzReg * kLzThreads;
   if (step < 0) {
     double s = 0.0;
     for (int i = tid; i < n; i += kLzThreads) s += w[i] * w[i];
@@ -87,45 +118,75 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos_vec(int n, int step, int
     return;
   }
   const double bj = step > 0 ? coef[32 + step] : 0.0;
-  double s = 0.0;
-  for (int i = tid; i < n; i += kLzThreads) {
-    const double x = w[i] - (step > 0 ? bj * vprev[i] : 0.0);
-    w[i] = x;
-    s += x * v[i];
+  double al, b;
+  if (reg) {
+    double x[kLzReg], vv[kLzReg];
+#pragma unroll
+    for (int u = 0; u < kLzReg; ++u) {
+      const int i = tid + kLzThreads * u;
+      const bool in = i < n;
+      x[u] = in ? w[i] : 0.0;
+      vv[u] = in ? v[i] : 0.0;
+      const double p = (in && step > 0) ? vprev[i] : 0.0;
+      x[u] = fma(-bj, p, x[u]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kLzReg; ++u) s = fma(x[u], vv[u], s);
+    al = lz_block_sum(s, red);
+    double s2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < kLzReg; ++u) {
+      x[u] = fma(-al, vv[u], x[u]);
+      s2 = fma(x[u], x[u], s2);
+    }
+    b = sqrt(lz_block_sum(s2, red));
+    // breakdown (an invariant subspace): the next vector is zero, so later
+    // steps add zero rows whose eigenvalue 0 only loosens the bound
+    const double sc = b > 1e-300 ? 1.0 / b : 0.0;
+#pragma unroll
+    for (int u = 0; u < kLzReg; ++u) {
+      const int i = tid + kLzThreads * u;
+      if (i < n) w[i] = x[u] * sc;
+    }
+  } else {
+    double s = 0.0;
+    for (int i = tid; i < n; i += kLzThreads) {
+      const double x = w[i] - (step > 0 ? bj * vprev[i] : 0.0);
+      w[i] = x;
+      s += x * v[i];
+    }
+    al = lz_block_sum(s, red);
+    double s2 = 0.0;
+    for (int i = tid; i < n; i += kLzThreads) {
+      const double x = w[i] - al * v[i];
+      w[i] = x;
+      s2 += x * x;
+    }
+    b = sqrt(lz_block_sum(s2, red));
+    const double sc = b > 1e-300 ? 1.0 / b : 0.0;
+    for (int i = tid; i < n; i += kLzThreads) w[i] *= sc;
   }
-  const double al = lz_block_sum(s, red);
-  double s2 = 0.0;
-  for (int i = tid; i < n; i += kLzThreads) {
-    const double x = w[i] - al * v[i];
-    w[i] = x;
-    s2 += x * x;
-  }
-  const double b = sqrt(lz_block_sum(s2, red));
-  // breakdown (an invariant subspace): the next vector is zero, so later
-  // steps add zero rows whose eigenvalue 0 only loosens the bound
-  const double sc = b > 1e-300 ? 1.0 / b : 0.0;
-  for (int i = tid; i < n; i += kLzThreads) w[i] *= sc;
   if (tid == 0) {
     coef[step] = al;
     coef[32 + step + 1] = b;
-    if (last) {
-      const int k = step + 1;
-      const double* A = coef;
-      const double* B = coef + 32;  // B[i] couples rows i - 1 and i
-      double lo = A[0], hi = A[0];
-      for (int i = 0; i < k; ++i) {
-        const double r = (i > 0 ? fabs(B[i]) : 0.0) + (i + 1 < k ? fabs(B[i + 1]) : 0.0);
-        lo = fmin(lo, A[i] - r);
-        hi = fmax(hi, A[i] + r);
+  }
+  if (last) {
+    // T_{step+1} into LDS: this step's coefficients from registers (every
+    // thread holds them), the earlier ones written by earlier launches
+    const int k = step + 1;
+    if (tid < k) {
+      tri[tid] = tid == step ? al : coef[tid];
+      tri[32 + tid] = tid == 0 ? 0.0 : coef[32 + tid];
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const double th = tridiag_min_wave(tri, tri + 32, k);
+      if (tid == 0) {
+        out[1] = th;
+        out[2] = b;
+        out[0] = th - b;
       }
-      // smallest eigenvalue: the largest x with no eigenvalue below it
-      for (int it = 0; it < 200 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (sturm_below(A, B, k, mid) >= 1) hi = mid; else lo = mid;
-      }
-      out[1] = lo;
-      out[2] = b;
-      out[0] = lo - b;
     }
   }
 }
