@@ -7,8 +7,11 @@
 // gives L L^T = M + dM with |dM| <= gamma_{L+1} |L| |L^T|, hence
 // ||dM||_2 <= gamma_{L+1} tr(M) / (1 - gamma_{L+1}); the factorization here
 // scales by a refined reciprocal square root and divides through rounded
-// reciprocals, a few more roundings per entry, which gamma_{L+8} covers.  The formation of M is bounded the same way from the
-// norms the kernels measure; eta is twice the sum of these terms.
+// reciprocals, a few more roundings per entry, which gamma_{L+8} covers (the
+// bound holds for any order of each entry's inner product, so it covers the
+// substitutions, the FMA updates and the matrix-core updates alike).  The
+// formation of M is bounded the same way from the norms the kernels
+// measure; eta is twice the sum of these terms.
 #include "cert.h"
 #include "common.h"
 
@@ -32,14 +35,15 @@ __device__ inline void tri_index(int b, int& ii, int& jj) {
   jj = b - i * (i + 1) / 2;
 }
 
-// 1 / sqrt(d) for d > 0: the hardware estimate refined by two Newton steps
-// (relative error a few units of roundoff; the margin eta allows for it).
+// 1 / sqrt(d) for d > 0: the hardware estimate (relative error about 2^-24)
+// refined by one third-order step y (1 + e / 2 + 3 e^2 / 8), e = 1 - d y^2
+// (the first terms of (1 - e)^(-1/2)); measured within 1.3 units of
+// roundoff, which the margin eta allows for.
 __device__ inline double rsqrt_nr(double d) {
-  double y = __builtin_amdgcn_rsq(d);
-  const double h = 0.5 * d;
-  y = y * fma(-h * y, y, 1.5);
-  y = y * fma(-h * y, y, 1.5);
-  return y;
+  const double y = __builtin_amdgcn_rsq(d);
+  const double e = fma(-d * y, y, 1.0);
+  const double p = fma(0.375, e, 0.5);
+  return fma(y * e, p, y);
 }
 
 // v of lane `src` (a constant) on every lane
@@ -52,9 +56,9 @@ __device__ inline double bcast_lane(double v, int src) {
 // v of lane N of this lane's sixteen-lane row (DPP row broadcast)
 template <int N>
 __device__ inline double row_bcast(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + N, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + N, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
+  // one 64-bit DPP move (row_newbcast is a DPP64 control); every lane has a
+  // source, so the old value is never kept
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xF, 0xF, true);
 }
 
 // row_bcast with the lane given at run time (a constant once unrolled)
@@ -79,122 +83,153 @@ __device__ inline double row_bcast_n(double v, int n) {
   }
 }
 
-// Right-looking Cholesky of the 32 x 32 diagonal block at (o, o) of the
+// Right-looking Cholesky of the 16 x 16 diagonal block at (o, o) of the
 // 64 x 64 tile held row-major (stride 65) in LDS, by the first wave: lane i
-// < 32 keeps row o + i in registers; at column j the pivot comes from lane j
-// by readlane, every lane forms 1 / sqrt(pivot) itself, writes its l_ij to an
-// LDS column buffer and updates its row with the broadcast l_cj, c > j (the
-// entries right of its diagonal take junk updates that are never read).
-// Returns 0 when a pivot is not positive and finite (the same on every lane).
-__device__ __attribute__((always_inline)) inline int chol32_wave(double* a, double* cb, int o) {
+// < 16 keeps row o + i in registers (the sixteen lanes of one DPP row); at
+// column j the pivot comes from lane j by readlane, every lane forms
+// 1 / sqrt(pivot) itself and its l_ij, and updates its row with l_cj, c > j,
+// received from lane c by a DPP row broadcast (the entries right of its
+// diagonal take junk updates that are never read).  Afterwards lane i writes
+// the block's transposed strict lower triangle (lt[c * 16 + i] = l_ic for
+// i > c, zero elsewhere) and 1 / l_ii (rinv) for the solves below the block.
+// Returns 0 when a pivot is not positive and finite (the same on every
+// lane).
+__device__ __attribute__((always_inline)) inline int chol16_wave(double* a, double* lt,
+                                                                double* rinv, int o) {
+  constexpr int B = 16;
   const int lane = threadIdx.x;
-  const bool act = lane < 32;
-  double r[32];
+  // lanes past the block repeat the rows of lanes 0..15 in their own DPP
+  // rows (their results are neither broadcast nor stored), so every load is
+  // unconditional
+  double r[B];
 #pragma unroll
-  for (int c = 0; c < 32; ++c) r[c] = act ? a[(o + lane) * kLd + o + c] : 0.0;
+  for (int c = 0; c < B; ++c) r[c] = a[(o + (lane & (B - 1))) * kLd + o + c];
   // No branch per column: a failed pivot clears `ok` (the same on every
   // lane) and is replaced by 1 so the remaining arithmetic stays finite.
   // The next pivot is lane j + 1's own update of its diagonal entry,
   // a_{j+1,j+1} - l_{j+1,j}^2 (the same FMA the column update below applies
-  // there), broadcast before the column goes through LDS, so that its
-  // reciprocal square root overlaps the rest of this column's updates.
+  // there), read before the rest of the column's updates so that its
+  // reciprocal square root overlaps them.
   int ok = 1;
   double d = bcast_lane(r[0], 0);
 #pragma unroll
-  for (int j = 0; j < 32; ++j) {
+  for (int j = 0; j < B; ++j) {
     ok &= (d > 0.0 && d < INFINITY) ? 1 : 0;
     d = ok ? d : 1.0;
     const double inv = rsqrt_nr(d);
     const double l = r[j] * inv;
     r[j] = (lane == j) ? d * inv : l;
-    const double dn = (j + 1 < 32) ? bcast_lane(fma(-l, l, r[(j + 1) & 31]), (j + 1) & 31) : 0.0;
-    double* b = cb + (j & 1) * kT;
-    b[lane] = l;
-    double w[32];
+    const double dn = (j + 1 < B) ? bcast_lane(fma(-l, l, r[(j + 1) & (B - 1)]), (j + 1) & (B - 1)) : 0.0;
 #pragma unroll
-    for (int c0 = (j + 1) & ~1; c0 < 32; c0 += 2) {
-      const double2 v = *(const double2*)(b + c0);
-      w[c0] = v.x;
-      w[c0 + 1] = v.y;
-    }
-#pragma unroll
-    for (int c = j + 1; c < 32; ++c) r[c] = fma(-l, w[c], r[c]);
+    for (int c = j + 1; c < B; ++c) r[c] = fma(-l, row_bcast_n(l, c), r[c]);
     d = dn;
   }
-  if (act) {
+  if (lane < B) {
 #pragma unroll
-    for (int c = 0; c < 32; ++c) a[(o + lane) * kLd + o + c] = r[c];
+    for (int c = 0; c < B; ++c) {
+      a[(o + lane) * kLd + o + c] = r[c];
+      lt[c * B + lane] = (lane > c) ? r[c] : 0.0;
+    }
+    rinv[lane] = 1.0 / r[lane];
   }
   return ok;
 }
 
-// Cholesky of the lower triangle of the 64 x 64 tile in LDS, blocked 2 x 2 on
-// 32-column halves: L11 (first wave), L21 = A21 L11^{-T} by column-ordered
-// substitution (eight lanes per row, lane g owning columns 4g .. 4g + 3, the
-// quotient x_c = a_c / l_cc by the rounded reciprocal broadcast to the row's
-// lanes by DPP), A22 -= L21 L21^T, then L22 (first wave).  Every entry is the
+// L_ik = A_ik L_kk^{-T} for the 16-row blocks i > K below the diagonal block
+// K of the tile in LDS: sixteen lanes per row (one DPP row), lane g owning
+// column 16 K + g, each lane 3 - K rows (three register slots, the unused
+// ones repeating the last row and never stored).  At column c the owning
+// lane forms x_c = a_c / l_cc by the rounded reciprocal, the row's lanes
+// receive it by a DPP row broadcast and update their columns with l_gc from
+// lt (zero on and above the diagonal, so every lane applies every update
+// unconditionally): the column-ordered substitution of the standard
+// algorithm.
+__device__ __attribute__((always_inline)) inline void trsm16_tile(double* a, const double* lt,
+                                                                 const double* rinv, int K) {
+  const int nr = 3 - K;
+  const int t = threadIdx.x, g = t & 15, gr = t >> 4;
+  const int col = 16 * K + g;
+  double x[3], w[16];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) x[u] = a[(16 * (K + 1) + gr + 16 * min(u, nr - 1)) * kLd + col];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) w[c] = lt[c * 16 + g];
+  const double rv = rinv[g];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const double v = row_bcast_n(x[u] * rv, c);
+      x[u] = (g == c) ? v : x[u];
+      x[u] = fma(-v, w[c], x[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+    if (u < nr) a[(16 * (K + 1) + gr + 16 * u) * kLd + col] = x[u];
+}
+
+// A_IJ -= L_IK L_JK^T for the 16 x 16 blocks K < J <= I < 4 of the tile in
+// LDS, on the matrix cores (v_mfma_f64_16x16x4f64, four k-steps of the
+// panel's 16 columns): wave w takes the blocks w, w + 4, ...  Operands:
+// A[row][k] = -l(16 I + row, 16 K + k) on lane (row + 16 k'), B[k][col] =
+// l(16 J + col, 16 K + k); D: lane -> column l % 16, rows l / 16 + 4 r.
+// Diagonal blocks are updated whole (their upper halves are never read).
+__device__ __attribute__((always_inline)) inline void update16_tile(double* a, int K) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int nt = 3 - K;  // trailing blocks
+  const int nb = nt * (nt + 1) / 2;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, li = lane & 15, gq = lane >> 4;
+  for (int p = wv; p < nb; p += 4) {
+    // block p of the trailing lower triangle, column by column
+    int J = K + 1, q = p;
+    while (q >= 4 - J) {
+      q -= 4 - J;
+      ++J;
+    }
+    const int I = J + q;
+    d4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = a[(16 * I + gq + 4 * r) * kLd + 16 * J + li];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const double av = -a[(16 * I + li) * kLd + 16 * K + 4 * s4 + gq];
+      const double bv = a[(16 * J + li) * kLd + 16 * K + 4 * s4 + gq];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[(16 * I + gq + 4 * r) * kLd + 16 * J + li] = acc[r];
+  }
+}
+
+// Cholesky of the lower triangle of the 64 x 64 tile in LDS, blocked 4 x 4
+// on 16-column blocks: for K = 0..3 the diagonal block by the first wave,
+// the blocks below it by substitution, then the trailing blocks' update on
+// the matrix cores.  The block loop is kept rolled so that the code a
+// workgroup runs once per panel stays small (instruction fetch, not
+// arithmetic, dominated the fully unrolled form).  Every entry is the
 // standard algorithm's inner product in some order.  Called by every thread
-// of the workgroup; returns false, on every thread, when a pivot is not
-// positive and finite; on success the lower triangle holds the factor.
-__device__ __attribute__((always_inline)) inline bool chol_tile_lds(double* a, double* cb, int* flag) {
-  const int t = threadIdx.x;
-  if (t < 64) {
-    const int ok = chol32_wave(a, cb, 0);
-    if (t == 0) *flag = ok;
-  }
-  __syncthreads();
-  if (!*flag) return false;
-  {
-    // eight lanes per row, two rows per sixteen-lane DPP row
-    const int row = 32 + (t >> 3), g = t & 7, hi8 = t & 8;
-    double x[4], rv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      x[q] = a[row * kLd + 4 * g + q];
-      rv[q] = 1.0 / a[(4 * g + q) * kLd + 4 * g + q];
-    }
-#pragma unroll
-    for (int c = 0; c < 32; ++c) {
-      const int own = c >> 2, qq = c & 3;
-      const double p = x[qq] * rv[qq];  // meaningful on the owning lane
-      const double v0 = row_bcast_n(p, own), v1 = row_bcast_n(p, 8 + own);
-      const double v = hi8 ? v1 : v0;
-      x[qq] = (g == own) ? v : x[qq];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int col = 4 * g + q;
-        const double w = (col > c) ? a[col * kLd + c] : 0.0;
-        x[q] = fma(-v, w, x[q]);
-      }
-    }
-    __syncthreads();  // every row of A21 read before L21 overwrites it
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[row * kLd + 4 * g + q] = x[q];
-  }
-  __syncthreads();
-  {
-    // A22 -= L21 L21^T: thread -> row 32 + t / 8, columns 32 + 4 (t % 8) + q
-    const int i = 32 + (t >> 3), j0 = 32 + 4 * (t & 7);
-    double acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = a[i * kLd + j0 + q];
-#pragma unroll 8
-    for (int c = 0; c < 32; ++c) {
-      const double li = a[i * kLd + c];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] = fma(-li, a[(j0 + q) * kLd + c], acc[q]);
+// of the workgroup; lt and rinv are 272 doubles of LDS scratch.  Returns
+// false, on every thread, when a pivot is not positive and finite; on
+// success the lower triangle holds the factor.
+__device__ __attribute__((always_inline)) inline bool chol_tile_lds(double* a, double* lt,
+                                                                   double* rinv, int* flag) {
+#pragma nounroll
+  for (int K = 0; K < 4; ++K) {
+    if (threadIdx.x < 64) {
+      const int ok = chol16_wave(a, lt, rinv, 16 * K);
+      if (threadIdx.x == 0) *flag = ok;
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) a[i * kLd + j0 + q] = acc[q];
+    if (!*flag) return false;
+    if (K < 3) {
+      trsm16_tile(a, lt, rinv, K);
+      __syncthreads();
+      update16_tile(a, K);
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  if (t < 64) {
-    const int ok = chol32_wave(a, cb, 32);
-    if (t == 0) *flag = ok;
-  }
-  __syncthreads();
-  return *flag != 0;
+  return true;
 }
 
 // tile (row block bi, column block bj) of column-major M <-> row-major LDS
@@ -435,13 +470,13 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int L
                                                    CertState* cs) {
   if (cert_failed(cs)) return;
   __shared__ double a[kT * kLd];
-  __shared__ __align__(16) double cb[2 * kT];
+  __shared__ double lt[16 * 16 + 16];
   __shared__ int flag;
   const long long t0 = wall_clock64();
   load_tile(M, L, k, k, a);
   __syncthreads();
   const long long t1 = wall_clock64();
-  if (!chol_tile_lds(a, cb, &flag)) {
+  if (!chol_tile_lds(a, lt, lt + 256, &flag)) {
     if (threadIdx.x == 0) cs->fail = 1 + k;
     return;
   }
@@ -517,8 +552,8 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ M, int L
                                                    CertState* cs) {
   if (cert_failed(cs)) return;
   __shared__ __align__(16) double sm[2 * kT * kT];
-  double* cb = sm + kT * kLd;  // column buffers of the lookahead factorization (16-byte aligned)
-  int* flag = (int*)(sm + kT * kLd + 2 * kT);
+  int* flag = (int*)(sm + kT * kLd);
+  double* lt = sm + kT * kLd + 8;  // 256 + 16 doubles: L_KK^T and 1 / l_ii
   double* pt = sm;            // pt[q * 64 + r] = L_ik(r, q)
   double* qt = sm + kT * kT;  // qt[q * 64 + c] = L_jk(c, q)
   int ii, jj;
@@ -576,7 +611,7 @@ __global__ __launch_bounds__(256) void k_chol_syrk(double* __restrict__ M, int L
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[(4 * tr + q) * kLd + 4 * tc + b] = acc[q][b];
   __syncthreads();
-  if (!chol_tile_lds(a, cb, flag)) {
+  if (!chol_tile_lds(a, lt, lt + 256, flag)) {
     if (t == 0) cs->fail = 1 + bi;
     return;
   }
