@@ -81,9 +81,9 @@ TRAFFIC = {
         "profile": "profiles/hbm_traffic_n4000_mixed_iid.txt",
     },
     ("n4000_mixed_iid", "cert"): {
-        "bytes": 3.9006e+09,  # per certificate: k_cert_* + 62 k_chol_trsm + 62 k_chol_syrk + W = A V
+        "bytes": 3.8954e+09,  # per certificate: k_cert_* + 62 k_chol_trsm + 62 k_chol_syrk + W = A V
         "files": ['paper_1912_02767_amd/csrc/k_cert.hip', 'paper_1912_02767_amd/csrc/cert.h', 'paper_1912_02767_amd/csrc/k_product.hip', 'paper_1912_02767_amd/csrc/common.h'],
-        "sha256": "5d13c13420e3f8d78b6cf4d5983e9dfd2a22dab1ad61c2644b4fdcc5cfa80fdd",
+        "sha256": "314bdd22a4405aa6a801620be77a8dc4bfbebadf506ff069e59312e24f5b3474",
         "profile": "profiles/hbm_traffic_n4000_mixed_iid.txt",
     },
 }
