@@ -162,7 +162,12 @@ typedef enum {
                                   /* failed certificates); filter products at    */
                                   /* opt.prec while the largest residual is 10x  */
                                   /* above that precision's rounding floor, else */
-                                  /* FP64; the same bound; info.iters = passes   */
+                                  /* FP64; the same bound; info.iters = passes.  */
+                                  /* The 10 Lanczos steps run on a second stream */
+                                  /* the handle creates (non-blocking, default   */
+                                  /* priority) after the input is ingested; the  */
+                                  /* call waits for it before any return, so the */
+                                  /* stream semantics of the call are unchanged  */
 } psdp_method;
 
 typedef struct {
