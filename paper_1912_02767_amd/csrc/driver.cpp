@@ -1676,10 +1676,26 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
       const double ap = std::acosh(xp);
       int d = (int)std::ceil(std::acosh(need) / ap);
       const double spread = std::acosh(xmax) - ap;
-      double rall = 0.0;
+      double rall = 0.0, rg = 0.0;
       for (int i = 0; i < m; ++i) rall = std::max(rall, st.rnorm[i]);
+      for (int i = np; i < m; ++i) rg = std::max(rg, st.rnorm[i]);
       const double R = std::min(1e13, std::max(1e5, 1e6 * (st.theta[0] - b) / std::max(rall, 1e-300)));
       if (spread > 0) d = std::min(d, (int)(std::log(R) / spread));
+      // the non-positive (guard) columns sit in the damped interval, so the
+      // filter leaves their own direction at most 1 while it multiplies their
+      // components along the top eigenvectors, at most r_g / (theta_0 -
+      // theta_g), by T_d(x_max).  Past some level the Cholesky-QR drops the
+      // guards as dependent, and the random columns that replace them cost a
+      // Rayleigh-Ritz pass and spoil the next call's warm start (its damped
+      // interval then ends at their Ritz values, far below zero).  The bound
+      // overstates the components; guards were kept at a bound of 3.5e9 and
+      // dropped at 1.2e12, so it is held to 1e10.
+      if (np > 0 && np < m && rg > 0.0) {
+        const double gapg = st.theta[0] - st.theta[np];
+        const double amax = std::acosh(xmax);
+        if (gapg > 0.0 && amax > 0.0)
+          d = std::min(d, (int)(std::log(2e10 * gapg / rg) / amax));
+      }
       d = std::max(2, std::min(d, dmax));
       // Y0 = X, Y1 = (AX - c X) / e (AX exact from the last Rayleigh-Ritz),
       // Y_{k+1} = 2 (A Y_k - c Y_k) / e - Y_{k-1} through the product epilogue
