@@ -669,11 +669,15 @@ struct Solver {
 };
 
 
-// Lower bound on the smallest eigenvalue of the ingested matrix: `steps`
-// plain Lanczos steps from a seeded random vector (products at precision
-// `prec`), then theta_min(T) - beta_steps (Zhou and Saad's estimator; the
-// Ritz value lies above the spectrum's lower end and the last coupling
-// bounds how far).  Used for the damped interval of the Chebyshev filter.
+// Lower end of the spectrum of the ingested matrix: `steps` plain Lanczos
+// steps from a seeded random vector (products at precision `prec`), then
+// theta_min(T) less twice the residual norm of its Ritz pair and 1 % of its
+// size, but never below theta_min - beta_steps (Zhou and Saad's estimator):
+// the Ritz value lies above the spectrum's lower end and an eigenvalue lies
+// within the residual of it.  Used for the damped interval of the Chebyshev
+// filter, where an end slightly inside the spectrum costs little (the
+// lowest eigenvalues grow by a small factor) and one far outside slows
+// every pass.
 // lanczos_launch queues the steps on the handle's second stream (the
 // ingested copies of A must be complete; only A and the Lanczos region of
 // the workspace are touched, so the first Rayleigh-Ritz step can run on the
@@ -718,7 +722,7 @@ psdp_status lanczos_launch(psdp_handle h, int n, int prec, int steps, uint64_t s
     iv = iw;
     iw = t;
   }
-  HIP_TRY(copy_to_host(h->h_pin_aux, out, 3 * sizeof(double), s));
+  HIP_TRY(copy_to_host(h->h_pin_aux, out, 4 * sizeof(double), s));
   return PSDP_OK;
 }
 
@@ -726,6 +730,9 @@ psdp_status lanczos_finish(psdp_handle h, double* lo, double* theta_min) {
   HIP_TRY(hipStreamSynchronize(h->aux));
   *lo = h->h_pin_aux[0];
   *theta_min = h->h_pin_aux[1];
+  if (h->trace)
+    std::fprintf(stderr, "psdp: lanczos theta_min %.6e beta %.3e residual %.3e lower end %.6e\n",
+                 h->h_pin_aux[1], h->h_pin_aux[2], h->h_pin_aux[3], h->h_pin_aux[0]);
   return std::isfinite(*lo) ? PSDP_OK : PSDP_ERR_NUMERICAL;
 }
 

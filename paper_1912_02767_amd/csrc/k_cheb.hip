@@ -9,8 +9,10 @@
 //    split-K reduction instead);
 //  * k_lanczos_vec: one step of the plain Lanczos recurrence on a single
 //    vector (one workgroup), and after the last step the smallest eigenvalue
-//    of the tridiagonal by Sturm bisection, from which the lower end of the
-//    spectrum is bounded (theta_min - beta_k, the Zhou-Saad estimator).
+//    of the tridiagonal by Sturm multisection and the residual norm of its
+//    Ritz pair, from which the lower end of the spectrum is estimated
+//    (theta_min less twice that residual and 1 %, never below theta_min -
+//    beta_k, the Zhou-Saad estimator).
 #include "common.h"
 
 namespace psdp {
@@ -92,7 +94,8 @@ __device__ inline double tridiag_min_wave(const double* A, const double* B, int 
 }
 
 // coef: alpha[0..31], beta[32..64] (beta[32 + j] = beta_j, beta_0 = 0),
-// out[0] = lower bound, out[1] = theta_min, out[2] = last beta.
+// out[0] = lower end, out[1] = theta_min, out[2] = last beta, out[3] = the
+// residual norm of the Ritz pair for theta_min.
 //   step < 0 : v <- v / ||v||
 //   step j   : w <- w - beta_j vprev; alpha_j = w.v; w <- w - alpha_j v;
 //              beta_{j+1} = ||w||; w <- w / beta_{j+1}  (the next v)
@@ -183,9 +186,39 @@ __global__ __launch_bounds__(kLzThreads) void k_lanczos_vec(int n, int step, int
     if (tid < 64) {
       const double th = tridiag_min_wave(tri, tri + 32, k);
       if (tid == 0) {
+        // residual norm of the Ritz pair for theta_min: beta_k |z_k|, z the
+        // unit eigenvector of T_k (its last component by the three-term
+        // recurrence of T_k's rows from z_1 = 1, rescaled as it grows)
+        const double* A = tri;
+        const double* B = tri + 32;
+        double y0 = 0.0, y1 = 1.0, s2 = 1.0;
+        bool ok = true;
+        for (int i = 0; i + 1 < k; ++i) {
+          const double bn = B[i + 1];
+          if (!(fabs(bn) > 0.0)) {
+            ok = false;
+            break;
+          }
+          const double y2 = ((th - A[i]) * y1 - B[i] * y0) / bn;
+          y0 = y1;
+          y1 = y2;
+          s2 += y2 * y2;
+          if (s2 > 1e200) {
+            y0 *= 1e-100;
+            y1 *= 1e-100;
+            s2 *= 1e-200;
+          }
+        }
+        const double zl = fabs(y1) / sqrt(s2);
+        const double rho = (ok && zl <= 1.0) ? b * zl : b;
         out[1] = th;
         out[2] = b;
-        out[0] = th - b;
+        out[3] = rho;
+        // twice the residual below theta_min (an eigenvalue lies within rho
+        // of it) and 1 % of its size; a lower end slightly inside the
+        // spectrum only lets the filter grow the lowest eigenvalues by a
+        // small factor, far below the wanted ones
+        out[0] = th - fmin(b, 2.0 * rho + 1e-2 * fabs(th));
       }
     }
   }
