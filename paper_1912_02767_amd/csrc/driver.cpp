@@ -1531,13 +1531,9 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   double tol = opt.tol > 0 ? opt.tol : 1e-8 * std::sqrt(fro2) / std::sqrt(2.0 * m0);
   if (tol <= 0) tol = 1e-300;
   // the Chebyshev variant's spectrum bound needs only the ingested A: it
-  // runs on the second stream beside the first Rayleigh-Ritz step
+  // runs on the second stream beside the first Rayleigh-Ritz step (queued
+  // after that step's launches, which are on the critical path)
   AuxJoin aux_join{h};
-  if (opt.method == PSDP_METHOD_CHEBYSHEV) {
-    psdp_status lr = lanczos_launch(h, n, prec0, 10, opt.seed, (h->calls << 8) | 0xFF);
-    if (lr != PSDP_OK) { info->status = lr; return lr; }
-    aux_join.pending = true;
-  }
   // ---- state init
   State& hs = *h->h_state;
   std::memset(&hs, 0, sizeof(State));
@@ -1565,7 +1561,17 @@ extern "C" psdp_status psdp_project(psdp_handle h, int n, const double* X, int l
   // initial Rayleigh-Ritz on span(X0) with an FP64 product (Alg. 3, first RR)
   for (int attempt = 0; attempt < 4; ++attempt) {
     int want = sv.m;
-    rc = sv.iterate(kModeXOnly, 0, want, 0);
+    if (attempt == 0 && opt.method == PSDP_METHOD_CHEBYSHEV) {
+      Solver::Queued q;
+      rc = sv.enqueue(kModeXOnly, 0, want, 0, 0, q);
+      if (rc != PSDP_OK) { info->status = rc; return rc; }
+      rc = lanczos_launch(h, n, prec0, 10, opt.seed, (h->calls << 8) | 0xFF);
+      if (rc != PSDP_OK) { info->status = rc; return rc; }
+      aux_join.pending = true;
+      rc = sv.complete(q);
+    } else {
+      rc = sv.iterate(kModeXOnly, 0, want, 0);
+    }
     if (rc != PSDP_OK) { info->status = rc; return rc; }
     if (sv.m >= std::min(m0, n)) break;
     // rank-deficient start: refill the missing columns with random ones
