@@ -203,7 +203,9 @@ typedef struct {
     double trunc_bound; /* PSDP_METHOD_TOP_R: sqrt(n - r) max(theta_r, 0), else  */
                         /* NaN                                                    */
     double spec_lower;  /* PSDP_METHOD_CHEBYSHEV: the lower end of the damped     */
-                        /* interval (a bound on the smallest eigenvalue), else NaN*/
+                        /* interval (an estimate at or below the smallest         */
+                        /* eigenvalue: the lowest Lanczos Ritz value less twice   */
+                        /* its residual and 2 %, not a proven bound), else NaN    */
     int products;       /* PSDP_METHOD_CHEBYSHEV: products with A (filter,        */
                         /* Rayleigh-Ritz and Lanczos), else 0                     */
 } psdp_info;
